@@ -1,0 +1,185 @@
+"""Seeded synthetic inputs: periodic Voronoi polycrystals with random orientations.
+
+This module only draws inputs.  It holds none of the method's arithmetic (no
+stiffness, energy or acceptance math), so both the HIP library's tests/bench
+and the CPU oracle take their lattices from here.
+
+The paper's microstructures are random polycrystals (Sec. 6 grain-growth runs
+and the Sec. 7 texture runs); no dataset is involved.  Inputs are drawn with
+``numpy.random.default_rng(seed)`` (PCG64):
+
+* ``n_grains`` seed points uniform in [0, K)^3 (float64), then
+* ``n_grains`` x 3 uniforms mapped to Bunge Euler angles with the Haar measure
+  on SO(3): phi1, phi2 ~ U[0, 2 pi), cos(Phi) ~ U[-1, 1];
+* every integer site (x, y, z) takes the index of the nearest seed point under
+  the periodic minimum-image distance; an exact tie goes to the lower index.
+
+Spins are 0-based grain indices, flat index ``x + K*(y + K*z)``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "Microstructure",
+    "voronoi_polycrystal",
+    "haar_euler",
+    "RunConfig",
+    "tiny_config",
+    "full_config",
+    "large_config",
+    "batched_configs",
+    "adjoint_config",
+    "random_spins",
+]
+
+
+@dataclass
+class Microstructure:
+    K: int
+    spins: np.ndarray   # int32, shape (K**3,), x fastest
+    euler: np.ndarray   # float64, shape (Q, 3), Bunge (phi1, Phi, phi2) in radians
+
+    @property
+    def Q(self) -> int:
+        return int(self.euler.shape[0])
+
+
+def haar_euler(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Bunge angles of ``n`` orientations drawn uniformly (Haar) on SO(3)."""
+    u = rng.uniform(size=(n, 3))
+    phi1 = 2.0 * math.pi * u[:, 0]
+    Phi = np.arccos(2.0 * u[:, 1] - 1.0)
+    phi2 = 2.0 * math.pi * u[:, 2]
+    return np.stack([phi1, Phi, phi2], axis=1)
+
+
+def _assign_voronoi(K: int, pts: np.ndarray) -> np.ndarray:
+    from scipy.spatial import cKDTree
+
+    g = np.arange(K, dtype=np.float64)
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    sites = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    n = pts.shape[0]
+    if n == 1:
+        return np.zeros(K ** 3, dtype=np.int32)
+    tree = cKDTree(pts, boxsize=float(K))
+    _, idx = tree.query(sites, k=2)
+    # exact squared minimum-image distances of the two candidates; ties -> lower index
+    best = np.empty(sites.shape[0], dtype=np.int64)
+    d2 = []
+    for j in range(2):
+        d = sites - pts[idx[:, j]]
+        d -= K * np.round(d / K)
+        d2.append(np.einsum("ij,ij->i", d, d))
+    a, b = idx[:, 0], idx[:, 1]
+    take_b = (d2[1] < d2[0]) | ((d2[1] == d2[0]) & (b < a))
+    best[:] = np.where(take_b, b, a)
+    return best.astype(np.int32)
+
+
+def voronoi_polycrystal(K: int, n_grains: int, seed: int,
+                        rng: np.random.Generator | None = None) -> Microstructure:
+    """Periodic Voronoi polycrystal on a K^3 lattice with Haar-random orientations."""
+    if rng is None:
+        rng = np.random.default_rng(seed)
+    pts = rng.uniform(0.0, float(K), size=(n_grains, 3))
+    euler = haar_euler(rng, n_grains)
+    spins = _assign_voronoi(K, pts)
+    return Microstructure(K=K, spins=spins, euler=euler)
+
+
+def random_spins(K: int, Q: int, seed: int) -> np.ndarray:
+    """Independent uniform spins in [0, Q): a maximally disordered test lattice."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, Q, size=K ** 3, dtype=np.int64).astype(np.int32)
+
+
+@dataclass
+class RunConfig:
+    """One workload: lattice, physics and run schedule (GPa for stresses)."""
+    name: str
+    K: int
+    neighbors: int
+    n_grains: int
+    sigma_MPa: np.ndarray          # Voigt xx, yy, zz, yz, xz, xy
+    kT: float
+    zone_h: int
+    zone_steps: int
+    sweeps: int
+    refresh_every: int
+    seed: int = 1                  # microstructure seed
+    philox_seed: int = 1
+    J: float = 1.0
+    C11: float = 246.5
+    C12: float = 147.3
+    C44: float = 124.7
+    proposal: int = 0              # 0 = random neighbour's spin, 1 = uniform other spin
+    refresh_steps: int = 200
+    cold_steps: int = 2000
+    histogram_every: int = 0
+    histogram_axes: tuple = ()
+    extra: dict = field(default_factory=dict)
+
+    def microstructure(self) -> Microstructure:
+        return voronoi_polycrystal(self.K, self.n_grains, self.seed)
+
+    def zero_load(self) -> "RunConfig":
+        import copy
+        c = copy.deepcopy(self)
+        c.name = self.name + "-zero-load"
+        c.sigma_MPa = np.zeros(6)
+        return c
+
+
+def tiny_config() -> RunConfig:
+    """16^3, 6 neighbours (red/black), 8 grains, 100 MPa along z, 3^3 zone x 50 steps."""
+    return RunConfig(name="tiny-16", K=16, neighbors=6, n_grains=8,
+                     sigma_MPa=np.array([0, 0, 100.0, 0, 0, 0]), kT=0.5,
+                     zone_h=1, zone_steps=50, sweeps=10, refresh_every=1)
+
+
+def full_config() -> RunConfig:
+    """64^3, 26 neighbours (8 colours), 500 grains, 200 MPa along z, 5^3 zone x 200 steps."""
+    return RunConfig(name="full-64", K=64, neighbors=26, n_grains=500,
+                     sigma_MPa=np.array([0, 0, 200.0, 0, 0, 0]), kT=0.5,
+                     zone_h=2, zone_steps=200, sweeps=100, refresh_every=10)
+
+
+def large_config() -> RunConfig:
+    """128^3, 26 neighbours, 4000 grains, biaxial 150/150 MPa, 5^3 zone x 200 steps."""
+    return RunConfig(name="large-128", K=128, neighbors=26, n_grains=4000,
+                     sigma_MPa=np.array([150.0, 150.0, 0, 0, 0, 0]), kT=0.7,
+                     zone_h=2, zone_steps=200, sweeps=200, refresh_every=10,
+                     histogram_every=10, histogram_axes=((1.0, 0, 0), (0, 1.0, 0)))
+
+
+def batched_configs(n_replicas: int = 64) -> list[RunConfig]:
+    """Replica ensemble: K in {32,48,64,96}, 8 grains per 16^3, random uniaxial load."""
+    rng = np.random.default_rng(0)
+    out = []
+    for r in range(n_replicas):
+        K = int((32, 48, 64, 96)[rng.integers(0, 4)])
+        s = float(rng.uniform(0.0, 300.0))
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        kT = float(rng.uniform(0.3, 1.0))
+        sig = s * np.outer(n, n)
+        voigt = np.array([sig[0, 0], sig[1, 1], sig[2, 2], sig[1, 2], sig[0, 2], sig[0, 1]])
+        out.append(RunConfig(name=f"replica-{r}", K=K, neighbors=26,
+                             n_grains=8 * (K // 16) ** 3, sigma_MPa=voigt, kT=kT,
+                             zone_h=2, zone_steps=200, sweeps=50, refresh_every=10,
+                             seed=r + 1, philox_seed=r + 1, extra={"axis": n, "load_MPa": s}))
+    return out
+
+
+def adjoint_config():
+    """64^3, 500 grains; six stress components U(-200, 200) MPa; 10 probe grains."""
+    rng = np.random.default_rng(1)
+    micro = voronoi_polycrystal(64, 500, 1, rng=rng)
+    sigma = rng.uniform(-200.0, 200.0, size=6)
+    probe = rng.choice(500, size=10, replace=False)
+    return micro, sigma, probe
