@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Throughput of the HMC hot path on one MI355X: site-trials/s of full sweeps (2 or 8
+colour passes with an elastic zone solve for every real trial flip, the global stress
+refresh every R sweeps and the texture histograms of the workload) on the large
+workload: 128^3 periodic lattice, 26 neighbours / 8 colours, 4000 Voronoi grains with
+Haar-random orientations, biaxial 150/150 MPa, kT = 0.7, 5^3 zone with 200 relaxation
+steps, refresh every 10 sweeps (200 steps), 10-degree texture histograms on x and y every
+10 sweeps.
+
+Prints ONE JSON line on stdout (progress goes to stderr).  A step is one sweep.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "site-trials/sec incl. elastic zone solve (128^3, 5^3 zone) vs oracle; % roofline"
+PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (256 CU x 2.4 GHz x 256 FLOP/clk)
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def zone_flops_per_solve(h: int, nr: int) -> float:
+    """Algorithmic FP32 work of one zone solve: per relaxation step and voxel, the strain
+    from the 8 corners (9 gradient entries as separable sums/differences: 24 + 3 shear
+    sums), the 6x6 stress (36 FMA = 72) and the corner forces (transposed sums: 27);
+    per node the heavy-ball update (3 x 4)."""
+    nv, nn = (2 * h + 1) ** 3, (2 * h + 2) ** 3
+    return nr * (126.0 * nv + 12.0 * nn)
+
+
+REFRESH_BYTES_PER_NODE_STEP = 50.0   # read u, w (24 B) + write u, w (24 B) + spin (2 B)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--proposal", choices=["neighbor", "uniform"], default="neighbor",
+                    help="neighbor: spin of a random neighbour slot (workload default); uniform: any other "
+                         "state, which makes every trial a real flip (zone-solve saturation)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--K", type=int, default=0, help="override the lattice edge (diagnostics only)")
+    return ap.parse_args()
+
+
+def cpu_baseline(lat, p, micro, seconds):
+    """The FP64 oracle, single thread, on a bounded sample of the same workload: random
+    site-trials of one colour pass from the GPU's current state, plus one explicit step of
+    the global solve; combined into site-trials/s of whole sweeps (K^3 trials plus
+    refresh_steps/refresh_every explicit steps per sweep)."""
+    import numpy as np
+
+    import oracle as O
+
+    K = p.K
+    spins = lat.get_spins().cpu().numpy()
+    sig = lat.get_stress().cpu().numpy().astype(np.float64)
+    s = lat.sweep_index()
+    Ct, St, _ = O.tables(micro.euler, p.C11, p.C12, p.C44)
+    prm = O.make_params(K, p.neighbors, micro.Q, proposal=p.proposal, h=p.zone_h, nr=p.zone_steps, elastic=True,
+                        J=p.J, kT=p.kT, lambda_el=p.lambda_el, zone_alpha=p.zone_alpha, zone_beta=p.zone_beta,
+                        seed=p.seed)
+    rng = np.random.default_rng(123)
+    # colour-0 sites: all coordinates even (8 colours) or x+y+z even (2 colours)
+    g = np.arange(K)
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    mask = ((x & 1) == 0) & ((y & 1) == 0) & ((z & 1) == 0) if p.neighbors == 26 else ((x + y + z) & 1) == 0
+    sites = np.nonzero(mask.ravel())[0]
+    rng.shuffle(sites)
+    done = 0
+    t_trials = 0.0
+    batch = 64
+    while t_trials < seconds and done < sites.size:
+        pick = sites[done:done + batch]
+        t0 = time.perf_counter()
+        O.trials(prm, spins, Ct, St, sig, s, pick)
+        t_trials += time.perf_counter() - t0
+        done += pick.size
+        batch = min(4096, batch * 2)
+    u = lat.get_displacement().cpu().numpy().astype(np.float64)
+    E = lat.macro_strain()
+    t0 = time.perf_counter()
+    O.global_solve(K, spins, Ct, St, np.zeros(6), 1, False, p.glob_alpha, p.glob_beta, p.glob_alphaE, u=u, E=E)
+    t_step = time.perf_counter() - t0
+    t_sweep = K ** 3 * (t_trials / done) + (p.refresh_steps / p.refresh_every) * t_step
+    return {
+        "value": K ** 3 / t_sweep,
+        "unit": "site-trials/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{done} random site-trials of colour pass 0 at sweep {s} from the GPU state "
+                   f"({t_trials:.1f} s) + 1 explicit global step at {K}^3 ({t_step:.1f} s), combined as "
+                   f"K^3 trials + {p.refresh_steps}/{p.refresh_every} steps per sweep; serial FP64 C, -O2"),
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in "
+                                   "DESIGN.md but not built", "n_gpus": a.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1009_0457_amd import hmc as H
+    from paper_1009_0457_amd.synth import large_config, voronoi_polycrystal
+
+    cfg = large_config()
+    K = a.K or cfg.K
+    log(f"[bench] building {K}^3 microstructure with {cfg.n_grains} grains")
+    micro = voronoi_polycrystal(K, cfg.n_grains if K == cfg.K else max(8, cfg.n_grains * K ** 3 // cfg.K ** 3),
+                                cfg.seed)
+    p = H.hmc_default_params(K, cfg.neighbors, cfg.zone_h)
+    p.kT = cfg.kT
+    p.zone_steps = cfg.zone_steps
+    p.refresh_every = cfg.refresh_every
+    p.proposal = 0 if a.proposal == "neighbor" else 1
+    p.seed = cfg.philox_seed
+    lat = H.Lattice(p, micro.Q)
+    lat.set_orientations(micro.euler)
+    lat.set_spins(micro.spins)
+    lat.set_load(cfg.sigma_MPa)
+    log(f"[bench] cold refresh ({p.cold_steps} steps)")
+    lat.stress_refresh(-1, True)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup {a.warmup} sweeps")
+    for _ in range(a.warmup):
+        lat.sweep(1)
+    torch.cuda.synchronize()
+    lat.reset_stats()
+    lat.kernel_times()
+    lat.set_profiling(True)
+    axes = [ax for ax in cfg.histogram_axes]
+    hist = []
+    log(f"[bench] timing {a.steps} sweeps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        s = lat.sweep_index()
+        lat.sweep(1)
+        if cfg.histogram_every and (s + 1) % cfg.histogram_every == 0:
+            hist.append([lat.texture_histogram(ax, 10.0, 6).tolist() for ax in axes])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat.set_profiling(False)
+    kt = lat.kernel_times()
+    st = lat.stats()
+    elapsed = t1 - t0
+    trials = a.steps * K ** 3
+    value = trials / elapsed
+    log(f"[bench] {elapsed:.3f} s, {value:.4e} site-trials/s, stats {st}")
+
+    solves = st["zone_solves"]
+    zt = kt["zone"]
+    fps = zone_flops_per_solve(p.zone_h, p.zone_steps)
+    achieved = fps * solves / (zt["total_ms"] * 1e-3) / 1e12 if zt["total_ms"] > 0 else 0.0
+    roof = {"kernel": "zone solve", "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+            "avg_launch_ms": round(zt["total_ms"] / max(1, zt["launches"]), 4),
+            "flop_per_solve": fps, "solves_per_launch": round(solves / max(1, zt["launches"]), 1)}
+    rs = kt["refresh_step"]
+    refresh_roof = None
+    if rs["launches"]:
+        bytes_step = REFRESH_BYTES_PER_NODE_STEP * K ** 3
+        ach = bytes_step * rs["launches"] / (rs["total_ms"] * 1e-3) / 1e9
+        refresh_roof = {"kernel": "global explicit step", "bound": "hbm", "achieved": round(ach, 1),
+                        "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
+                        "avg_launch_ms": round(rs["total_ms"] / rs["launches"], 4),
+                        "note": f"working set {(13 * 4 + 2) * K ** 3 / 2 ** 20:.0f} MiB (cache-resident at 128^3)"}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "site-trials/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": elapsed / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"large-{K}: {K}^3 periodic, 26 neighbours / 8 colours, {micro.Q} Voronoi grains, "
+                               f"biaxial 150/150 MPa, kT {p.kT}, 5^3 zone x {p.zone_steps} steps, refresh every "
+                               f"{p.refresh_every} sweeps x {p.refresh_steps} steps, proposal {a.proposal}",
+                   "K": K, "neighbors": p.neighbors, "zone_h": p.zone_h, "zone_steps": p.zone_steps,
+                   "proposal": a.proposal},
+        "zone_solve_fraction": solves / trials,
+        "zone_solves_per_s": solves / elapsed,
+        "acceptance": st["accepted"] / max(1, st["real_flips"]),
+        "roofline": roof,
+        "refresh_roofline": refresh_roof,
+        "kernel_ms": {k: round(v["total_ms"], 3) for k, v in kt.items()},
+    }
+    if not a.no_cpu_baseline:
+        log("[bench] oracle CPU baseline")
+        out["cpu_baseline"] = cpu_baseline(lat, p, micro, a.cpu_seconds)
+    lat.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

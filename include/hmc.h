@@ -1,0 +1,219 @@
+/*
+ * hmc.h -- C ABI of the MI355X (gfx950) library for the hot path of the hybrid Monte Carlo
+ * (HMC) method of Zhang, Bartel & Lusk, "Parallelized Hybrid Monte Carlo Simulation of
+ * Stress-Induced Texture Evolution" (arXiv:1009.0457):
+ *
+ *   a checkerboard Potts sweep over a periodic K^3 lattice of grain orientations in which
+ *   every trial flip gets a grain-boundary energy change (Sec. 3, Eq. H_1) and an elastic
+ *   energy change from a local constant-traction zone solve (Sec. 3, Eq. H_1 second form,
+ *   Fig. 1), is accepted by Metropolis (Sec. 3, Eq. metrop_1) with counter-based Philox
+ *   variates, and sees the stress of a global explicit elastic relaxation (Sec. 5) that is
+ *   refreshed between sweeps.
+ *
+ * Conventions for every entry point:
+ *   - Lattice sites are indexed i = x + K*(y + K*z); device arrays are dense in that order.
+ *   - Voigt order xx, yy, zz, yz, xz, xy; engineering shear strains; stiffness and stress in
+ *     GPa; elastic energies in GPa * voxel (voxel volume = 1).
+ *   - Stress-field arrays are 6 component planes of K^3 floats (structure of arrays).
+ *   - "dev" pointers are HIP device pointers on the context's device; "host" pointers are
+ *     ordinary host memory.  The library never keeps a caller pointer beyond the call except
+ *     the workspace passed to hmc_create, which it borrows until hmc_destroy.
+ *   - The library allocates no device memory: everything lives in the caller's workspace.
+ *   - Work is enqueued on the context's stream; only calls that return host values
+ *     (hmc_energy, hmc_texture_histogram, hmc_get_stats, hmc_get_macro_strain) synchronise
+ *     that stream.
+ *   - Every call returns an hmc_status; nothing throws or aborts across the ABI.  On error
+ *     hmc_last_error(ctx) holds a message.  A context is not thread-safe; separate contexts
+ *     are independent.
+ */
+#ifndef HMC_H_
+#define HMC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HMC_OK = 0,
+    HMC_EINVAL = 1,    /* bad argument (null pointer, out-of-range value) */
+    HMC_ESHAPE = 2,    /* unsupported lattice shape: K odd, K < 2, K > 1024, K < 2h+2 with
+                          elasticity, Q outside [1, 32767], workspace too small */
+    HMC_ESTATE = 3,    /* call out of order (e.g. sweep before spins/orientations, elastic
+                          sweep before a stress field exists) */
+    HMC_EDEVICE = 4,   /* a HIP call or kernel launch failed */
+    HMC_ENUMERIC = 5   /* non-finite input (Euler angles, load, parameters) or singular C */
+} hmc_status;
+
+typedef struct hmc_ctx_s* hmc_ctx;
+
+/* Run parameters.  hmc_default_params fills every field from (K, neighbors, zone_h). */
+typedef struct {
+    int32_t K;              /* lattice edge; even, 2 <= K <= 1024 */
+    int32_t neighbors;      /* 6 (two-colour red/black) or 26 (eight-colour 2x2x2) */
+    int32_t proposal;       /* 0: spin of a random neighbour slot; 1: uniform other state */
+    int32_t zone_h;         /* zone half-width h in 0..3: the zone has (2h+1)^3 voxels */
+    int32_t zone_steps;     /* heavy-ball steps n_r of each zone solve, >= 0 */
+    int32_t refresh_every;  /* R >= 1: hmc_sweep refreshes the stress before sweep s when
+                               s % R == 0 */
+    int32_t refresh_steps;  /* explicit steps of each such warm refresh */
+    int32_t cold_steps;     /* explicit steps hmc_stress_refresh uses for cold_start with
+                               n_steps < 0 */
+    double J;               /* grain-boundary energy per unlike bond (MC units) */
+    double kT;              /* Monte Carlo temperature T_mc (MC units), > 0 */
+    double C11, C12, C44;   /* cubic stiffness in the crystal frame (GPa) */
+    double lambda_el;       /* MC energy per GPa*voxel (Sec. 4, Eq. elamc); 0 turns the
+                               elastic term and all elastic buffers off */
+    double zone_alpha, zone_beta;   /* zone heavy-ball step and momentum */
+    double glob_alpha, glob_beta;   /* global relaxation step and momentum (displacements) */
+    double glob_alphaE;             /* global relaxation step of the macroscopic strain */
+    uint64_t seed;          /* Philox key: (seed & 0xffffffff, seed >> 32) */
+} hmc_params;
+
+/* Per-trial record written by hmc_colour_pass when a record array is given (24 bytes). */
+typedef struct {
+    int32_t q_new;   /* proposed state */
+    int32_t gb;      /* change in the number of unlike neighbour bonds (energy J*gb) */
+    float dPi;       /* zone energy change in GPa*voxel (0 unless a zone was solved) */
+    uint32_t r1;     /* Metropolis variate: accept iff dE <= 0 or r1 < 2^32 exp(-dE/kT) */
+    int32_t flags;   /* bit 0: q_new differs from the current state; bit 1: accepted;
+                        bit 2: a zone solve produced dPi */
+    int32_t reserved;
+} hmc_trial_record;
+
+/* Counters accumulated since hmc_create (or the last hmc_reset_stats). */
+typedef struct {
+    int64_t site_trials;    /* trials, no-ops included (K^3 per sweep) */
+    int64_t real_flips;     /* trials whose proposal differs from the current state */
+    int64_t zone_solves;    /* zone solves run */
+    int64_t accepted;       /* accepted real flips */
+    int64_t refresh_steps;  /* explicit global steps run */
+} hmc_stats;
+
+/* Fill *p with the defaults for a K^3 lattice: J = 1, kT = 0.5, the workload's nickel
+ * constants C11/C12/C44 = 246.5/147.3/124.7 GPa, lambda_el = 2.6667e6/K (Sec. 4 with the
+ * Table 1 values and l0 = 1 mm), n_r = 50 for h <= 1 and 200 otherwise, R = 10,
+ * refresh 200 / cold 2000 steps, seed 1, and Polyak heavy-ball constants
+ * alpha = 4/(sqrt(L)+sqrt(mu))^2, beta = ((sqrt(L)-sqrt(mu))/(sqrt(L)+sqrt(mu)))^2 with
+ * L = 4 max(C11+2C12, C11-C12, 2C44), mu = (C11-C12)/2 (2 sin(pi/K))^2 for the global grid
+ * and mu = (C11-C12)/2 / (2h+1)^2 for the zone.  Returns HMC_EINVAL for bad arguments. */
+hmc_status hmc_default_params(hmc_params* p, int32_t K, int32_t neighbors, int32_t zone_h);
+
+/* Bytes of device workspace hmc_create needs for these parameters and Q grains
+ * (0 if the parameters are invalid). */
+size_t hmc_workspace_bytes(const hmc_params* p, int32_t Q);
+
+/* Create a context on the current HIP device.  dev_workspace: device buffer of at least
+ * hmc_workspace_bytes(p, Q) bytes, 256-byte aligned, borrowed until hmc_destroy.
+ * stream: the stream all work is enqueued on (0 = null stream).  On failure *out is NULL
+ * and the status says why (HMC_ESHAPE, HMC_EINVAL, HMC_EDEVICE). */
+hmc_status hmc_create(const hmc_params* p, int32_t Q, void* dev_workspace, size_t ws_bytes,
+                      hipStream_t stream, hmc_ctx* out);
+
+void hmc_destroy(hmc_ctx ctx);
+
+/* Message of the last failed call on ctx (empty if none); valid until the next call. */
+const char* hmc_last_error(hmc_ctx ctx);
+
+/* Per-grain orientations: host array of Q Bunge triples (phi1, Phi, phi2) in radians.
+ * The lab-frame stiffness is C' = A A A A C_crystal (Sec. 5, Eq. stiffrot) with the active
+ * rotation A = Rz(phi1) Rx(Phi) Rz(phi2) (crystal -> lab), evaluated in double precision on
+ * the host and uploaded in single precision together with its inverse.  HMC_ENUMERIC for
+ * non-finite angles. */
+hmc_status hmc_set_orientations(hmc_ctx ctx, const double* euler_host);
+
+/* Spins: dev array of K^3 int32 grain indices in [0, Q) (copied; values are checked on
+ * the device and HMC_EINVAL is returned for any out of range).  Resets no other state. */
+hmc_status hmc_set_spins(hmc_ctx ctx, const int32_t* spins_dev);
+hmc_status hmc_get_spins(hmc_ctx ctx, int32_t* spins_dev);
+
+/* Applied macroscopic stress Sigma (Voigt, MPa, host array of 6): the average stress the
+ * global solve holds (periodic lattice, Sec. 5).  All-zero load turns the elastic term off
+ * (decisions then use exact integer thresholds). */
+hmc_status hmc_set_load(hmc_ctx ctx, const double sigma_MPa[6]);
+
+/* Global explicit relaxation (Sec. 5), n_steps steps (cold_start with n_steps < 0 uses
+ * p.cold_steps).  cold_start = 1: displacements zero and the macroscopic strain set to the
+ * uniform-stress (Reuss) value mean(S_q) Sigma; 0: warm start from the current state with
+ * zero velocities.  Ends by writing the stress field used by the zone solves.
+ * HMC_ESTATE without orientations/spins/load or when lambda_el == 0. */
+hmc_status hmc_stress_refresh(hmc_ctx ctx, int32_t n_steps, int32_t cold_start);
+
+/* n_sweeps Monte Carlo steps (Sec. 3: one step = K^3 trials), starting at the current sweep
+ * index s and advancing it.  Each sweep runs the colour classes in order 0..C-1; trials of
+ * one class see the spins at the start of that class pass (Sec. 6, deferred updates).  With
+ * the elastic term on, a warm refresh of p.refresh_steps precedes sweep s when
+ * s % p.refresh_every == 0.  HMC_ESTATE if spins/orientations are missing or the elastic
+ * term is on and no stress field exists yet. */
+hmc_status hmc_sweep(hmc_ctx ctx, int32_t n_sweeps);
+
+/* One colour pass of the current sweep index (no refresh, index not advanced): for tests
+ * and lock-step comparison.  records_dev: NULL or a dev array of K^3 hmc_trial_record; the
+ * record of every site of this colour is written at its site index (others untouched). */
+hmc_status hmc_colour_pass(hmc_ctx ctx, int32_t colour, hmc_trial_record* records_dev);
+
+/* Number of unlike bonds (each bond once) and the stored elastic energy
+ * 1/2 sum_v eps_v . C_{q_v} eps_v (GPa*voxel) of the current spins and displacement state
+ * (0 when the elastic term has no state).  Synchronises. */
+hmc_status hmc_energy(hmc_ctx ctx, int64_t* unlike_bonds, double* U_el);
+
+/* Volume-weighted histogram of the angle between the unit lab axis and the nearest crystal
+ * <100> direction of each site's grain: bin b = floor(angle / bin_deg), clamped to
+ * nbins - 1.  counts_host: nbins int64.  1 <= nbins <= 64, bin_deg > 0.  Synchronises. */
+hmc_status hmc_texture_histogram(hmc_ctx ctx, const double axis[3], double bin_deg,
+                                 int32_t nbins, int64_t* counts_host);
+
+/* Stress field of the last refresh (dev, 6 x K^3 float) out / in.  hmc_set_stress injects
+ * a field (tests) and marks the stress as present. */
+hmc_status hmc_get_stress(hmc_ctx ctx, float* dev_out);
+hmc_status hmc_set_stress(hmc_ctx ctx, const float* dev_in);
+
+/* Displacement fluctuation (dev, 3 x K^3 float planes) and macroscopic strain (host, 6
+ * doubles) of the global solve; set_state also zeroes the velocities (tests, resume). */
+hmc_status hmc_get_displacement(hmc_ctx ctx, float* dev_out);
+hmc_status hmc_get_macro_strain(hmc_ctx ctx, double E_host[6]);
+hmc_status hmc_set_elastic_state(hmc_ctx ctx, const float* u_dev, const double E_host[6]);
+
+/* Sweep index s used for the Philox counter (resume). */
+hmc_status hmc_set_sweep_index(hmc_ctx ctx, int64_t s);
+hmc_status hmc_get_sweep_index(hmc_ctx ctx, int64_t* s);
+
+hmc_status hmc_get_stats(hmc_ctx ctx, hmc_stats* out);
+hmc_status hmc_reset_stats(hmc_ctx ctx);
+
+/* Kernel timing.  While profiling is enabled the library records a pair of HIP events on
+ * the context's stream around every launch of each kernel class below; hmc_get_kernel_times
+ * synchronises, resolves the pairs recorded since the last call (or since enabling) into
+ * launch counts and summed durations, and clears them.  Costs two event records per launch. */
+typedef struct {
+    int64_t launches;
+    double total_ms;
+} hmc_kernel_time;
+
+typedef struct {
+    hmc_kernel_time potts;          /* colour pass: draws, proposals, bond counts */
+    hmc_kernel_time zone;           /* zone solves of one colour pass */
+    hmc_kernel_time apply;          /* deferred writes of accepted elastic flips */
+    hmc_kernel_time refresh_step;   /* one explicit step of the global solve (node part) */
+    hmc_kernel_time refresh_other;  /* strain update, start, final stress field */
+} hmc_kernel_times;
+
+hmc_status hmc_set_profiling(hmc_ctx ctx, int32_t enable);
+hmc_status hmc_get_kernel_times(hmc_ctx ctx, hmc_kernel_times* out);
+
+/* Host-only helper (no device use): lab-frame Voigt stiffness and compliance (Q x 36
+ * doubles each, row-major 6x6) exactly as hmc_set_orientations computes them before the
+ * single-precision upload.  The compliance is built from the closed-form cubic compliance
+ * and the strain transformation, not by inverting C. */
+hmc_status hmc_grain_tables(const double* euler_host, int32_t Q, double C11, double C12,
+                            double C44, double* C_out, double* S_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMC_H_ */

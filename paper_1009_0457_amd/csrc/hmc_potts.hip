@@ -1,0 +1,299 @@
+// hmc_potts.hip -- colour-pass kernels of the Potts sweep (Sec. 3 Eqs. H_1 and metrop_1,
+// Sec. 6 checkerboard with deferred updates) and small utility kernels.
+//
+// One thread per site of the active colour class.  Each thread draws its two Philox
+// words, forms the trial state, counts the change of unlike neighbour bonds and either
+// decides at once (elastic term off: exact integer threshold table) or appends the real
+// flip to a compacted list for the zone-solve kernel (elastic term on).  Because no two
+// sites of one class are neighbours, the decide-at-once path may write spins in place:
+// every read of the pass touches other classes only.
+#include "hmc_internal.h"
+
+namespace hmc {
+
+// ------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds; in each, the first and
+// third words are multiplied by fixed odd constants, the high halves are mixed with the
+// other two words and the key, and the key is advanced by the golden-ratio Weyl steps.
+// ------------------------------------------------------------------------------------
+struct Philox4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                 uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a = 0xD2511F53u * c0;
+        const uint32_t ah = __umulhi(0xD2511F53u, c0);
+        const uint32_t b = 0xCD9E8D57u * c2;
+        const uint32_t bh = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = bh ^ c1 ^ k0;
+        const uint32_t n2 = ah ^ c3 ^ k1;
+        c0 = n0;
+        c1 = b;
+        c2 = n2;
+        c3 = a;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Philox4 out;
+    out.v[0] = c0;
+    out.v[1] = c1;
+    out.v[2] = c2;
+    out.v[3] = c3;
+    return out;
+}
+
+__device__ __forceinline__ int wrapi(int a, int K) { return a < 0 ? a + K : (a >= K ? a - K : a); }
+
+struct PassArgs {
+    int16_t* spins;
+    const uint64_t* thr;            // integer thresholds indexed by gb + M
+    TrialEntry* list;
+    uint32_t* list_count;
+    hmc_trial_record* rec;
+    unsigned long long* stats;
+    int K, Kh, colour, Q, proposal;
+    uint32_t sweep, key0, key1;
+    int64_t n_active;
+};
+
+// Site of thread t within colour `colour`.
+template <int M>
+__device__ __forceinline__ void active_site(const PassArgs& a, int64_t t, int& x, int& y, int& z)
+{
+    if (M == 26) {
+        const int i = (int)(t % a.Kh);
+        const int j = (int)((t / a.Kh) % a.Kh);
+        const int k = (int)(t / ((int64_t)a.Kh * a.Kh));
+        x = 2 * i + (a.colour & 1);
+        y = 2 * j + ((a.colour >> 1) & 1);
+        z = 2 * k + ((a.colour >> 2) & 1);
+    } else {
+        const int i = (int)(t % a.Kh);
+        y = (int)((t / a.Kh) % a.K);
+        z = (int)(t / ((int64_t)a.Kh * a.K));
+        x = 2 * i + ((y + z + a.colour) & 1);
+    }
+}
+
+// Offset of neighbour slot k.  6: -x,+x,-y,+y,-z,+z.  26: (dz,dy,dx) lexicographic over
+// {-1,0,1}^3 without the centre.
+template <int M>
+__device__ __forceinline__ void slot_offset(int k, int& dx, int& dy, int& dz)
+{
+    if (M == 6) {
+        dx = (k == 0) ? -1 : (k == 1 ? 1 : 0);
+        dy = (k == 2) ? -1 : (k == 3 ? 1 : 0);
+        dz = (k == 4) ? -1 : (k == 5 ? 1 : 0);
+    } else {
+        const int n = k + (k >= 13);
+        dx = n % 3 - 1;
+        dy = (n / 3) % 3 - 1;
+        dz = n / 9 - 1;
+    }
+}
+
+// Wave-aggregated append: returns this lane's slot (valid where pred is true).
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred)
+{
+    const unsigned long long mask = __ballot(pred);
+    if (mask == 0) return 0;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader);
+    const unsigned long long below = (lane == 0) ? 0ull : (mask & ((~0ull) >> (64 - lane)));
+    return base + (uint32_t)__popcll(below);
+}
+
+__device__ __forceinline__ void wave_count(unsigned long long* ctr, bool pred)
+{
+    const unsigned long long mask = __ballot(pred);
+    if (mask != 0 && __lane_id() == __ffsll((long long)mask) - 1)
+        atomicAdd(ctr, (unsigned long long)__popcll(mask));
+}
+
+template <int M, bool ELASTIC>
+__global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool real = false, accepted = false;
+    uint32_t site = 0, r1 = 0;
+    int q_new = 0, gb = 0;
+    if (t < a.n_active) {
+        int x, y, z;
+        active_site<M>(a, t, x, y, z);
+        const int K = a.K;
+        site = (uint32_t)(x + K * (y + K * z));
+        const Philox4 r = philox4x32_10(site, a.sweep, 0u, 0u, a.key0, a.key1);
+        r1 = r.v[1];
+        const int q_old = a.spins[site];
+        if (a.proposal == 0) {
+            const int k = (int)__umulhi(r.v[0], (uint32_t)M);
+            int dx, dy, dz;
+            slot_offset<M>(k, dx, dy, dz);
+            q_new = a.spins[wrapi(x + dx, K) + K * (wrapi(y + dy, K) + K * wrapi(z + dz, K))];
+        } else {
+            const uint32_t step = __umulhi(r.v[0], (uint32_t)(a.Q - 1));
+            q_new = (int)(((uint32_t)q_old + 1u + step) % (uint32_t)a.Q);
+        }
+        real = (q_new != q_old);
+        if (real) {
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                int dx, dy, dz;
+                slot_offset<M>(k, dx, dy, dz);
+                const int qn = a.spins[wrapi(x + dx, K) + K * (wrapi(y + dy, K) + K * wrapi(z + dz, K))];
+                gb += (qn == q_old) - (qn == q_new);
+            }
+            if (!ELASTIC) accepted = (uint64_t)r1 < a.thr[gb + M];
+        }
+        if (a.rec) {
+            hmc_trial_record rc;
+            rc.q_new = q_new;
+            rc.gb = gb;
+            rc.dPi = 0.0f;
+            rc.r1 = r1;
+            rc.flags = (real ? 1 : 0) | (accepted ? 2 : 0);
+            rc.reserved = 0;
+            a.rec[site] = rc;
+        }
+        // same-colour sites are never neighbours: nothing else in this pass reads `site`
+        if (!ELASTIC && accepted) a.spins[site] = (int16_t)q_new;
+    }
+    // wave-collective tail, reached by every lane of the wave
+    if (ELASTIC) {
+        const uint32_t slot = wave_append(a.list_count, real);
+        if (real) {
+            TrialEntry e;
+            e.site = site;
+            e.q_new = q_new;
+            e.gb = gb;
+            e.r1 = r1;
+            a.list[slot] = e;
+        }
+    } else {
+        wave_count(&a.stats[kStatAccepted], accepted);
+    }
+    wave_count(&a.stats[kStatReal], real);
+}
+
+// Deferred update of an elastic pass: every accepted entry writes its new state.
+__global__ __launch_bounds__(256) void k_apply(int16_t* spins, const TrialEntry* list, const uint8_t* acc,
+                                               const uint32_t* count)
+{
+    const uint32_t n = *count;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x)
+        if (acc[e]) spins[list[e].site] = (int16_t)list[e].q_new;
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_f32(float* p, float v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_convert_spins(const int32_t* in, int16_t* out, int64_t n, int32_t Q, uint32_t* err)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = in[i];
+        if (v < 0 || v >= Q) {
+            atomicOr(err, 1u);
+            out[i] = 0;
+        } else {
+            out[i] = (int16_t)v;
+        }
+    }
+}
+
+__global__ void k_export_spins(const int16_t* in, int32_t* out, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[i];
+}
+
+static unsigned grid_for(int64_t n, int block, unsigned cap = 65535u * 8u)
+{
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > (int64_t)cap) g = cap;
+    return (unsigned)g;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_spins(const int32_t* in, int16_t* out, int64_t n, int32_t Q, uint32_t* err, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_convert_spins, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, in, out, n, Q, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_spins(const int16_t* in, int32_t* out, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_export_spins, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_potts_pass(hmc_ctx_s* c, int colour, uint32_t sweep, hmc_trial_record* rec)
+{
+    PassArgs a;
+    a.spins = c->d.spins;
+    a.thr = c->d.thr;
+    a.list = c->d.list;
+    a.list_count = c->d.counters + kListCount + colour;
+    a.rec = rec;
+    a.stats = c->d.stats;
+    a.K = c->p.K;
+    a.Kh = c->p.K / 2;
+    a.colour = colour;
+    a.Q = c->Q;
+    a.proposal = c->p.proposal;
+    a.sweep = sweep;
+    a.key0 = (uint32_t)(c->p.seed & 0xffffffffu);
+    a.key1 = (uint32_t)(c->p.seed >> 32);
+    a.n_active = c->n3 / c->colours;
+    const bool el = c->elastic_buffers && c->load_nonzero;
+    const dim3 grid(grid_for(a.n_active, 256, 0x7fffffffu)), block(256);
+    const int tok = prof_begin(c, kProfPotts);
+    if (c->p.neighbors == 26) {
+        if (el) hipLaunchKernelGGL((k_potts_pass<26, true>), grid, block, 0, c->stream, a);
+        else hipLaunchKernelGGL((k_potts_pass<26, false>), grid, block, 0, c->stream, a);
+    } else {
+        if (el) hipLaunchKernelGGL((k_potts_pass<6, true>), grid, block, 0, c->stream, a);
+        else hipLaunchKernelGGL((k_potts_pass<6, false>), grid, block, 0, c->stream, a);
+    }
+    prof_end(c, tok);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_pass(hmc_ctx_s* c, int colour)
+{
+    const unsigned g = grid_for(c->max_list, 256, 2048);
+    const int tok = prof_begin(c, kProfApply);
+    hipLaunchKernelGGL(k_apply, dim3(g), dim3(256), 0, c->stream, c->d.spins, c->d.list, c->d.accept,
+                       c->d.counters + kListCount + colour);
+    prof_end(c, tok);
+    return hipGetLastError();
+}
+
+}  // namespace hmc

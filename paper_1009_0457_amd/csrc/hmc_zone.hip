@@ -1,0 +1,292 @@
+// hmc_zone.hip -- local elastic energy change of each real trial flip (Sec. 3, Eq. H_1
+// second form and Fig. 1): the (2h+1)^3-voxel zone around the trial site keeps the
+// traction on its boundary, so the flip's energy change is the zone's stored energy minus
+// the work of that traction.  With eps_p = S_old sigma_p (the site's strain under its
+// stored stress), dC = C_new - C_old and t = dC eps_p, it equals
+//     1/2 eps_p.dC eps_p + Phi(du),   Phi(du) = t.(B_p du) + 1/2 sum_v (B_v du).C_v (B_v du),
+// minimised over the extra displacement du of the zone's (2h+2)^3 corner nodes (outer
+// boundary free) by n_r explicit heavy-ball steps from rest (no early exit).  B_v is the
+// centre-point strain of voxel v from its 8 corners; C_v the stiffness of the pass's
+// snapshot spin at v, except C_new at the trial site.
+//
+// Layout: one 64-lane wavefront (one work-group) owns one trial at a time.  Lane l owns
+// voxels l, l+64, ... (their 21 stiffness entries stay in registers) and nodes l, l+64, ...
+// (displacement and velocity in registers).  Each step is two phases exchanged through LDS:
+//   A: every owned voxel reads its 8 corner displacements, forms strain and stress, and
+//      publishes the stress;
+//   B: every owned node gathers the forces of its (up to 8) voxels, takes the heavy-ball
+//      step and publishes its new displacement.
+// State and arithmetic are FP32; the final energy is accumulated in FP64.  The decision
+// uses the same predicate as the integer path: accept iff dE <= 0 or r1 < 2^32 exp(-dE/kT).
+#include "hmc_internal.h"
+
+namespace hmc {
+
+struct ZoneArgs {
+    const int16_t* spins;
+    const float* Ctab;
+    const float* Stab;
+    const float* sigma;
+    const TrialEntry* list;
+    const uint32_t* count;
+    uint8_t* acc;
+    hmc_trial_record* rec;
+    unsigned long long* stats;
+    int K;
+    int nr;
+    int64_t n3;
+    float alpha, beta;
+    double J, kT, lambda;
+};
+
+__device__ __forceinline__ void load_sym(const float* __restrict__ t, float c[21])
+{
+#pragma unroll
+    for (int i = 0; i < 21; ++i) c[i] = t[i];
+}
+
+// s = C e for a symmetric Voigt matrix stored as its upper triangle.
+__device__ __forceinline__ void symv(const float c[21], const float e[6], float s[6])
+{
+    s[0] = c[0] * e[0] + c[1] * e[1] + c[2] * e[2] + c[3] * e[3] + c[4] * e[4] + c[5] * e[5];
+    s[1] = c[1] * e[0] + c[6] * e[1] + c[7] * e[2] + c[8] * e[3] + c[9] * e[4] + c[10] * e[5];
+    s[2] = c[2] * e[0] + c[7] * e[1] + c[11] * e[2] + c[12] * e[3] + c[13] * e[4] + c[14] * e[5];
+    s[3] = c[3] * e[0] + c[8] * e[1] + c[12] * e[2] + c[15] * e[3] + c[16] * e[4] + c[17] * e[5];
+    s[4] = c[4] * e[0] + c[9] * e[1] + c[13] * e[2] + c[16] * e[3] + c[18] * e[4] + c[19] * e[5];
+    s[5] = c[5] * e[0] + c[10] * e[1] + c[14] * e[2] + c[17] * e[3] + c[19] * e[4] + c[20] * e[5];
+}
+
+// Centre-point Voigt strain of a voxel from its corner displacements u[c], c = a + 2b + 4d.
+__device__ __forceinline__ void corner_strain(const float4 u[8], float e[6])
+{
+    float gx[3], gy[3], gz[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        auto comp = [&](int c) { return j == 0 ? u[c].x : (j == 1 ? u[c].y : u[c].z); };
+        const float s01 = comp(0) + comp(1), s23 = comp(2) + comp(3), s45 = comp(4) + comp(5),
+                    s67 = comp(6) + comp(7);
+        const float d01 = comp(1) - comp(0), d23 = comp(3) - comp(2), d45 = comp(5) - comp(4),
+                    d67 = comp(7) - comp(6);
+        gx[j] = 0.25f * ((d01 + d23) + (d45 + d67));
+        gy[j] = 0.25f * ((s23 - s01) + (s67 - s45));
+        gz[j] = 0.25f * ((s45 + s67) - (s01 + s23));
+    }
+    e[0] = gx[0];
+    e[1] = gy[1];
+    e[2] = gz[2];
+    e[3] = gz[1] + gy[2];
+    e[4] = gz[0] + gx[2];
+    e[5] = gy[0] + gx[1];
+}
+
+template <int H>
+__global__ __launch_bounds__(64) void k_zone(ZoneArgs a)
+{
+    constexpr int N = 2 * H + 1, NN = 2 * H + 2;
+    constexpr int NV = N * N * N, NNODE = NN * NN * NN;
+    constexpr int VPL = (NV + 63) / 64, NPL = (NNODE + 63) / 64;
+    constexpr int CENTRE = H + N * (H + N * H);
+
+    __shared__ float4 s_du[NNODE];
+    __shared__ float4 s_sig[NV][2];
+
+    const int lane = threadIdx.x;
+    const uint32_t count = *a.count;
+    const int K = a.K;
+
+    for (uint32_t e = blockIdx.x; e < count; e += gridDim.x) {
+        const TrialEntry ent = a.list[e];
+        const int px = (int)(ent.site % (uint32_t)K);
+        const int py = (int)((ent.site / (uint32_t)K) % (uint32_t)K);
+        const int pz = (int)(ent.site / ((uint32_t)K * (uint32_t)K));
+        const int q_old = a.spins[ent.site];
+        const int q_new = ent.q_new;
+
+        // centre: eps_p = S_old sigma_p, t = (C_new - C_old) eps_p
+        float sp[6], eps[6], t[6];
+        {
+            float c[21], s[6];
+#pragma unroll
+            for (int I = 0; I < 6; ++I) sp[I] = a.sigma[(int64_t)I * a.n3 + ent.site];
+            load_sym(a.Stab + (int64_t)q_old * kTab, c);
+            symv(c, sp, eps);
+            load_sym(a.Ctab + (int64_t)q_new * kTab, c);
+            symv(c, eps, t);
+            load_sym(a.Ctab + (int64_t)q_old * kTab, c);
+            symv(c, eps, s);
+#pragma unroll
+            for (int I = 0; I < 6; ++I) t[I] -= s[I];
+        }
+
+        // owned voxels: stiffness in registers
+        float Cv[VPL][21];
+#pragma unroll
+        for (int m = 0; m < VPL; ++m) {
+            const int v = lane + 64 * m;
+            if (v < NV) {
+                const int i = v % N, j = (v / N) % N, k = v / (N * N);
+                int g;
+                if (v == CENTRE) {
+                    g = q_new;
+                } else {
+                    int gx = px + i - H, gy = py + j - H, gz = pz + k - H;
+                    gx = (gx % K + K) % K;
+                    gy = (gy % K + K) % K;
+                    gz = (gz % K + K) % K;
+                    g = a.spins[gx + K * (gy + K * gz)];
+                }
+                load_sym(a.Ctab + (int64_t)g * kTab, Cv[m]);
+            }
+        }
+
+        // owned nodes: displacement and velocity from rest
+        float du[NPL][3], w[NPL][3];
+#pragma unroll
+        for (int m = 0; m < NPL; ++m) {
+            du[m][0] = du[m][1] = du[m][2] = 0.f;
+            w[m][0] = w[m][1] = w[m][2] = 0.f;
+            const int n = lane + 64 * m;
+            if (n < NNODE) s_du[n] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        __syncthreads();
+
+        for (int step = 0; step < a.nr; ++step) {
+            // phase A: voxel stresses
+#pragma unroll
+            for (int m = 0; m < VPL; ++m) {
+                const int v = lane + 64 * m;
+                if (v < NV) {
+                    const int i = v % N, j = (v / N) % N, k = v / (N * N);
+                    const int n0 = i + NN * (j + NN * k);
+                    float4 u[8];
+#pragma unroll
+                    for (int c = 0; c < 8; ++c)
+                        u[c] = s_du[n0 + (c & 1) + NN * (((c >> 1) & 1) + NN * (c >> 2))];
+                    float ev[6], sv[6];
+                    corner_strain(u, ev);
+                    symv(Cv[m], ev, sv);
+                    if (v == CENTRE) {
+#pragma unroll
+                        for (int I = 0; I < 6; ++I) sv[I] += t[I];
+                    }
+                    s_sig[v][0] = make_float4(sv[0], sv[1], sv[2], sv[3]);
+                    s_sig[v][1] = make_float4(sv[4], sv[5], 0.f, 0.f);
+                }
+            }
+            __syncthreads();
+            // phase B: node forces and heavy-ball step
+#pragma unroll
+            for (int m = 0; m < NPL; ++m) {
+                const int n = lane + 64 * m;
+                if (n < NNODE) {
+                    const int na = n % NN, nb = (n / NN) % NN, nc = n / (NN * NN);
+                    float fx = 0.f, fy = 0.f, fz = 0.f;
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const int ca = c & 1, cb = (c >> 1) & 1, cc = c >> 2;
+                        const int vi = na - ca, vj = nb - cb, vk = nc - cc;
+                        if (vi >= 0 && vi < N && vj >= 0 && vj < N && vk >= 0 && vk < N) {
+                            const int v = vi + N * (vj + N * vk);
+                            const float4 s0 = s_sig[v][0], s1 = s_sig[v][1];
+                            const float sx = ca ? 0.25f : -0.25f, sy = cb ? 0.25f : -0.25f,
+                                        sz = cc ? 0.25f : -0.25f;
+                            fx += sx * s0.x + sy * s1.y + sz * s1.x;
+                            fy += sx * s1.y + sy * s0.y + sz * s0.w;
+                            fz += sx * s1.x + sy * s0.w + sz * s0.z;
+                        }
+                    }
+                    w[m][0] = a.beta * w[m][0] - a.alpha * fx;
+                    w[m][1] = a.beta * w[m][1] - a.alpha * fy;
+                    w[m][2] = a.beta * w[m][2] - a.alpha * fz;
+                    du[m][0] += w[m][0];
+                    du[m][1] += w[m][1];
+                    du[m][2] += w[m][2];
+                    s_du[n] = make_float4(du[m][0], du[m][1], du[m][2], 0.f);
+                }
+            }
+            __syncthreads();
+        }
+
+        // energy at the final displacement
+        double part = 0.0;
+#pragma unroll
+        for (int m = 0; m < VPL; ++m) {
+            const int v = lane + 64 * m;
+            if (v < NV) {
+                const int i = v % N, j = (v / N) % N, k = v / (N * N);
+                const int n0 = i + NN * (j + NN * k);
+                float4 u[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) u[c] = s_du[n0 + (c & 1) + NN * (((c >> 1) & 1) + NN * (c >> 2))];
+                float ev[6], sv[6];
+                corner_strain(u, ev);
+                symv(Cv[m], ev, sv);
+                double d = 0.0;
+#pragma unroll
+                for (int I = 0; I < 6; ++I) d += 0.5 * (double)ev[I] * (double)sv[I];
+                if (v == CENTRE) {
+#pragma unroll
+                    for (int I = 0; I < 6; ++I) d += (double)t[I] * (double)ev[I];
+                }
+                part += d;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+
+        if (lane == 0) {
+            double base = 0.0;
+#pragma unroll
+            for (int I = 0; I < 6; ++I) base += 0.5 * (double)eps[I] * (double)t[I];
+            const double dPi = base + part;
+            const double dE = a.J * (double)ent.gb + a.lambda * dPi;
+            const bool accept = (dE <= 0.0) || ((double)ent.r1 < ldexp(exp(-dE / a.kT), 32));
+            a.acc[e] = accept ? 1 : 0;
+            if (a.rec) {
+                a.rec[ent.site].dPi = (float)dPi;
+                a.rec[ent.site].flags = 1 | 4 | (accept ? 2 : 0);
+            }
+            atomicAdd(&a.stats[kStatSolves], 1ull);
+            if (accept) atomicAdd(&a.stats[kStatAccepted], 1ull);
+        }
+        __syncthreads();   // LDS is reused by the next trial
+    }
+}
+
+hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
+{
+    ZoneArgs a;
+    a.spins = c->d.spins;
+    a.Ctab = c->d.Ctab;
+    a.Stab = c->d.Stab;
+    a.sigma = c->d.sigma;
+    a.list = c->d.list;
+    a.count = c->d.counters + kListCount + colour;
+    a.acc = c->d.accept;
+    a.rec = rec;
+    a.stats = c->d.stats;
+    a.K = c->p.K;
+    a.nr = c->p.zone_steps;
+    a.n3 = c->n3;
+    a.alpha = (float)c->p.zone_alpha;
+    a.beta = (float)c->p.zone_beta;
+    a.J = c->p.J;
+    a.kT = c->p.kT;
+    a.lambda = c->p.lambda_el;
+    int64_t g = c->max_list;
+    if (g > 256 * 40) g = 256 * 40;
+    if (g < 1) g = 1;
+    const dim3 grid((unsigned)g), block(64);
+    const int tok = prof_begin(c, kProfZone);
+    switch (c->p.zone_h) {
+        case 0: hipLaunchKernelGGL(k_zone<0>, grid, block, 0, c->stream, a); break;
+        case 1: hipLaunchKernelGGL(k_zone<1>, grid, block, 0, c->stream, a); break;
+        case 2: hipLaunchKernelGGL(k_zone<2>, grid, block, 0, c->stream, a); break;
+        case 3: hipLaunchKernelGGL(k_zone<3>, grid, block, 0, c->stream, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    prof_end(c, tok);
+    return hipGetLastError();
+}
+
+}  // namespace hmc

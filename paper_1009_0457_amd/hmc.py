@@ -1,0 +1,383 @@
+"""Thin Python binding of the C ABI in include/hmc.h (argument marshalling only).
+
+Every ``hmc_*`` function here calls the function of the same name in ``libhmc.so``;
+device arrays are torch tensors on the HIP device (PyTorch supplies device memory and
+streams, nothing else).  ``Lattice`` is a small convenience owner of one context and its
+workspace.  There is no fallback: without the built HIP library or a GPU every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhmc.so")
+
+HMC_OK, HMC_EINVAL, HMC_ESHAPE, HMC_ESTATE, HMC_EDEVICE, HMC_ENUMERIC = range(6)
+_STATUS = {0: "HMC_OK", 1: "HMC_EINVAL", 2: "HMC_ESHAPE", 3: "HMC_ESTATE", 4: "HMC_EDEVICE", 5: "HMC_ENUMERIC"}
+
+
+class HmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class hmc_params(C.Structure):
+    _fields_ = [("K", C.c_int32), ("neighbors", C.c_int32), ("proposal", C.c_int32), ("zone_h", C.c_int32),
+                ("zone_steps", C.c_int32), ("refresh_every", C.c_int32), ("refresh_steps", C.c_int32),
+                ("cold_steps", C.c_int32),
+                ("J", C.c_double), ("kT", C.c_double), ("C11", C.c_double), ("C12", C.c_double),
+                ("C44", C.c_double), ("lambda_el", C.c_double), ("zone_alpha", C.c_double),
+                ("zone_beta", C.c_double), ("glob_alpha", C.c_double), ("glob_beta", C.c_double),
+                ("glob_alphaE", C.c_double), ("seed", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class hmc_kernel_time(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
+class hmc_kernel_times(C.Structure):
+    _fields_ = [("potts", hmc_kernel_time), ("zone", hmc_kernel_time), ("apply", hmc_kernel_time),
+                ("refresh_step", hmc_kernel_time), ("refresh_other", hmc_kernel_time)]
+
+
+class hmc_stats(C.Structure):
+    _fields_ = [("site_trials", C.c_int64), ("real_flips", C.c_int64), ("zone_solves", C.c_int64),
+                ("accepted", C.c_int64), ("refresh_steps", C.c_int64)]
+
+
+# numpy view of hmc_trial_record (24 bytes)
+record_dtype = np.dtype([("q_new", np.int32), ("gb", np.int32), ("dPi", np.float32), ("r1", np.uint32),
+                         ("flags", np.int32), ("reserved", np.int32)])
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point, in header order
+_SIGS = [
+    ("hmc_default_params", C.c_int, [C.POINTER(hmc_params), C.c_int32, C.c_int32, C.c_int32]),
+    ("hmc_workspace_bytes", C.c_size_t, [C.POINTER(hmc_params), C.c_int32]),
+    ("hmc_create", C.c_int, [C.POINTER(hmc_params), C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
+                             C.POINTER(C.c_void_p)]),
+    ("hmc_destroy", None, [C.c_void_p]),
+    ("hmc_last_error", C.c_char_p, [C.c_void_p]),
+    ("hmc_set_orientations", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("hmc_set_spins", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("hmc_get_spins", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("hmc_set_load", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("hmc_stress_refresh", C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    ("hmc_sweep", C.c_int, [C.c_void_p, C.c_int32]),
+    ("hmc_colour_pass", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    ("hmc_energy", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    ("hmc_texture_histogram", C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p]),
+    ("hmc_get_stress", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("hmc_set_stress", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("hmc_get_displacement", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("hmc_get_macro_strain", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("hmc_set_elastic_state", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("hmc_set_sweep_index", C.c_int, [C.c_void_p, C.c_int64]),
+    ("hmc_get_sweep_index", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    ("hmc_get_stats", C.c_int, [C.c_void_p, C.POINTER(hmc_stats)]),
+    ("hmc_reset_stats", C.c_int, [C.c_void_p]),
+    ("hmc_set_profiling", C.c_int, [C.c_void_p, C.c_int32]),
+    ("hmc_get_kernel_times", C.c_int, [C.c_void_p, C.POINTER(hmc_kernel_times)]),
+    ("hmc_grain_tables", C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_void_p,
+                                   C.c_void_p]),
+]
+
+
+def lib():
+    """Load libhmc.so (built by paper_1009_0457_amd.build); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"HIP library not built: {LIB_PATH} (run paper_1009_0457_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_names():
+    return [n for n, _, _ in _SIGS]
+
+
+def _ptr(t):
+    return C.c_void_p(int(t.data_ptr()))
+
+
+def _check(status, ctx=None):
+    if status != HMC_OK:
+        msg = lib().hmc_last_error(ctx).decode() if ctx else ""
+        raise HmcError(status, msg)
+
+
+# ---- same-name wrappers --------------------------------------------------------------
+def hmc_default_params(K, neighbors, zone_h) -> hmc_params:
+    p = hmc_params()
+    _check(lib().hmc_default_params(C.byref(p), K, neighbors, zone_h))
+    return p
+
+
+def hmc_workspace_bytes(p: hmc_params, Q: int) -> int:
+    return int(lib().hmc_workspace_bytes(C.byref(p), Q))
+
+
+def hmc_create(p: hmc_params, Q: int, workspace, stream_handle: int):
+    ctx = C.c_void_p()
+    _check(lib().hmc_create(C.byref(p), Q, _ptr(workspace), workspace.numel(), C.c_void_p(stream_handle),
+                            C.byref(ctx)))
+    return ctx
+
+
+def hmc_destroy(ctx):
+    lib().hmc_destroy(ctx)
+
+
+def hmc_last_error(ctx) -> str:
+    return lib().hmc_last_error(ctx).decode()
+
+
+def hmc_set_orientations(ctx, euler):
+    e = np.ascontiguousarray(euler, np.float64)
+    _check(lib().hmc_set_orientations(ctx, e.ctypes.data_as(C.c_void_p)), ctx)
+
+
+def hmc_set_spins(ctx, spins_dev):
+    assert spins_dev.dtype.itemsize == 4 and spins_dev.is_contiguous() and spins_dev.is_cuda
+    _check(lib().hmc_set_spins(ctx, _ptr(spins_dev)), ctx)
+
+
+def hmc_get_spins(ctx, out_dev):
+    assert out_dev.is_cuda and out_dev.is_contiguous()
+    _check(lib().hmc_get_spins(ctx, _ptr(out_dev)), ctx)
+
+
+def hmc_set_load(ctx, sigma_MPa):
+    s = np.ascontiguousarray(sigma_MPa, np.float64)
+    assert s.shape == (6,)
+    _check(lib().hmc_set_load(ctx, s.ctypes.data_as(C.c_void_p)), ctx)
+
+
+def hmc_stress_refresh(ctx, n_steps, cold_start):
+    _check(lib().hmc_stress_refresh(ctx, int(n_steps), int(cold_start)), ctx)
+
+
+def hmc_sweep(ctx, n):
+    _check(lib().hmc_sweep(ctx, int(n)), ctx)
+
+
+def hmc_colour_pass(ctx, colour, records_dev=None):
+    _check(lib().hmc_colour_pass(ctx, int(colour), None if records_dev is None else _ptr(records_dev)), ctx)
+
+
+def hmc_energy(ctx):
+    n = C.c_int64()
+    u = C.c_double()
+    _check(lib().hmc_energy(ctx, C.byref(n), C.byref(u)), ctx)
+    return int(n.value), float(u.value)
+
+
+def hmc_texture_histogram(ctx, axis, bin_deg=10.0, nbins=6):
+    a = np.ascontiguousarray(axis, np.float64)
+    out = np.zeros(nbins, np.int64)
+    _check(lib().hmc_texture_histogram(ctx, a.ctypes.data_as(C.c_void_p), float(bin_deg), int(nbins),
+                                       out.ctypes.data_as(C.c_void_p)), ctx)
+    return out
+
+
+def hmc_get_stress(ctx, out_dev):
+    _check(lib().hmc_get_stress(ctx, _ptr(out_dev)), ctx)
+
+
+def hmc_set_stress(ctx, in_dev):
+    _check(lib().hmc_set_stress(ctx, _ptr(in_dev)), ctx)
+
+
+def hmc_get_displacement(ctx, out_dev):
+    _check(lib().hmc_get_displacement(ctx, _ptr(out_dev)), ctx)
+
+
+def hmc_get_macro_strain(ctx):
+    E = np.zeros(6)
+    _check(lib().hmc_get_macro_strain(ctx, E.ctypes.data_as(C.c_void_p)), ctx)
+    return E
+
+
+def hmc_set_elastic_state(ctx, u_dev, E):
+    e = np.ascontiguousarray(E, np.float64)
+    _check(lib().hmc_set_elastic_state(ctx, _ptr(u_dev), e.ctypes.data_as(C.c_void_p)), ctx)
+
+
+def hmc_set_sweep_index(ctx, s):
+    _check(lib().hmc_set_sweep_index(ctx, int(s)), ctx)
+
+
+def hmc_get_sweep_index(ctx):
+    s = C.c_int64()
+    _check(lib().hmc_get_sweep_index(ctx, C.byref(s)), ctx)
+    return int(s.value)
+
+
+def hmc_get_stats(ctx) -> dict:
+    st = hmc_stats()
+    _check(lib().hmc_get_stats(ctx, C.byref(st)), ctx)
+    return {k: int(getattr(st, k)) for k, _ in st._fields_}
+
+
+def hmc_reset_stats(ctx):
+    _check(lib().hmc_reset_stats(ctx), ctx)
+
+
+def hmc_set_profiling(ctx, enable):
+    _check(lib().hmc_set_profiling(ctx, int(bool(enable))), ctx)
+
+
+def hmc_get_kernel_times(ctx) -> dict:
+    kt = hmc_kernel_times()
+    _check(lib().hmc_get_kernel_times(ctx, C.byref(kt)), ctx)
+    return {k: {"launches": int(getattr(kt, k).launches), "total_ms": float(getattr(kt, k).total_ms)}
+            for k, _ in kt._fields_}
+
+
+def hmc_grain_tables(euler, C11, C12, C44):
+    e = np.ascontiguousarray(euler, np.float64)
+    Q = e.shape[0]
+    Cl = np.zeros((Q, 6, 6))
+    Sl = np.zeros((Q, 6, 6))
+    _check(lib().hmc_grain_tables(e.ctypes.data_as(C.c_void_p), Q, C11, C12, C44,
+                                  Cl.ctypes.data_as(C.c_void_p), Sl.ctypes.data_as(C.c_void_p)))
+    return Cl, Sl
+
+
+# ---- convenience owner ------------------------------------------------------------------
+class Lattice:
+    """One context plus its torch-allocated workspace on ``device``.
+
+    ``params`` may be an hmc_params or a dict of overrides on the defaults of
+    (K, neighbors, zone_h)."""
+
+    def __init__(self, params, Q, device="cuda:0", stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HMC library needs a HIP device; none is visible")
+        self.torch = torch
+        self.device = torch.device(device)
+        if isinstance(params, dict):
+            d = dict(params)
+            p = hmc_default_params(d.pop("K"), d.pop("neighbors"), d.pop("zone_h"))
+            for k, v in d.items():
+                setattr(p, k, v)
+            params = p
+        self.params = params
+        self.Q = int(Q)
+        self.K = params.K
+        self.n3 = params.K ** 3
+        nbytes = hmc_workspace_bytes(params, self.Q)
+        if nbytes == 0:
+            raise HmcError(HMC_EINVAL, "invalid parameters")
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.ctx = hmc_create(params, self.Q, self.workspace, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            hmc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # thin pass-throughs
+    def set_orientations(self, euler):
+        hmc_set_orientations(self.ctx, euler)
+
+    def set_spins(self, spins):
+        t = self.torch.as_tensor(np.asarray(spins, np.int32) if not hasattr(spins, "is_cuda") else spins)
+        t = t.to(device=self.device, dtype=self.torch.int32).contiguous()
+        hmc_set_spins(self.ctx, t)
+
+    def get_spins(self):
+        out = self.torch.empty(self.n3, dtype=self.torch.int32, device=self.device)
+        hmc_get_spins(self.ctx, out)
+        return out
+
+    def set_load(self, sigma_MPa):
+        hmc_set_load(self.ctx, sigma_MPa)
+
+    def stress_refresh(self, n_steps=-1, cold_start=False):
+        hmc_stress_refresh(self.ctx, n_steps, cold_start)
+
+    def sweep(self, n=1):
+        hmc_sweep(self.ctx, n)
+
+    def colour_pass(self, colour, records=False):
+        rec = None
+        if records:
+            rec = self.torch.zeros(self.n3 * record_dtype.itemsize, dtype=self.torch.uint8, device=self.device)
+        hmc_colour_pass(self.ctx, colour, rec)
+        if rec is None:
+            return None
+        self.stream.synchronize()
+        return rec.cpu().numpy().view(record_dtype)
+
+    def energy(self):
+        return hmc_energy(self.ctx)
+
+    def texture_histogram(self, axis, bin_deg=10.0, nbins=6):
+        return hmc_texture_histogram(self.ctx, axis, bin_deg, nbins)
+
+    def get_stress(self):
+        out = self.torch.empty((6, self.n3), dtype=self.torch.float32, device=self.device)
+        hmc_get_stress(self.ctx, out)
+        return out
+
+    def set_stress(self, sig):
+        t = self.torch.as_tensor(sig).to(device=self.device, dtype=self.torch.float32).contiguous()
+        assert t.numel() == 6 * self.n3
+        hmc_set_stress(self.ctx, t)
+        self._keep = t
+
+    def get_displacement(self):
+        out = self.torch.empty((3, self.n3), dtype=self.torch.float32, device=self.device)
+        hmc_get_displacement(self.ctx, out)
+        return out
+
+    def macro_strain(self):
+        return hmc_get_macro_strain(self.ctx)
+
+    def set_elastic_state(self, u, E):
+        t = self.torch.as_tensor(u).to(device=self.device, dtype=self.torch.float32).contiguous()
+        hmc_set_elastic_state(self.ctx, t, E)
+
+    def set_sweep_index(self, s):
+        hmc_set_sweep_index(self.ctx, s)
+
+    def sweep_index(self):
+        return hmc_get_sweep_index(self.ctx)
+
+    def stats(self):
+        return hmc_get_stats(self.ctx)
+
+    def reset_stats(self):
+        hmc_reset_stats(self.ctx)
+
+    def set_profiling(self, enable=True):
+        hmc_set_profiling(self.ctx, enable)
+
+    def kernel_times(self):
+        return hmc_get_kernel_times(self.ctx)

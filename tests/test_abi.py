@@ -1,0 +1,110 @@
+"""CPU checks of the C-ABI library: it loads, exports every entry point the header
+declares, and its host-only logic (defaults, validation, per-grain tables) is right.
+No call here touches a GPU."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from conftest import ROOT
+
+H = pytest.importorskip("paper_1009_0457_amd.hmc")
+
+
+def _lib_or_skip():
+    if not os.path.exists(H.LIB_PATH):
+        pytest.skip("libhmc.so not built")
+    return H.lib()
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "hmc.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hmc_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    L = _lib_or_skip()
+    names = header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(H.exported_names()) == names
+
+
+def test_default_params_match_the_oracle_reading():
+    _lib_or_skip()
+    for K, M, h in ((16, 6, 1), (64, 26, 2), (128, 26, 2), (8, 26, 0)):
+        p = H.hmc_default_params(K, M, h)
+        za, zb, ga, gb, gE = O.solver_defaults(p.C11, p.C12, p.C44, K, h)
+        assert p.zone_alpha == pytest.approx(za, rel=1e-14)
+        assert p.zone_beta == pytest.approx(zb, rel=1e-14)
+        assert p.glob_alpha == pytest.approx(ga, rel=1e-14)
+        assert p.glob_beta == pytest.approx(gb, rel=1e-14)
+        assert p.glob_alphaE == pytest.approx(gE, rel=1e-14)
+        assert p.lambda_el == pytest.approx(O.calibration(K)[2], rel=1e-12)
+        assert p.zone_steps == (50 if h <= 1 else 200)
+
+
+def test_grain_tables_agree_with_oracle_by_another_route():
+    """Library: 6x6 transformation matrices and the closed-form cubic compliance.
+    Oracle: 4-index tensor rotation and a numerical inverse."""
+    _lib_or_skip()
+    rng = np.random.default_rng(17)
+    e = rng.uniform(0, 2 * math.pi, (64, 3))
+    Cl, Sl = H.hmc_grain_tables(e, 246.5, 147.3, 124.7)
+    Co, So, _ = O.tables(e, 246.5, 147.3, 124.7)
+    assert np.abs(Cl - Co).max() < 1e-11
+    assert np.abs(Sl - So).max() < 1e-15
+    bad = e.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(H.HmcError) as ei:
+        H.hmc_grain_tables(bad, 246.5, 147.3, 124.7)
+    assert ei.value.status == H.HMC_ENUMERIC
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("K", 15, H.HMC_ESHAPE), ("K", 0, H.HMC_ESHAPE), ("K", 2048, H.HMC_ESHAPE),
+    ("neighbors", 8, H.HMC_EINVAL), ("zone_h", 4, H.HMC_EINVAL), ("kT", 0.0, H.HMC_EINVAL),
+    ("kT", float("nan"), H.HMC_ENUMERIC), ("proposal", 2, H.HMC_EINVAL), ("refresh_every", 0, H.HMC_EINVAL),
+    ("C44", -1.0, H.HMC_ENUMERIC),
+])
+def test_create_validates_before_touching_the_device(field, value, status):
+    L = _lib_or_skip()
+    p = H.hmc_default_params(16, 6, 1)
+    setattr(p, field, value)
+    assert L.hmc_workspace_bytes(C.byref(p), 8) == 0
+    ctx = C.c_void_p()
+    buf = (C.c_char * 512)()
+    st = L.hmc_create(C.byref(p), 8, C.cast(buf, C.c_void_p), 512, None, C.byref(ctx))
+    assert st == status and not ctx.value
+
+
+def test_shape_limits():
+    L = _lib_or_skip()
+    p = H.hmc_default_params(4, 26, 2)          # K < 2h+2 with the elastic term on
+    assert L.hmc_workspace_bytes(C.byref(p), 4) == 0
+    p.lambda_el = 0.0                            # fine with elasticity off
+    assert L.hmc_workspace_bytes(C.byref(p), 4) > 0
+    p = H.hmc_default_params(16, 6, 1)
+    assert L.hmc_workspace_bytes(C.byref(p), 32768) == 0
+    assert L.hmc_workspace_bytes(C.byref(p), 32767) > 0
+    ws = L.hmc_workspace_bytes(C.byref(p), 8)
+    ctx = C.c_void_p()
+    buf = (C.c_char * 64)()
+    # too-small workspace is refused before any device call
+    aligned = (C.addressof(buf) + 255) // 256 * 256
+    assert ws > 64
+    st = L.hmc_create(C.byref(p), 8, C.c_void_p(aligned), 16, None, C.byref(ctx))
+    assert st == H.HMC_ESHAPE
+
+
+def test_null_context_calls_are_rejected():
+    L = _lib_or_skip()
+    assert L.hmc_sweep(None, 1) == H.HMC_EINVAL
+    assert L.hmc_set_load(None, None) == H.HMC_EINVAL
+    assert L.hmc_last_error(None) == b"null context"

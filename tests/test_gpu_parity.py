@@ -1,0 +1,335 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+* zero load: spins identical after n sweeps (bit-exact), both proposals, 2 and 8
+  colours, lattices from K=2 to the 128^3 workload;
+* elastic: lock-step replay -- before each colour pass the oracle is fed the GPU's spins
+  and stress field and recomputes every trial; proposals and bond counts must match
+  exactly, zone energies within the FP32 tolerance, decisions identical except trials
+  whose oracle energy lies within that tolerance of the Metropolis threshold;
+* global refresh: stress field, macroscopic strain and stored energy against the oracle;
+* energies and texture histograms exactly (integers) or to FP64 reduction round-off.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1009_0457_amd import hmc as H
+from paper_1009_0457_amd.synth import (full_config, large_config, random_spins, tiny_config,
+                                       voronoi_polycrystal)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # collected on CPU hosts, never run there
+    pytest.skip("no HIP device", allow_module_level=True)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_params(p, Q, elastic, sigma_GPa=(0, 0, 0, 0, 0, 0)):
+    return O.make_params(p.K, p.neighbors, Q, proposal=p.proposal, h=p.zone_h, nr=p.zone_steps,
+                         elastic=elastic, R=p.refresh_every, n_warm=p.refresh_steps, J=p.J, kT=p.kT,
+                         lambda_el=p.lambda_el, zone_alpha=p.zone_alpha, zone_beta=p.zone_beta,
+                         glob_alpha=p.glob_alpha, glob_beta=p.glob_beta, glob_alphaE=p.glob_alphaE,
+                         Sigma=sigma_GPa, seed=p.seed)
+
+
+def make_lattice(K, M, h, micro, **over):
+    p = H.hmc_default_params(K, M, h)
+    for k, v in over.items():
+        setattr(p, k, v)
+    lat = H.Lattice(p, micro.Q)
+    lat.set_orientations(micro.euler)
+    lat.set_spins(micro.spins)
+    return p, lat
+
+
+# --------------------------------------------------------------------------------------
+# zero load: bit-exact spins
+# --------------------------------------------------------------------------------------
+ZERO_CASES = [
+    # K, M, grains (0 = random spins with Q=5), proposal, sweeps, kT
+    (2, 6, 0, 1, 40, 1.0),
+    (2, 26, 0, 1, 40, 3.0),
+    (6, 6, 0, 0, 8, 0.5),
+    (10, 26, 0, 1, 6, 0.9),
+    (16, 6, 8, 0, 10, 0.5),      # tiny workload, zero-load twin
+    (16, 6, 8, 1, 10, 0.5),
+    (18, 26, 12, 0, 5, 0.7),     # edge not a multiple of any tile
+    (64, 26, 500, 0, 6, 0.5),    # full workload, zero-load twin
+    (64, 26, 500, 1, 3, 0.5),
+    (128, 26, 4000, 0, 2, 0.7),  # large workload, zero-load twin
+]
+
+
+@pytest.mark.parametrize("K,M,ng,prop,n,kT", ZERO_CASES)
+def test_zero_load_spins_bit_exact(K, M, ng, prop, n, kT):
+    say(f"[zero-load] K={K} M={M} grains={ng} proposal={prop} sweeps={n} kT={kT}")
+    if ng == 0:
+        Q = 5
+        micro = voronoi_polycrystal(K, Q, 7)
+        micro.spins = random_spins(K, Q, 11 + K)
+    else:
+        micro = voronoi_polycrystal(K, ng, 1)
+    p, lat = make_lattice(K, M, 1 if K < 4 else 1, micro, proposal=prop, kT=kT, lambda_el=0.0, seed=2024 + K)
+    lat.set_sweep_index(3)
+    lat.sweep(n)
+    got = lat.get_spins().cpu().numpy()
+    q = micro.spins.copy()
+    prm = oracle_params(p, micro.Q, False)
+    d = np.zeros(1)
+    O.sweeps(prm, q, np.zeros(36 * micro.Q), np.zeros(36 * micro.Q), d, np.zeros(6), d, 3, n)
+    changed = int(np.count_nonzero(q != micro.spins))
+    say(f"    oracle changed {changed} sites; mismatches {int(np.count_nonzero(got != q))}")
+    assert changed > 0
+    assert np.array_equal(got, q)
+    st = lat.stats()
+    assert st["site_trials"] == n * K ** 3
+    lat.close()
+
+
+def test_zero_load_energy_and_resume():
+    K, M = 32, 26
+    micro = voronoi_polycrystal(K, 40, 5)
+    say("[zero-load resume] K=32")
+    p, a = make_lattice(K, M, 1, micro, lambda_el=0.0, kT=0.6)
+    a.sweep(10)
+    full = a.get_spins().cpu().numpy()
+    p, b = make_lattice(K, M, 1, micro, lambda_el=0.0, kT=0.6)
+    b.sweep(5)
+    mid = b.get_spins()
+    b.close()
+    p, c = make_lattice(K, M, 1, micro, lambda_el=0.0, kT=0.6)
+    c.set_spins(mid)
+    c.set_sweep_index(5)
+    c.sweep(5)
+    assert np.array_equal(c.get_spins().cpu().numpy(), full)
+    bonds, U = a.energy()
+    assert bonds == O.unlike_bonds(K, M, full) and U == 0.0
+    a.close()
+    c.close()
+
+
+# --------------------------------------------------------------------------------------
+# global refresh
+# --------------------------------------------------------------------------------------
+@pytest.mark.parametrize("K,ng,steps", [(8, 5, 300), (16, 8, 500), (20, 30, 200)])
+def test_refresh_matches_oracle(K, ng, steps):
+    say(f"[refresh] K={K} grains={ng} steps={steps}")
+    micro = voronoi_polycrystal(K, ng, 9)
+    p, lat = make_lattice(K, 26, 1, micro)
+    sig = np.array([120.0, -40.0, 80.0, 30.0, -20.0, 10.0])
+    lat.set_load(sig)
+    lat.stress_refresh(steps, True)
+    s_gpu = lat.get_stress().cpu().numpy().astype(np.float64)
+    E_gpu = lat.macro_strain()
+    bonds, U_gpu = lat.energy()
+    Ct, St, _ = O.tables(micro.euler, p.C11, p.C12, p.C44)
+    u, E, s_ora, info = O.global_solve(K, micro.spins, Ct, St, sig * 1e-3, steps, True, p.glob_alpha, p.glob_beta,
+                                       p.glob_alphaE)
+    rel = np.linalg.norm(s_gpu - s_ora) / np.linalg.norm(s_ora)
+    say(f"    rel |dsigma| = {rel:.3e}; |dE|/|E| = {np.linalg.norm(E_gpu - E) / np.linalg.norm(E):.3e}")
+    assert rel <= 1e-4
+    assert np.linalg.norm(E_gpu - E) <= 1e-5 * np.linalg.norm(E)
+    assert U_gpu == pytest.approx(info["U"], rel=1e-5)
+    # warm restart continues the same relaxation
+    lat.stress_refresh(50, False)
+    u2, E2, s2, info2 = O.global_solve(K, micro.spins, Ct, St, sig * 1e-3, 50, False, p.glob_alpha, p.glob_beta,
+                                       p.glob_alphaE, u=u, E=E)
+    s_gpu2 = lat.get_stress().cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(s_gpu2 - s2) / np.linalg.norm(s2) <= 1e-4
+    lat.close()
+
+
+def test_refresh_single_crystal_closed_form():
+    K = 12
+    micro = voronoi_polycrystal(K, 1, 2)
+    micro.euler[0] = (0.0, math.acos(1 / math.sqrt(3)), math.pi / 4)    # [111] along z
+    p, lat = make_lattice(K, 6, 1, micro)
+    lat.set_load([0, 0, 100.0, 0, 0, 0])
+    lat.stress_refresh(20, True)
+    s = lat.get_stress().cpu().numpy()
+    assert np.allclose(s[2], 0.1, rtol=2e-6) and np.abs(s[[0, 1, 3, 4, 5]]).max() < 1e-7
+    _, U = lat.energy()
+    C11, C12, C44 = p.C11, p.C12, p.C44
+    d = (C11 - C12) * (C11 + 2 * C12)
+    S11, S12, S44 = (C11 + C12) / d, -C12 / d, 1 / C44
+    E111 = 1.0 / (S11 - 2 * (S11 - S12 - 0.5 * S44) / 3.0)
+    assert U / K ** 3 == pytest.approx(0.1 ** 2 / (2 * E111), rel=1e-5)
+    lat.close()
+
+
+# --------------------------------------------------------------------------------------
+# elastic lock-step replay
+# --------------------------------------------------------------------------------------
+def zone_tol(sig, St, spins_snapshot, ref_dPi):
+    """FP32 zone solve vs FP64: 1e-5 of max(|dPi|, W_p), W_p = 1/2 sigma_p.S_old sigma_p the
+    stored energy of the trial site (the magnitude every term of dPi is built from)."""
+    W = 0.5 * np.einsum("in,nij,jn->n", sig, St[spins_snapshot], sig)
+    return 1e-5 * np.maximum(np.abs(ref_dPi), W), W
+
+
+def compare_pass(rec, ref, sites, p, tol, what):
+    g, r = rec[sites], ref
+    assert np.array_equal(g["q_new"], r["q_new"]), what
+    assert np.array_equal(g["gb"], r["gb"]), what
+    assert np.array_equal(g["r1"], r["r1"]), what
+    assert np.array_equal(g["flags"] & 1, r["flags"] & 1), what
+    solved = (r["flags"] & 1) != 0
+    err = np.abs(g["dPi"][solved].astype(np.float64) - r["dPi"][solved])
+    assert np.all(err <= tol[solved]), (what, float(err.max()), float((err / tol[solved]).max()))
+    # decisions: identical unless the oracle's energy is within tolerance of the threshold
+    estar = -p.kT * np.log(np.maximum(r["r1"].astype(np.float64), 0.5) * 2.0 ** -32)
+    band = p.lambda_el * tol + 2.0 ** -20 * np.maximum(1.0, np.abs(r["dE"]))
+    near = solved & (np.abs(r["dE"] - estar) <= band)
+    dec_g = (g["flags"] & 2) != 0
+    dec_r = (r["flags"] & 2) != 0
+    bad = (dec_g != dec_r) & ~near
+    assert not np.any(bad), (what, int(bad.sum()))
+    return int(solved.sum()), int(near.sum()), float((err / tol[solved]).max()) if solved.any() else 0.0
+
+
+@pytest.mark.parametrize("cfg", ["tiny", "tiny-uniform"])
+def test_elastic_lockstep_tiny_workload(cfg):
+    c = tiny_config()
+    micro = c.microstructure()
+    over = dict(kT=c.kT, refresh_every=c.refresh_every, proposal=1 if cfg == "tiny-uniform" else 0)
+    p, lat = make_lattice(c.K, c.neighbors, c.zone_h, micro, **over)
+    lat.set_load(c.sigma_MPa)
+    lat.stress_refresh(-1, True)
+    Ct, St, _ = O.tables(micro.euler, p.C11, p.C12, p.C44)
+    prm = oracle_params(p, micro.Q, True)
+    cols = O.colour_of(c.K, c.neighbors)
+    tot = near = 0
+    worst = 0.0
+    for s in range(c.sweeps):
+        lat.set_sweep_index(s)
+        if s % c.refresh_every == 0 and s > 0:
+            lat.stress_refresh(p.refresh_steps, False)
+        sig = lat.get_stress().cpu().numpy().astype(np.float64)
+        for col in range(O.num_colours(c.neighbors)):
+            say(f"[lockstep {cfg}] sweep {s} colour {col}")
+            snap = lat.get_spins().cpu().numpy()
+            rec = lat.colour_pass(col, records=True)
+            q = snap.copy()
+            ref = O.colour_pass(prm, q, Ct, St, sig, s, col, want_records=True)
+            sites = np.nonzero(cols == col)[0]
+            tol, _ = zone_tol(sig[:, sites], St, snap[sites], ref["dPi"][sites])
+            n, k, w = compare_pass(rec, ref[sites], sites, p, tol, f"sweep {s} colour {col}")
+            tot, near, worst = tot + n, near + k, max(worst, w)
+            # the GPU applied its own decisions: they equal the oracle's outside the flagged band
+            got = lat.get_spins().cpu().numpy()
+            diff = np.nonzero(got != q)[0]
+            assert len(diff) <= k
+    say(f"    zone solves compared: {tot}; flagged near-threshold: {near}; worst err/tol {worst:.3f}")
+    assert tot > 100
+    lat.close()
+
+
+@pytest.mark.parametrize("which", ["full", "large"])
+def test_elastic_lockstep_sampled_at_workload_size(which):
+    """Full-size workloads in the benchmark's launch configuration: every trial of a
+    colour pass runs on the GPU; the oracle recomputes a seeded sample of them."""
+    c = full_config() if which == "full" else large_config()
+    micro = c.microstructure()
+    p, lat = make_lattice(c.K, c.neighbors, c.zone_h, micro, kT=c.kT, refresh_every=c.refresh_every)
+    say(f"[lockstep sampled {which}] K={c.K}: cold refresh")
+    lat.set_load(c.sigma_MPa)
+    lat.stress_refresh(-1, True)
+    lat.sweep(2)          # leave the initial Voronoi state
+    Ct, St, _ = O.tables(micro.euler, p.C11, p.C12, p.C44)
+    prm = oracle_params(p, micro.Q, True)
+    sig = lat.get_stress().cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(5)
+    cols = O.colour_of(c.K, c.neighbors)
+    for col in (0, 5):
+        say(f"[lockstep sampled {which}] colour {col}")
+        snap = lat.get_spins().cpu().numpy()
+        rec = lat.colour_pass(col, records=True)
+        sites = np.nonzero(cols == col)[0]
+        real = sites[(rec["flags"][sites] & 1) != 0]
+        pick = np.sort(rng.choice(real, size=min(60, real.size), replace=False))
+        ref = O.trials(prm, snap, Ct, St, sig, lat.sweep_index(), pick)
+        tol, _ = zone_tol(sig[:, pick], St, snap[pick], ref["dPi"])
+        n, k, w = compare_pass(rec, ref, pick, p, tol, f"{which} colour {col}")
+        say(f"    sampled {n} solves, flagged {k}, worst err/tol {w:.3f}; real flips in pass {real.size}")
+    lat.close()
+
+
+def test_elastic_sweeps_are_deterministic():
+    c = tiny_config()
+    micro = c.microstructure()
+    outs = []
+    for _ in range(2):
+        p, lat = make_lattice(c.K, c.neighbors, c.zone_h, micro, kT=c.kT, refresh_every=1)
+        lat.set_load(c.sigma_MPa)
+        lat.stress_refresh(-1, True)
+        lat.sweep(4)
+        outs.append((lat.get_spins().cpu().numpy(), lat.get_stress().cpu().numpy(), lat.stats()))
+        lat.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
+
+
+# --------------------------------------------------------------------------------------
+# energies and texture
+# --------------------------------------------------------------------------------------
+def test_energy_and_texture_match_oracle():
+    K = 24
+    micro = voronoi_polycrystal(K, 60, 4)
+    p, lat = make_lattice(K, 26, 2, micro, kT=0.6)
+    lat.set_load([150.0, 150.0, 0, 0, 0, 0])
+    lat.stress_refresh(300, True)
+    lat.sweep(3)
+    spins = lat.get_spins().cpu().numpy()
+    u = lat.get_displacement().cpu().numpy().astype(np.float64)
+    E = lat.macro_strain()
+    bonds, U = lat.energy()
+    Ct, St, At = O.tables(micro.euler, p.C11, p.C12, p.C44)
+    assert bonds == O.unlike_bonds(K, 26, spins)
+    assert U == pytest.approx(O.elastic_energy(K, spins, Ct, u, E), rel=1e-5)
+    for axis in ([1, 0, 0], [0, 1, 0], [0.3, -0.2, 0.9]):
+        for bins, width in ((6, 10.0), (11, 5.0), (1, 90.0)):
+            got = lat.texture_histogram(axis, width, bins)
+            ref = O.texture_counts(K, spins, At, axis, width, bins)
+            assert np.array_equal(got, ref)
+            assert got.sum() == K ** 3
+    lat.close()
+
+
+def test_error_paths():
+    K = 8
+    micro = voronoi_polycrystal(K, 4, 1)
+    p = H.hmc_default_params(K, 26, 1)
+    lat = H.Lattice(p, micro.Q)
+    with pytest.raises(H.HmcError) as e:
+        lat.sweep(1)
+    assert e.value.status == H.HMC_ESTATE
+    lat.set_orientations(micro.euler)
+    bad = micro.spins.copy()
+    bad[5] = micro.Q
+    with pytest.raises(H.HmcError) as e:
+        lat.set_spins(bad)
+    assert e.value.status == H.HMC_EINVAL
+    lat.set_spins(micro.spins)
+    lat.set_load([0, 0, 50.0, 0, 0, 0])
+    with pytest.raises(H.HmcError) as e:
+        lat.sweep(1)                     # elastic term on, no stress field yet
+    assert e.value.status == H.HMC_ESTATE
+    with pytest.raises(H.HmcError) as e:
+        lat.set_load([0, 0, float("inf"), 0, 0, 0])
+    assert e.value.status == H.HMC_ENUMERIC
+    with pytest.raises(H.HmcError) as e:
+        lat.texture_histogram([0, 0, 0])
+    assert e.value.status == H.HMC_EINVAL
+    with pytest.raises(H.HmcError) as e:
+        lat.colour_pass(8)
+    assert e.value.status == H.HMC_EINVAL
+    lat.close()
