@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--K", type=int, default=0, help="override the lattice edge (diagnostics only)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -120,6 +122,14 @@ def main():
     from paper_1009_0457_amd import hmc as H
     from paper_1009_0457_amd.synth import large_config, voronoi_polycrystal
 
+    if a.copy_probe_mib:
+        src = torch.ones(a.copy_probe_mib * 2 ** 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {a.copy_probe_mib} MiB read + {a.copy_probe_mib} MiB written")
+        del src, dst
     cfg = large_config()
     K = a.K or cfg.K
     log(f"[bench] building {K}^3 microstructure with {cfg.n_grains} grains")

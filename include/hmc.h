@@ -63,6 +63,9 @@ typedef struct {
     int32_t refresh_steps;  /* explicit steps of each such warm refresh */
     int32_t cold_steps;     /* explicit steps hmc_stress_refresh uses for cold_start with
                                n_steps < 0 */
+    int32_t zone_variant;   /* zone-solve kernel: 0 automatic, 1 one wavefront per trial,
+                               2 node columns across a 256-lane work-group (h <= 2) */
+    int32_t reserved0;      /* must be 0 */
     double J;               /* grain-boundary energy per unlike bond (MC units) */
     double kT;              /* Monte Carlo temperature T_mc (MC units), > 0 */
     double C11, C12, C44;   /* cubic stiffness in the crystal frame (GPa) */
@@ -205,12 +208,85 @@ typedef struct {
 hmc_status hmc_set_profiling(hmc_ctx ctx, int32_t enable);
 hmc_status hmc_get_kernel_times(hmc_ctx ctx, hmc_kernel_times* out);
 
+/* Capture each sweep's launches (the colour passes, and the refresh that precedes every
+ * refresh_every-th sweep) once into HIP graphs and replay them on later hmc_sweep calls.
+ * Needs a context created on a non-null stream (HMC_EINVAL otherwise).  Graphs are
+ * dropped and re-captured whenever orientations, spins, loads or the elastic state change.
+ * Kernel timing (hmc_set_profiling) bypasses the graphs while it is on. */
+hmc_status hmc_set_graphs(hmc_ctx ctx, int32_t enable);
+
+/* ---- Batches: many independent replicas in every launch -----------------------------
+ * A batch is an hmc_ctx whose replicas differ in lattice size, grains, temperature, load,
+ * elastic scale, global relaxation constants and Philox seed, and share everything else in
+ * the common hmc_params (neighbours, proposal, zone, step counts, J, C11/C12/C44; the
+ * common K, kT, lambda_el, glob_* and seed are ignored).  Every colour pass, zone-solve
+ * pass and explicit refresh step is one launch over all replicas; with hmc_set_graphs a
+ * whole sweep of all replicas is one graph launch.  Results per replica are identical to
+ * running it alone with the same parameters. */
+typedef struct {
+    int32_t K;              /* lattice edge (same rules as hmc_params.K) */
+    int32_t Q;              /* grains of this replica */
+    double kT;
+    double lambda_el;       /* 0: elastic term off for this replica */
+    double glob_alpha, glob_beta, glob_alphaE;
+    double sigma_MPa[6];    /* applied average stress (Voigt, MPa) */
+    uint64_t seed;          /* Philox key */
+} hmc_replica;
+
+/* Fill *r for a K^3 replica with Q grains: kT and seed from common, lambda_el = 2.6667e6/K
+ * and the global heavy-ball constants for K as in hmc_default_params, zero load. */
+hmc_status hmc_default_replica(hmc_replica* r, const hmc_params* common, int32_t K, int32_t Q);
+
+/* Workspace bytes of a batch of n replicas (0 if any description is invalid). */
+size_t hmc_batch_workspace_bytes(const hmc_params* common, int32_t n, const hmc_replica* reps);
+
+/* Create a batch of 1 <= n <= 4096 replicas (host array reps, copied).  Same workspace and
+ * stream rules as hmc_create.  Then give every replica its orientations and spins with
+ * hmc_batch_set_replica; hmc_stress_refresh, hmc_sweep, hmc_set_sweep_index, hmc_get_stats,
+ * hmc_set_profiling/hmc_get_kernel_times and hmc_set_graphs act on all replicas. */
+hmc_status hmc_batch_create(const hmc_params* common, int32_t n, const hmc_replica* reps, void* dev_workspace,
+                            size_t ws_bytes, hipStream_t stream, hmc_ctx* out);
+
+/* Replica r's orientations (host, Q_r Bunge triples) and spins (dev, K_r^3 int32). */
+hmc_status hmc_batch_set_replica(hmc_ctx ctx, int32_t r, const double* euler_host, const int32_t* spins_dev);
+
+/* Per-replica read-outs, as hmc_get_spins / hmc_get_stress / hmc_energy /
+ * hmc_texture_histogram for replica r (those four act on replica 0). */
+hmc_status hmc_batch_get_spins(hmc_ctx ctx, int32_t r, int32_t* spins_dev);
+hmc_status hmc_batch_get_stress(hmc_ctx ctx, int32_t r, float* dev_out);
+hmc_status hmc_batch_energy(hmc_ctx ctx, int32_t r, int64_t* unlike_bonds, double* U_el);
+hmc_status hmc_batch_texture_histogram(hmc_ctx ctx, int32_t r, const double axis[3], double bin_deg,
+                                       int32_t nbins, int64_t* counts_host);
+
+/* ---- Adjoint of the global explicit solve (single-lattice contexts) ------------------
+ * U(theta, Sigma) = stored elastic energy after a cold start and n_steps explicit steps of
+ * the global relaxation (as hmc_stress_refresh(ctx, n_steps, 1)), as a function of every
+ * grain's Euler angles theta and the applied stress Sigma.  hmc_elastic_forward runs it and
+ * keeps a checkpoint of the state every ckpt_every steps in the caller's adjoint workspace
+ * (dev, hmc_adjoint_workspace_bytes, 256-byte aligned); hmc_elastic_backward recomputes one
+ * segment at a time from those checkpoints and runs the reverse recurrence, returning
+ * dU * dU/dtheta (host, Q x 3, per radian) and dU * dU/dSigma (host, 6, per MPa).  The
+ * backward call leaves the context at the forward's final state.  The adjoint workspace must
+ * not change between the two calls.  HMC_ESTATE on batches, without a forward, or with the
+ * elastic term disabled. */
+size_t hmc_adjoint_workspace_bytes(hmc_ctx ctx, int32_t n_steps, int32_t ckpt_every);
+hmc_status hmc_elastic_forward(hmc_ctx ctx, int32_t n_steps, int32_t ckpt_every, void* dev_adjoint_ws,
+                               size_t adjoint_ws_bytes, double* U_host);
+hmc_status hmc_elastic_backward(hmc_ctx ctx, void* dev_adjoint_ws, size_t adjoint_ws_bytes, double dU,
+                                double* grad_euler_host, double grad_sigma_MPa[6]);
+
 /* Host-only helper (no device use): lab-frame Voigt stiffness and compliance (Q x 36
  * doubles each, row-major 6x6) exactly as hmc_set_orientations computes them before the
  * single-precision upload.  The compliance is built from the closed-form cubic compliance
  * and the strain transformation, not by inverting C. */
 hmc_status hmc_grain_tables(const double* euler_host, int32_t Q, double C11, double C12,
                             double C44, double* C_out, double* S_out);
+
+/* Host-only helper (no device use): derivatives of those tables with respect to the three
+ * Euler angles, dC_out and dS_out of Q x 3 x 36 doubles ([grain][angle][6x6 row-major]),
+ * by differentiating A = Rz(phi1) Rx(Phi) Rz(phi2) factor by factor. */
+hmc_status hmc_grain_table_derivatives(const double* euler_host, int32_t Q, double C11, double C12,
+                                       double C44, double* dC_out, double* dS_out);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,594 @@
+// hmc_adjoint.hip -- reverse-mode derivative of the global explicit elastic solve (Sec. 5)
+// with respect to the per-grain Euler angles and the applied stress.
+//
+// Forward (as hmc_stress_refresh with a cold start): E_0 = mean(S_q) Sigma, u_0 = w_0 = 0,
+// then n explicit steps; U = 1/2 sum_v eps_v . C_v eps_v at the final state.  With the state
+// of step t written (u_t, w_t, E_t, wE_t), the adjoint runs the recurrence backwards:
+//
+//   w~ = w^_{t+1} + u^_{t+1},  a = alpha w~          (nodal)
+//   wE~ = wE^_{t+1} + E^_{t+1}, b = alphaE wE~       (6)
+//   eta_v = B_v a + b / K^3,  tau_v = C_v eta_v      (per voxel: the adjoint stress)
+//   u^_t = u^_{t+1} - sum_v B_v^T tau_v,   w^_t = beta w~
+//   E^_t = E^_{t+1} - sum_v tau_v,         wE^_t = beta wE~
+//   dU/dtheta_g += -sum_{v in g} eta_v . (dC_g/dtheta) eps_{t,v},   dU/dSigma += b
+//
+// from u^_n = sum_v B_v^T sigma_v, E^_n = sum_v sigma_v, w^_n = wE^_n = 0 and the direct
+// term dU/dtheta_g += sum_{v in g} 1/2 eps_v . (dC_g/dtheta) eps_v; after step 0 the start
+// E_0 = mean(S_q) Sigma adds E^_0 . (n_g/K^3) (dS_g/dtheta) Sigma and mean(S) E^_0.
+//
+// The stiffness-derivative terms are accumulated per voxel as the symmetric 6x6 matrix
+// M_v = 1/2 eps_n eps_n^T - sum_t sym(eta_t eps_t^T) (FP64) and contracted with dC/dtheta
+// once at the end; per-grain sums use 64-bit fixed-point atomics (order-independent, so
+// the result is deterministic).  Forward states are recovered from checkpoints every
+// `ckpt_every` steps by recomputing one segment at a time.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "hmc_device.h"
+
+namespace hmc {
+
+constexpr double kFixScale = 1099511627776.0;   // 2^40
+
+struct AdjLayout {
+    size_t ckpt, seg_u, seg_E, ub0, ub1, wb0, wb1, M, dC, dS, adj, grad, total;
+    int n_ck;          // checkpoints of segment starts
+    size_t ck_bytes;   // bytes per checkpoint: u, w planes then 12 doubles
+};
+
+static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+static AdjLayout adj_layout(const hmc_ctx_s* c, int n_steps, int k)
+{
+    AdjLayout L{};
+    const size_t n3 = (size_t)c->reps[0].n3;
+    const size_t Q = (size_t)c->reps[0].Q;
+    L.n_ck = (n_steps + k - 1) / k + 1;          // + the final state
+    L.ck_bytes = al256(6 * n3 * sizeof(float)) + 256;
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        const size_t at = o;
+        o = al256(o + b);
+        return at;
+    };
+    L.ckpt = take((size_t)L.n_ck * L.ck_bytes);
+    L.seg_u = take((size_t)(k + 1) * 3 * n3 * sizeof(float));
+    L.seg_E = take((size_t)(k + 1) * 8 * sizeof(double));
+    L.ub0 = take(3 * n3 * sizeof(float));
+    L.ub1 = take(3 * n3 * sizeof(float));
+    L.wb0 = take(3 * n3 * sizeof(float));
+    L.wb1 = take(3 * n3 * sizeof(float));
+    L.M = take(21 * n3 * sizeof(double));
+    L.dC = take(Q * 3 * kTab * sizeof(float));
+    L.dS = take(Q * 3 * kTab * sizeof(float));
+    L.adj = take(64 * sizeof(double));
+    L.grad = take(Q * 3 * sizeof(unsigned long long));
+    L.total = o;
+    return L;
+}
+
+// Slots of the adjoint's small state block.
+enum AdjSlot { kEb = 0, kWEb = 6, kB = 12, kSigb = 18, kWEt = 24, kE0 = 30, kAdjDoubles = 64 };
+
+__device__ __forceinline__ void sym_acc(double* __restrict__ M, int64_t n3, int64_t v, const float x[6],
+                                        const float y[6], double scale)
+{
+    // M_IJ += scale * (x_I y_J + x_J y_I) / 2 over the upper triangle
+    int k = 0;
+#pragma unroll
+    for (int I = 0; I < 6; ++I)
+#pragma unroll
+        for (int J = I; J < 6; ++J) {
+            const double s = 0.5 * ((double)x[I] * (double)y[J] + (double)x[J] * (double)y[I]);
+            M[(int64_t)k * n3 + v] += scale * s;
+            ++k;
+        }
+}
+
+struct AdjInitArgs {
+    const int16_t* spins;
+    const float* Ctab;
+    const float* u;
+    float* ub;
+    float* wb;
+    double* M;
+    double* partials;
+    const double* state;
+    int K;
+    int64_t n3;
+};
+
+// Final-state adjoint: u^_n = sum_v B_v^T sigma_v, M_v = 1/2 eps eps^T, partial sums of sigma.
+__global__ __launch_bounds__(256) void k_adj_init(AdjInitArgs a)
+{
+    const int K = a.K;
+    float E[6];
+#pragma unroll
+    for (int I = 0; I < 6; ++I) E[I] = (float)a.state[kE + I];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < a.n3; n += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(n % K), y = (int)((n / K) % K), z = (int)(n / ((int64_t)K * K));
+        float f[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int ca = c & 1, cb = (c >> 1) & 1, cc = c >> 2;
+            const int vx = wrapk(x - ca, K), vy = wrapk(y - cb, K), vz = wrapk(z - cc, K);
+            float e[6], s[6];
+            voxel_strain(a.u, a.n3, K, vx, vy, vz, E, e);
+            const int g = a.spins[vx + (int64_t)K * (vy + (int64_t)K * vz)];
+            symv21(a.Ctab + (int64_t)g * kTab, e, s);
+            const float sx = ca ? 0.25f : -0.25f, sy = cb ? 0.25f : -0.25f, sz = cc ? 0.25f : -0.25f;
+            f[0] += sx * s[0] + sy * s[5] + sz * s[4];
+            f[1] += sx * s[5] + sy * s[1] + sz * s[3];
+            f[2] += sx * s[4] + sy * s[3] + sz * s[2];
+            if (c == 0) {
+#pragma unroll
+                for (int I = 0; I < 6; ++I) acc[I] += (double)s[I];
+                int k = 0;
+#pragma unroll
+                for (int I = 0; I < 6; ++I)
+#pragma unroll
+                    for (int J = I; J < 6; ++J) {
+                        a.M[(int64_t)k * a.n3 + n] = 0.5 * (double)e[I] * (double)e[J];
+                        ++k;
+                    }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            a.ub[(int64_t)j * a.n3 + n] = f[j];
+            a.wb[(int64_t)j * a.n3 + n] = 0.f;
+        }
+    }
+    block_sum_to<6>(a.partials, acc);
+}
+
+struct AdjStepArgs {
+    const int16_t* spins;
+    const float* Ctab;
+    const float* ub_in;
+    float* ub_out;
+    const float* wb_in;      // read at neighbour nodes: ping-pong like ub
+    float* wb_out;
+    const float* u_t;        // forward displacement of step t
+    const double* E_t;       // forward macroscopic strain of step t (6)
+    const double* adj;       // b
+    double* M;
+    double* partials;
+    int K;
+    int64_t n3;
+    float alpha, beta;
+};
+
+__device__ __forceinline__ void adj_a_strain(const float* __restrict__ ub, const float* __restrict__ wb, int64_t n3,
+                                             int K, int vx, int vy, int vz, float alpha, const float b3[6],
+                                             float eta[6])
+{
+    // eta = B_v a + b/K^3 with a = alpha (w^ + u^) at the voxel's corners
+    const int x1 = wrapk(vx + 1, K), y1 = wrapk(vy + 1, K), z1 = wrapk(vz + 1, K);
+    const int64_t n[8] = {
+        vx + (int64_t)K * (vy + (int64_t)K * vz), x1 + (int64_t)K * (vy + (int64_t)K * vz),
+        vx + (int64_t)K * (y1 + (int64_t)K * vz), x1 + (int64_t)K * (y1 + (int64_t)K * vz),
+        vx + (int64_t)K * (vy + (int64_t)K * z1), x1 + (int64_t)K * (vy + (int64_t)K * z1),
+        vx + (int64_t)K * (y1 + (int64_t)K * z1), x1 + (int64_t)K * (y1 + (int64_t)K * z1)};
+    float g[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const float* uj = ub + (int64_t)j * n3;
+        const float* wj = wb + (int64_t)j * n3;
+        float cv[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) cv[c] = alpha * (wj[n[c]] + uj[n[c]]);
+        g[j][0] = 0.25f * ((cv[1] - cv[0]) + (cv[3] - cv[2]) + (cv[5] - cv[4]) + (cv[7] - cv[6]));
+        g[j][1] = 0.25f * ((cv[2] + cv[3]) - (cv[0] + cv[1]) + (cv[6] + cv[7]) - (cv[4] + cv[5]));
+        g[j][2] = 0.25f * ((cv[4] + cv[5] + cv[6] + cv[7]) - (cv[0] + cv[1] + cv[2] + cv[3]));
+    }
+    eta[0] = b3[0] + g[0][0];
+    eta[1] = b3[1] + g[1][1];
+    eta[2] = b3[2] + g[2][2];
+    eta[3] = b3[3] + g[1][2] + g[2][1];
+    eta[4] = b3[4] + g[0][2] + g[2][0];
+    eta[5] = b3[5] + g[0][1] + g[1][0];
+}
+
+__global__ __launch_bounds__(256) void k_adj_step(AdjStepArgs a)
+{
+    const int K = a.K;
+    float b3[6], E[6];
+    const double inv_n3 = 1.0 / (double)a.n3;
+#pragma unroll
+    for (int I = 0; I < 6; ++I) {
+        b3[I] = (float)(a.adj[kB + I] * inv_n3);
+        E[I] = (float)a.E_t[I];
+    }
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < a.n3; n += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(n % K), y = (int)((n / K) % K), z = (int)(n / ((int64_t)K * K));
+        float f[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int ca = c & 1, cb = (c >> 1) & 1, cc = c >> 2;
+            const int vx = wrapk(x - ca, K), vy = wrapk(y - cb, K), vz = wrapk(z - cc, K);
+            float eta[6], tau[6];
+            adj_a_strain(a.ub_in, a.wb_in, a.n3, K, vx, vy, vz, a.alpha, b3, eta);
+            const int g = a.spins[vx + (int64_t)K * (vy + (int64_t)K * vz)];
+            symv21(a.Ctab + (int64_t)g * kTab, eta, tau);
+            const float sx = ca ? 0.25f : -0.25f, sy = cb ? 0.25f : -0.25f, sz = cc ? 0.25f : -0.25f;
+            f[0] += sx * tau[0] + sy * tau[5] + sz * tau[4];
+            f[1] += sx * tau[5] + sy * tau[1] + sz * tau[3];
+            f[2] += sx * tau[4] + sy * tau[3] + sz * tau[2];
+            if (c == 0) {
+#pragma unroll
+                for (int I = 0; I < 6; ++I) acc[I] += (double)tau[I];
+                float eps[6];
+                voxel_strain(a.u_t, a.n3, K, vx, vy, vz, E, eps);
+                sym_acc(a.M, a.n3, n, eta, eps, -1.0);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int64_t idx = (int64_t)j * a.n3 + n;
+            const float u_in = a.ub_in[idx];
+            a.ub_out[idx] = u_in - f[j];
+            a.wb_out[idx] = a.beta * (a.wb_in[idx] + u_in);
+        }
+    }
+    block_sum_to<6>(a.partials, acc);
+}
+
+// Folds the per-block sums (fixed order).  mode 0 (start): E^ = sum sigma, wE^ = 0,
+// Sigma^ = 0.  mode 1 (after a step): E^ -= sum tau, wE^ = beta wE~, Sigma^ += b.  Both then
+// prepare the next step: wE~ = wE^ + E^, b = alphaE wE~.
+__global__ __launch_bounds__(256) void k_adj_E(double* adj, const double* partials, int nblocks, int mode,
+                                               double betaE, double alphaE)
+{
+    __shared__ double red[6][256];
+    const int t = threadIdx.x;
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int bk = t; bk < nblocks; bk += 256)
+#pragma unroll
+        for (int I = 0; I < 6; ++I) s[I] += partials[(int64_t)bk * 8 + I];
+#pragma unroll
+    for (int I = 0; I < 6; ++I) red[I][t] = s[I];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h)
+#pragma unroll
+            for (int I = 0; I < 6; ++I) red[I][t] += red[I][t + h];
+        __syncthreads();
+    }
+    if (t < 6) {
+        if (mode == 0) {
+            adj[kEb + t] = red[t][0];
+            adj[kWEb + t] = 0.0;
+            adj[kSigb + t] = 0.0;
+        } else {
+            adj[kEb + t] -= red[t][0];
+            adj[kWEb + t] = betaE * adj[kWEt + t];
+            adj[kSigb + t] += adj[kB + t];
+        }
+        const double wt = adj[kWEb + t] + adj[kEb + t];
+        adj[kWEt + t] = wt;
+        adj[kB + t] = alphaE * wt;
+    }
+}
+
+struct AdjGradArgs {
+    const int16_t* spins;
+    const float* Stab;
+    const float* dC;    // Q x 3 x kTab
+    const float* dS;
+    const double* M;
+    const double* adj;  // E^_0 at kEb
+    double Sigma[6];
+    unsigned long long* grad;   // Q x 3 fixed point
+    double* partials;
+    int64_t n3;
+};
+
+// Per voxel: the three stiffness-angle contractions dC : M_v plus the start-strain term
+// (1/K^3) E^_0 . dS Sigma into its grain (fixed-point atomics); partial sums of S E^_0.
+__global__ __launch_bounds__(256) void k_adj_grad(AdjGradArgs a)
+{
+    double Eb[6];
+    float Ebf[6];
+    const double inv_n3 = 1.0 / (double)a.n3;
+#pragma unroll
+    for (int I = 0; I < 6; ++I) {
+        Eb[I] = a.adj[kEb + I];
+        Ebf[I] = (float)Eb[I];
+    }
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.n3; v += (int64_t)gridDim.x * blockDim.x) {
+        const int g = a.spins[v];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const float* dc = a.dC + ((int64_t)g * 3 + q) * kTab;
+            const float* ds = a.dS + ((int64_t)g * 3 + q) * kTab;
+            double val = 0.0;
+            int k = 0;
+#pragma unroll
+            for (int I = 0; I < 6; ++I)
+#pragma unroll
+                for (int J = I; J < 6; ++J) {
+                    val += (I == J ? 1.0 : 2.0) * (double)dc[k] * a.M[(int64_t)k * a.n3 + v];
+                    // start term: E^_0 . (dS Sigma) with the symmetric dS
+                    const double sym = (I == J) ? Eb[I] * a.Sigma[I] : Eb[I] * a.Sigma[J] + Eb[J] * a.Sigma[I];
+                    val += inv_n3 * (double)ds[k] * sym;
+                    ++k;
+                }
+            const long long fx = llrint(val * kFixScale);
+            atomicAdd(&a.grad[(int64_t)g * 3 + q], (unsigned long long)fx);
+        }
+        float se[6];
+        symv21(a.Stab + (int64_t)g * kTab, Ebf, se);
+#pragma unroll
+        for (int I = 0; I < 6; ++I) acc[I] += (double)se[I];
+    }
+    block_sum_to<6>(a.partials, acc);
+}
+
+}  // namespace hmc
+
+using namespace hmc;
+
+namespace {
+
+hmc_status afail(hmc_ctx c, hmc_status s, const char* m)
+{
+    c->err = m;
+    return s;
+}
+
+hmc_status adev(hmc_ctx c, hipError_t e, const char* where)
+{
+    c->err = std::string(where) + ": " + hipGetErrorString(e);
+    return HMC_EDEVICE;
+}
+
+#define ATRY(expr, where)                              \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return adev(c, e_, where); \
+    } while (0)
+
+int adj_blocks(int64_t n3)
+{
+    int64_t b = (n3 + 255) / 256;
+    if (b > kMaxChunkBlocks) b = kMaxChunkBlocks;
+    return (int)(b < 1 ? 1 : b);
+}
+
+// checkpoint j: u (3 planes), w (3 planes), then E, wE (12 doubles)
+hmc_status save_ckpt(hmc_ctx c, char* base, const AdjLayout& L, int j)
+{
+    const size_t n3 = (size_t)c->reps[0].n3;
+    char* ck = base + L.ckpt + (size_t)j * L.ck_bytes;
+    ATRY(hipMemcpyAsync(ck, c->d.u[c->cur_u], 3 * n3 * sizeof(float), hipMemcpyDeviceToDevice, c->stream), "ckpt");
+    ATRY(hipMemcpyAsync(ck + 3 * n3 * sizeof(float), c->d.w, 3 * n3 * sizeof(float), hipMemcpyDeviceToDevice,
+                        c->stream),
+         "ckpt");
+    ATRY(hipMemcpyAsync(ck + al256(6 * n3 * sizeof(float)), c->d.state + kE, 12 * sizeof(double),
+                        hipMemcpyDeviceToDevice, c->stream),
+         "ckpt");
+    return HMC_OK;
+}
+
+// restores checkpoint j with u into `u_dst`
+hmc_status load_ckpt(hmc_ctx c, char* base, const AdjLayout& L, int j, float* u_dst)
+{
+    const size_t n3 = (size_t)c->reps[0].n3;
+    char* ck = base + L.ckpt + (size_t)j * L.ck_bytes;
+    ATRY(hipMemcpyAsync(u_dst, ck, 3 * n3 * sizeof(float), hipMemcpyDeviceToDevice, c->stream), "restore");
+    ATRY(hipMemcpyAsync(c->d.w, ck + 3 * n3 * sizeof(float), 3 * n3 * sizeof(float), hipMemcpyDeviceToDevice,
+                        c->stream),
+         "restore");
+    ATRY(hipMemcpyAsync(c->d.state + kE, ck + al256(6 * n3 * sizeof(float)), 12 * sizeof(double),
+                        hipMemcpyDeviceToDevice, c->stream),
+         "restore");
+    return HMC_OK;
+}
+
+hmc_status check_adj(hmc_ctx c, int n_steps, int k, void* ws, size_t bytes, AdjLayout* L)
+{
+    if (c->is_batch || c->n_rep != 1) return afail(c, HMC_ESTATE, "the adjoint acts on a single lattice");
+    if (!c->elastic_buffers) return afail(c, HMC_ESTATE, "elastic term disabled (lambda_el == 0)");
+    if (n_steps < 1 || k < 1) return afail(c, HMC_EINVAL, "need n_steps >= 1 and ckpt_every >= 1");
+    if (!ws || ((uintptr_t)ws % 256) != 0) return afail(c, HMC_EINVAL, "adjoint workspace must be 256-byte aligned");
+    *L = adj_layout(c, n_steps, k);
+    if (bytes < L->total) return afail(c, HMC_ESHAPE, "adjoint workspace too small");
+    return HMC_OK;
+}
+
+}  // namespace
+
+namespace hmc {
+hipError_t launch_global_step_ptrs(hmc_ctx_s* c, const float* uin, float* uout);
+}
+
+extern "C" {
+
+size_t hmc_adjoint_workspace_bytes(hmc_ctx c, int32_t n_steps, int32_t ckpt_every)
+{
+    if (!c || c->n_rep != 1 || n_steps < 1 || ckpt_every < 1) return 0;
+    return adj_layout(c, n_steps, ckpt_every).total;
+}
+
+hmc_status hmc_elastic_forward(hmc_ctx c, int32_t n_steps, int32_t ckpt_every, void* ws, size_t bytes, double* U)
+{
+    if (!c) return HMC_EINVAL;
+    c->err.clear();
+    AdjLayout L;
+    hmc_status st = check_adj(c, n_steps, ckpt_every, ws, bytes, &L);
+    if (st != HMC_OK) return st;
+    if (!U) return afail(c, HMC_EINVAL, "null output");
+    if (!c->have_orient || !c->have_spins || !c->have_load)
+        return afail(c, HMC_ESTATE, "forward needs orientations, spins and a load");
+    char* base = (char*)ws;
+    // cold start exactly as hmc_stress_refresh
+    ATRY(launch_fill_f32(c->d.u[0], 0.f, 3 * c->total_sites, c->stream), "forward");
+    ATRY(launch_fill_f32(c->d.w, 0.f, 3 * c->total_sites, c->stream), "forward");
+    c->cur_u = 0;
+    ATRY(launch_reuss(c), "forward");
+    for (int t = 0; t < n_steps; ++t) {
+        if (t % ckpt_every == 0) {
+            st = save_ckpt(c, base, L, t / ckpt_every);
+            if (st != HMC_OK) return st;
+        }
+        ATRY(launch_global_steps(c, 1), "forward");
+    }
+    st = save_ckpt(c, base, L, L.n_ck - 1);   // final state
+    if (st != HMC_OK) return st;
+    ATRY(launch_global_final(c, true), "forward");
+    double u = 0;
+    ATRY(hipMemcpyAsync(&u, c->d.state + kU, sizeof u, hipMemcpyDeviceToHost, c->stream), "forward");
+    ATRY(hipStreamSynchronize(c->stream), "forward");
+    c->host_refresh_steps += n_steps;
+    c->have_state = c->have_stress = true;
+    c->adj_steps = n_steps;
+    c->adj_every = ckpt_every;
+    *U = u;
+    return HMC_OK;
+}
+
+hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, double* grad_euler,
+                                double grad_sigma_MPa[6])
+{
+    if (!c) return HMC_EINVAL;
+    c->err.clear();
+    if (c->adj_steps < 1) return afail(c, HMC_ESTATE, "no forward pass recorded");
+    AdjLayout L;
+    const int n = c->adj_steps, k = c->adj_every;
+    hmc_status st = check_adj(c, n, k, ws, bytes, &L);
+    if (st != HMC_OK) return st;
+    if (!grad_euler || !grad_sigma_MPa) return afail(c, HMC_EINVAL, "null output");
+    const RepDev& R = c->reps[0];
+    const int64_t n3 = R.n3;
+    const int Q = R.Q;
+    char* base = (char*)ws;
+    float* seg_u = (float*)(base + L.seg_u);
+    double* seg_E = (double*)(base + L.seg_E);
+    float* ub[2] = {(float*)(base + L.ub0), (float*)(base + L.ub1)};
+    float* wb[2] = {(float*)(base + L.wb0), (float*)(base + L.wb1)};
+    double* M = (double*)(base + L.M);
+    float* dC = (float*)(base + L.dC);
+    float* dS = (float*)(base + L.dS);
+    double* adj = (double*)(base + L.adj);
+    unsigned long long* grad = (unsigned long long*)(base + L.grad);
+    const int nb = adj_blocks(n3);
+
+    // per-grain derivative tables
+    {
+        std::vector<float> hC((size_t)Q * 3 * kTab, 0.f), hS((size_t)Q * 3 * kTab, 0.f);
+        std::vector<double> dCd((size_t)Q * 108), dSd((size_t)Q * 108);
+        if (hmc_grain_table_derivatives(c->euler.data(), Q, c->p.C11, c->p.C12, c->p.C44, dCd.data(), dSd.data()) !=
+            HMC_OK)
+            return afail(c, HMC_ENUMERIC, "orientation derivatives");
+        for (int g = 0; g < Q; ++g)
+            for (int q = 0; q < 3; ++q)
+                for (int i = 0; i < 6; ++i)
+                    for (int j = i; j < 6; ++j) {
+                        hC[((size_t)g * 3 + q) * kTab + sym_index(i, j)] = (float)dCd[(size_t)g * 108 + q * 36 + 6 * i + j];
+                        hS[((size_t)g * 3 + q) * kTab + sym_index(i, j)] = (float)dSd[(size_t)g * 108 + q * 36 + 6 * i + j];
+                    }
+        ATRY(hipMemcpyAsync(dC, hC.data(), hC.size() * sizeof(float), hipMemcpyHostToDevice, c->stream), "backward");
+        ATRY(hipMemcpyAsync(dS, hS.data(), hS.size() * sizeof(float), hipMemcpyHostToDevice, c->stream), "backward");
+        ATRY(hipMemsetAsync(grad, 0, (size_t)Q * 3 * sizeof(unsigned long long), c->stream), "backward");
+        ATRY(hipStreamSynchronize(c->stream), "backward");
+    }
+
+    // final state -> initial adjoint
+    st = load_ckpt(c, base, L, L.n_ck - 1, c->d.u[0]);
+    if (st != HMC_OK) return st;
+    c->cur_u = 0;
+    {
+        AdjInitArgs a{c->d.spins, c->d.Ctab, c->d.u[0], ub[0], wb[0], M, c->d.partials, c->d.state, R.K, n3};
+        hipLaunchKernelGGL(k_adj_init, dim3(nb), dim3(256), 0, c->stream, a);
+        hipLaunchKernelGGL(k_adj_E, dim3(1), dim3(256), 0, c->stream, adj, c->d.partials, nb, 0, (double)R.glob_beta,
+                           R.glob_alphaE);
+        ATRY(hipGetLastError(), "backward: start");
+    }
+    int cur_b = 0;
+    const int n_seg = (n + k - 1) / k;
+    for (int j = n_seg - 1; j >= 0; --j) {
+        const int t0 = j * k, t1 = (t0 + k < n) ? t0 + k : n;
+        // recompute the segment's forward states u_t, E_t for t in [t0, t1)
+        st = load_ckpt(c, base, L, j, seg_u);
+        if (st != HMC_OK) return st;
+        for (int t = t0; t < t1; ++t) {
+            float* ut = seg_u + (size_t)(t - t0) * 3 * n3;
+            ATRY(hipMemcpyAsync(seg_E + (size_t)(t - t0) * 8, c->d.state + kE, 6 * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->stream),
+                 "backward: recompute");
+            if (t + 1 < t1) ATRY(launch_global_step_ptrs(c, ut, ut + 3 * n3), "backward: recompute");
+        }
+        // adjoint steps t1-1 .. t0
+        for (int t = t1 - 1; t >= t0; --t) {
+            AdjStepArgs a;
+            a.spins = c->d.spins;
+            a.Ctab = c->d.Ctab;
+            a.ub_in = ub[cur_b];
+            a.ub_out = ub[1 - cur_b];
+            a.wb_in = wb[cur_b];
+            a.wb_out = wb[1 - cur_b];
+            a.u_t = seg_u + (size_t)(t - t0) * 3 * n3;
+            a.E_t = seg_E + (size_t)(t - t0) * 8;
+            a.adj = adj;
+            a.M = M;
+            a.partials = c->d.partials;
+            a.K = R.K;
+            a.n3 = n3;
+            a.alpha = R.glob_alpha;
+            a.beta = R.glob_beta;
+            const int tok = prof_begin(c, kProfRefreshStep);
+            hipLaunchKernelGGL(k_adj_step, dim3(nb), dim3(256), 0, c->stream, a);
+            prof_end(c, tok);
+            hipLaunchKernelGGL(k_adj_E, dim3(1), dim3(256), 0, c->stream, adj, c->d.partials, nb, 1,
+                               (double)R.glob_beta, R.glob_alphaE);
+            ATRY(hipGetLastError(), "backward: step");
+            cur_b = 1 - cur_b;
+        }
+    }
+    // contractions and the start-strain terms
+    {
+        AdjGradArgs a;
+        a.spins = c->d.spins;
+        a.Stab = c->d.Stab;
+        a.dC = dC;
+        a.dS = dS;
+        a.M = M;
+        a.adj = adj;
+        for (int I = 0; I < 6; ++I) a.Sigma[I] = R.Sigma[I];
+        a.grad = grad;
+        a.partials = c->d.partials;
+        a.n3 = n3;
+        hipLaunchKernelGGL(k_adj_grad, dim3(nb), dim3(256), 0, c->stream, a);
+        ATRY(hipGetLastError(), "backward: gradient");
+    }
+    std::vector<unsigned long long> g((size_t)Q * 3);
+    std::vector<double> parts((size_t)nb * 8);
+    double ad[kAdjDoubles];
+    ATRY(hipMemcpyAsync(g.data(), grad, g.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream),
+         "backward");
+    ATRY(hipMemcpyAsync(parts.data(), c->d.partials, parts.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+         "backward");
+    ATRY(hipMemcpyAsync(ad, adj, sizeof ad, hipMemcpyDeviceToHost, c->stream), "backward");
+    ATRY(hipStreamSynchronize(c->stream), "backward");
+    for (size_t i = 0; i < g.size(); ++i) grad_euler[i] = dU * (double)(long long)g[i] / kFixScale;
+    for (int I = 0; I < 6; ++I) {
+        double s = 0.0;   // mean(S) E^_0, folded in block order
+        for (int b = 0; b < nb; ++b) s += parts[(size_t)b * 8 + I];
+        // dU/dSigma in GPa^-1 * GPa*voxel; per MPa: x 1e-3
+        grad_sigma_MPa[I] = dU * (ad[kSigb + I] + s / (double)n3) * 1e-3;
+    }
+    // leave the context at the final forward state
+    st = load_ckpt(c, base, L, L.n_ck - 1, c->d.u[0]);
+    if (st != HMC_OK) return st;
+    c->cur_u = 0;
+    ATRY(launch_global_final(c, true), "backward: restore");
+    ATRY(hipStreamSynchronize(c->stream), "backward: restore");
+    return HMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// hmc_device.h -- device helpers shared by the global-solve and adjoint kernels.
+#pragma once
+
+#include "hmc_internal.h"
+
+namespace hmc {
+
+__device__ __forceinline__ int wrapk(int a, int K) { return a < 0 ? a + K : (a >= K ? a - K : a); }
+
+__device__ __forceinline__ void symv21(const float* __restrict__ c, const float e[6], float s[6])
+{
+    s[0] = c[0] * e[0] + c[1] * e[1] + c[2] * e[2] + c[3] * e[3] + c[4] * e[4] + c[5] * e[5];
+    s[1] = c[1] * e[0] + c[6] * e[1] + c[7] * e[2] + c[8] * e[3] + c[9] * e[4] + c[10] * e[5];
+    s[2] = c[2] * e[0] + c[7] * e[1] + c[11] * e[2] + c[12] * e[3] + c[13] * e[4] + c[14] * e[5];
+    s[3] = c[3] * e[0] + c[8] * e[1] + c[12] * e[2] + c[15] * e[3] + c[16] * e[4] + c[17] * e[5];
+    s[4] = c[4] * e[0] + c[9] * e[1] + c[13] * e[2] + c[16] * e[3] + c[18] * e[4] + c[19] * e[5];
+    s[5] = c[5] * e[0] + c[10] * e[1] + c[14] * e[2] + c[17] * e[3] + c[19] * e[4] + c[20] * e[5];
+}
+
+// Strain E + B_v u of voxel (vx,vy,vz) of the periodic grid.
+__device__ __forceinline__ void voxel_strain(const float* __restrict__ u, int64_t n3, int K, int vx, int vy,
+                                             int vz, const float E[6], float e[6])
+{
+    const int x1 = wrapk(vx + 1, K), y1 = wrapk(vy + 1, K), z1 = wrapk(vz + 1, K);
+    const int64_t n[8] = {
+        vx + (int64_t)K * (vy + (int64_t)K * vz), x1 + (int64_t)K * (vy + (int64_t)K * vz),
+        vx + (int64_t)K * (y1 + (int64_t)K * vz), x1 + (int64_t)K * (y1 + (int64_t)K * vz),
+        vx + (int64_t)K * (vy + (int64_t)K * z1), x1 + (int64_t)K * (vy + (int64_t)K * z1),
+        vx + (int64_t)K * (y1 + (int64_t)K * z1), x1 + (int64_t)K * (y1 + (int64_t)K * z1)};
+    float g[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const float* uj = u + (int64_t)j * n3;
+        const float c0 = uj[n[0]], c1 = uj[n[1]], c2 = uj[n[2]], c3 = uj[n[3]];
+        const float c4 = uj[n[4]], c5 = uj[n[5]], c6 = uj[n[6]], c7 = uj[n[7]];
+        g[j][0] = 0.25f * ((c1 - c0) + (c3 - c2) + (c5 - c4) + (c7 - c6));
+        g[j][1] = 0.25f * ((c2 + c3) - (c0 + c1) + (c6 + c7) - (c4 + c5));
+        g[j][2] = 0.25f * ((c4 + c5 + c6 + c7) - (c0 + c1 + c2 + c3));
+    }
+    e[0] = E[0] + g[0][0];
+    e[1] = E[1] + g[1][1];
+    e[2] = E[2] + g[2][2];
+    e[3] = E[3] + g[1][2] + g[2][1];
+    e[4] = E[4] + g[0][2] + g[2][0];
+    e[5] = E[5] + g[0][1] + g[1][0];
+}
+
+// Deterministic block sum of NV doubles per thread into partials[blockIdx.x * 8 + k].
+template <int NVALS>
+__device__ __forceinline__ void block_sum_to(double* __restrict__ partials, const double v[NVALS])
+{
+    __shared__ double red[NVALS][256];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < NVALS; ++k) red[k][t] = v[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (t < s) {
+#pragma unroll
+            for (int k = 0; k < NVALS; ++k) red[k][t] += red[k][t + s];
+        }
+        __syncthreads();
+    }
+    if (t < NVALS) partials[(int64_t)blockIdx.x * 8 + t] = red[t][0];
+}
+
+// Node-parallel kernels: block b belongs to replica node_rep[b]; within a replica the
+// blocks cover 256 consecutive nodes each (and stride by the replica's block count beyond
+// 8192 blocks), so the per-block partial sums and their fixed-order folding do not depend
+// on how many replicas share the launch.
+struct NodeRange {
+    RepDev R;
+    int64_t first, stride;
+};
+
+__device__ __forceinline__ NodeRange node_range(const RepDev* reps, const int32_t* node_rep)
+{
+    NodeRange n;
+    n.R = reps[node_rep[blockIdx.x]];
+    n.first = (int64_t)(blockIdx.x - n.R.node_first) * blockDim.x + threadIdx.x;
+    n.stride = (int64_t)n.R.node_blocks * blockDim.x;
+    return n;
+}
+
+}  // namespace hmc

@@ -1,4 +1,8 @@
 // hmc_internal.h -- shared declarations of the HIP library (host API <-> kernel launchers).
+//
+// Every kernel works on a table of replicas (independent lattices with their own size,
+// load, temperature and Philox key) laid end to end in shared buffers.  A single-lattice
+// context is a table of one; a batch fuses many replicas into each launch.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,84 +16,104 @@
 namespace hmc {
 
 // Per-grain tables on the device: the 21 distinct entries of a symmetric 6x6 Voigt matrix,
-// upper triangle row by row, padded to 24 floats (96 bytes, three 32-byte sectors).
+// upper triangle row by row, padded to 24 floats (96 bytes).
 constexpr int kTab = 24;
 
 __host__ __device__ constexpr int sym_index(int i, int j)
 {
-    // row-major upper triangle of a 6x6 matrix, i <= j
     return i * 6 - (i * (i - 1)) / 2 + (j - i);
 }
 
 // One entry of the compacted list of real trial flips of a colour pass.
 struct TrialEntry {
-    uint32_t site;
-    int32_t q_new;
+    uint32_t site;     // site index within its replica
+    uint32_t qr;       // q_new | replica << 16
     int32_t gb;
     uint32_t r1;
 };
 
-// Slots of the small device state block (doubles).
+constexpr int kMaxReplicas = 4096;
+constexpr int kSiteBlock = 256;        // sites (or nodes) per block of site-parallel kernels
+constexpr int kMaxChunkBlocks = 8192;  // blocks per replica of node-parallel reductions
+
+// Device description of one replica.
+struct RepDev {
+    int32_t K, Kh, Q, proposal;
+    int32_t elastic;                 // elastic term on for this replica (lambda != 0, load != 0)
+    int32_t pad0;
+    int64_t n3;
+    int64_t site_off;                // into spins / sigma / u / w planes (sites)
+    int64_t grain_off;               // into Ctab / Stab (grains)
+    int32_t pass_first, pass_blocks; // blocks of a colour pass (active sites / 256, rounded up)
+    int32_t node_first, node_blocks; // blocks of node-parallel kernels (<= kMaxChunkBlocks)
+    double J, kT, lambda;
+    float glob_alpha, glob_beta;
+    double glob_alphaE;
+    double Sigma[6];                 // applied average stress (GPa)
+    uint32_t key0, key1;
+};
+
+// Slots of the per-replica device state block (doubles).
 enum StateSlot {
     kE = 0,        // macroscopic strain E[6]
     kWE = 6,       // its heavy-ball velocity wE[6]
-    kSigma = 12,   // applied average stress (GPa)[6]
-    kU = 18,       // stored energy of the last energy evaluation
-    kStateDoubles = 32
+    kU = 12,       // stored energy of the last energy evaluation
+    kStateDoubles = 16
 };
 
-// Counters (uint32): list counts per colour, then error flags.
-enum CounterSlot {
-    kListCount = 0,   // [8]
-    kErrFlag = 8,
-    kCounters = 16
-};
+// Counters (uint32): list counts per colour, error flag.
+enum CounterSlot { kListCount = 0, kErrFlag = 8, kCounters = 16 };
 
 // 64-bit statistics slots.
 enum StatSlot { kStatReal = 0, kStatSolves = 1, kStatAccepted = 2, kStats = 8 };
 
-constexpr int kMaxPartials = 8192;   // blocks of one reduction pass
-
 struct DeviceState {
-    int16_t* spins = nullptr;        // K^3
-    float* Ctab = nullptr;           // Q x kTab
-    float* Stab = nullptr;           // Q x kTab
-    float* sigma = nullptr;          // 6 x K^3
-    float* u[2] = {nullptr, nullptr};  // 3 x K^3 each (ping-pong)
-    float* w = nullptr;              // 3 x K^3
+    int16_t* spins = nullptr;        // sum of n3
+    float* Ctab = nullptr;           // sum of Q, x kTab
+    float* Stab = nullptr;
+    float* sigma = nullptr;          // 6 planes of total sites
+    float* u[2] = {nullptr, nullptr};  // 3 planes each (ping-pong)
+    float* w = nullptr;              // 3 planes
     TrialEntry* list = nullptr;      // max_list
     uint8_t* accept = nullptr;       // max_list
-    double* state = nullptr;         // kStateDoubles
-    double* partials = nullptr;      // kMaxPartials x 8
+    double* state = nullptr;         // n_rep x kStateDoubles
+    double* partials = nullptr;      // total node blocks x 8
     uint32_t* counters = nullptr;    // kCounters
     unsigned long long* stats = nullptr;  // kStats
-    uint64_t* thr = nullptr;         // 2*M+1 integer Metropolis thresholds
-    int32_t* tex_bin = nullptr;      // Q
+    uint64_t* thr = nullptr;         // n_rep x 64 integer Metropolis thresholds
+    int32_t* tex_bin = nullptr;      // sum of Q
     unsigned long long* hist = nullptr;  // 64
     unsigned long long* bonds = nullptr; // 1
+    RepDev* reps = nullptr;          // n_rep
+    int32_t* pass_rep = nullptr;     // block -> replica for colour passes
+    int32_t* node_rep = nullptr;     // block -> replica for node kernels
+    int64_t* sweep = nullptr;        // device copy of the sweep index (Philox counter)
 };
 
 }  // namespace hmc
 
 struct hmc_ctx_s {
-    hmc_params p{};
-    int32_t Q = 0;
+    hmc_params p{};                 // common parameters (K of replica 0 for a single lattice)
+    int32_t Q = 0;                  // total grains
     hipStream_t stream = nullptr;
     int device = 0;
-    int64_t n3 = 0;
+    int n_rep = 1;
+    bool is_batch = false;
+    std::vector<hmc::RepDev> reps;  // host mirror of the replica table
+    std::vector<int64_t> rep_euler_off;  // per replica, offset into `euler` (grains)
+    int64_t total_sites = 0;
     int colours = 0;
     int64_t max_list = 0;
-    bool elastic_buffers = false;   // lambda_el != 0: stress/displacement buffers exist
-    bool load_nonzero = false;
+    int pass_blocks = 0;            // total blocks of a colour pass
+    int node_blocks = 0;            // total blocks of node kernels
+    bool elastic_buffers = false;
     bool have_orient = false, have_spins = false, have_load = false, have_stress = false;
-    bool have_state = false;        // displacement/E state initialised
-    int cur_u = 0;                  // which u buffer is current
+    bool have_state = false;
+    int cur_u = 0;
     int64_t sweep = 0;
     int64_t host_site_trials = 0;
     int64_t host_refresh_steps = 0;
-    double sigma_GPa[6] = {0, 0, 0, 0, 0, 0};
     std::vector<double> euler;      // host copy of the orientations (texture bins)
-    // kernel timing (hmc_set_profiling): pending event pairs per class
     bool profiling = false;
     struct ProfPair {
         int cls;
@@ -97,13 +121,25 @@ struct hmc_ctx_s {
     };
     std::vector<ProfPair> prof_pending;
     std::vector<hipEvent_t> prof_free;
+    // captured sweeps: [0] without refresh, [1] with refresh (valid for the cur_u parity
+    // recorded in graph_u)
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int graph_u[2] = {-1, -1};
+    bool use_graphs = false;
+    int adj_steps = 0, adj_every = 0;   // last hmc_elastic_forward
     hmc::DeviceState d;
     std::string err;
+
+    bool any_elastic() const
+    {
+        for (const auto& r : reps)
+            if (r.elastic) return true;
+        return false;
+    }
 };
 
 namespace hmc {
 
-// ---- kernel timing classes and hooks (no-ops unless profiling is on) ----
 enum ProfClass { kProfPotts = 0, kProfZone, kProfApply, kProfRefreshStep, kProfRefreshOther, kProfClasses };
 int prof_begin(hmc_ctx_s* c, int cls);   // returns a token (-1 when off)
 void prof_end(hmc_ctx_s* c, int token);
@@ -111,17 +147,19 @@ void prof_end(hmc_ctx_s* c, int token);
 // ---- launchers (each returns hipGetLastError of its launch) ----
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f32(float* p, float v, int64_t n, hipStream_t s);
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
+hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s);
 hipError_t launch_convert_spins(const int32_t* in, int16_t* out, int64_t n, int32_t Q, uint32_t* err,
                                 hipStream_t s);
 hipError_t launch_export_spins(const int16_t* in, int32_t* out, int64_t n, hipStream_t s);
-hipError_t launch_potts_pass(hmc_ctx_s* c, int colour, uint32_t sweep, hmc_trial_record* rec);
+hipError_t launch_potts_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec);
 hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec);
 hipError_t launch_apply_pass(hmc_ctx_s* c, int colour);
 hipError_t launch_reuss(hmc_ctx_s* c);
 hipError_t launch_global_steps(hmc_ctx_s* c, int n_steps);
 hipError_t launch_global_final(hmc_ctx_s* c, bool write_sigma);
-hipError_t launch_unlike_bonds(hmc_ctx_s* c);
-hipError_t launch_texture(hmc_ctx_s* c, int nbins);
 hipError_t launch_zero_wE(hmc_ctx_s* c);
+hipError_t launch_unlike_bonds(hmc_ctx_s* c, int rep);
+hipError_t launch_texture(hmc_ctx_s* c, int rep, int nbins);
 
 }  // namespace hmc

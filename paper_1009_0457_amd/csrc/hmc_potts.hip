@@ -49,33 +49,34 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 __device__ __forceinline__ int wrapi(int a, int K) { return a < 0 ? a + K : (a >= K ? a - K : a); }
 
 struct PassArgs {
-    int16_t* spins;
-    const uint64_t* thr;            // integer thresholds indexed by gb + M
+    int16_t* spins;                 // all replicas, end to end
+    const RepDev* reps;
+    const int32_t* pass_rep;        // block -> replica
+    const uint64_t* thr;            // per replica: 64 integer thresholds indexed by gb + M
     TrialEntry* list;
     uint32_t* list_count;
-    hmc_trial_record* rec;
+    hmc_trial_record* rec;          // indexed by site_off + site, or null
     unsigned long long* stats;
-    int K, Kh, colour, Q, proposal;
-    uint32_t sweep, key0, key1;
-    int64_t n_active;
+    const int64_t* sweep;           // Philox counter word 1 (low 32 bits)
+    int colour;
 };
 
-// Site of thread t within colour `colour`.
+// Site of thread t within colour `colour` of a K^3 lattice.
 template <int M>
-__device__ __forceinline__ void active_site(const PassArgs& a, int64_t t, int& x, int& y, int& z)
+__device__ __forceinline__ void active_site(int K, int Kh, int colour, int64_t t, int& x, int& y, int& z)
 {
     if (M == 26) {
-        const int i = (int)(t % a.Kh);
-        const int j = (int)((t / a.Kh) % a.Kh);
-        const int k = (int)(t / ((int64_t)a.Kh * a.Kh));
-        x = 2 * i + (a.colour & 1);
-        y = 2 * j + ((a.colour >> 1) & 1);
-        z = 2 * k + ((a.colour >> 2) & 1);
+        const int i = (int)(t % Kh);
+        const int j = (int)((t / Kh) % Kh);
+        const int k = (int)(t / ((int64_t)Kh * Kh));
+        x = 2 * i + (colour & 1);
+        y = 2 * j + ((colour >> 1) & 1);
+        z = 2 * k + ((colour >> 2) & 1);
     } else {
-        const int i = (int)(t % a.Kh);
-        y = (int)((t / a.Kh) % a.K);
-        z = (int)(t / ((int64_t)a.Kh * a.K));
-        x = 2 * i + ((y + z + a.colour) & 1);
+        const int i = (int)(t % Kh);
+        y = (int)((t / Kh) % K);
+        z = (int)(t / ((int64_t)Kh * K));
+        x = 2 * i + ((y + z + colour) & 1);
     }
 }
 
@@ -117,29 +118,35 @@ __device__ __forceinline__ void wave_count(unsigned long long* ctr, bool pred)
         atomicAdd(ctr, (unsigned long long)__popcll(mask));
 }
 
-template <int M, bool ELASTIC>
+// One block covers 256 active sites of one replica (the replica is uniform per block).
+template <int M>
 __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = a.pass_rep[blockIdx.x];
+    const RepDev R = a.reps[r];
+    const int64_t t = (int64_t)(blockIdx.x - R.pass_first) * kSiteBlock + threadIdx.x;
+    const int64_t n_active = R.n3 / (M == 26 ? 8 : 2);
+    const bool elastic = R.elastic != 0;
+    int16_t* spins = a.spins + R.site_off;
     bool real = false, accepted = false;
     uint32_t site = 0, r1 = 0;
     int q_new = 0, gb = 0;
-    if (t < a.n_active) {
+    if (t < n_active) {
         int x, y, z;
-        active_site<M>(a, t, x, y, z);
-        const int K = a.K;
+        const int K = R.K;
+        active_site<M>(K, R.Kh, a.colour, t, x, y, z);
         site = (uint32_t)(x + K * (y + K * z));
-        const Philox4 r = philox4x32_10(site, a.sweep, 0u, 0u, a.key0, a.key1);
-        r1 = r.v[1];
-        const int q_old = a.spins[site];
-        if (a.proposal == 0) {
-            const int k = (int)__umulhi(r.v[0], (uint32_t)M);
+        const Philox4 rn = philox4x32_10(site, (uint32_t)(*a.sweep), 0u, 0u, R.key0, R.key1);
+        r1 = rn.v[1];
+        const int q_old = spins[site];
+        if (R.proposal == 0) {
+            const int k = (int)__umulhi(rn.v[0], (uint32_t)M);
             int dx, dy, dz;
             slot_offset<M>(k, dx, dy, dz);
-            q_new = a.spins[wrapi(x + dx, K) + K * (wrapi(y + dy, K) + K * wrapi(z + dz, K))];
+            q_new = spins[wrapi(x + dx, K) + K * (wrapi(y + dy, K) + K * wrapi(z + dz, K))];
         } else {
-            const uint32_t step = __umulhi(r.v[0], (uint32_t)(a.Q - 1));
-            q_new = (int)(((uint32_t)q_old + 1u + step) % (uint32_t)a.Q);
+            const uint32_t step = __umulhi(rn.v[0], (uint32_t)(R.Q - 1));
+            q_new = (int)(((uint32_t)q_old + 1u + step) % (uint32_t)R.Q);
         }
         real = (q_new != q_old);
         if (real) {
@@ -147,10 +154,10 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
             for (int k = 0; k < M; ++k) {
                 int dx, dy, dz;
                 slot_offset<M>(k, dx, dy, dz);
-                const int qn = a.spins[wrapi(x + dx, K) + K * (wrapi(y + dy, K) + K * wrapi(z + dz, K))];
+                const int qn = spins[wrapi(x + dx, K) + K * (wrapi(y + dy, K) + K * wrapi(z + dz, K))];
                 gb += (qn == q_old) - (qn == q_new);
             }
-            if (!ELASTIC) accepted = (uint64_t)r1 < a.thr[gb + M];
+            if (!elastic) accepted = (uint64_t)r1 < a.thr[(int64_t)r * 64 + gb + M];
         }
         if (a.rec) {
             hmc_trial_record rc;
@@ -160,18 +167,18 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
             rc.r1 = r1;
             rc.flags = (real ? 1 : 0) | (accepted ? 2 : 0);
             rc.reserved = 0;
-            a.rec[site] = rc;
+            a.rec[R.site_off + site] = rc;
         }
         // same-colour sites are never neighbours: nothing else in this pass reads `site`
-        if (!ELASTIC && accepted) a.spins[site] = (int16_t)q_new;
+        if (accepted) spins[site] = (int16_t)q_new;
     }
-    // wave-collective tail, reached by every lane of the wave
-    if (ELASTIC) {
+    // wave-collective tail, reached by every lane of the wave (replica uniform per block)
+    if (elastic) {
         const uint32_t slot = wave_append(a.list_count, real);
         if (real) {
             TrialEntry e;
             e.site = site;
-            e.q_new = q_new;
+            e.qr = (uint32_t)q_new | ((uint32_t)r << 16);
             e.gb = gb;
             e.r1 = r1;
             a.list[slot] = e;
@@ -183,12 +190,25 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
 }
 
 // Deferred update of an elastic pass: every accepted entry writes its new state.
-__global__ __launch_bounds__(256) void k_apply(int16_t* spins, const TrialEntry* list, const uint8_t* acc,
-                                               const uint32_t* count)
+__global__ __launch_bounds__(256) void k_apply(int16_t* spins, const RepDev* reps, const TrialEntry* list,
+                                               const uint8_t* acc, const uint32_t* count)
 {
     const uint32_t n = *count;
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x)
-        if (acc[e]) spins[list[e].site] = (int16_t)list[e].q_new;
+        if (acc[e]) {
+            const TrialEntry t = list[e];
+            spins[reps[t.qr >> 16].site_off + t.site] = (int16_t)(t.qr & 0xffffu);
+        }
+}
+
+__global__ void k_set_i64(int64_t* p, int64_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+__global__ void k_add_i64(int64_t* p, int64_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p += v;
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n)
@@ -254,34 +274,35 @@ hipError_t launch_export_spins(const int16_t* in, int32_t* out, int64_t n, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_potts_pass(hmc_ctx_s* c, int colour, uint32_t sweep, hmc_trial_record* rec)
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, s, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_i64, dim3(1), dim3(64), 0, s, p, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_potts_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
 {
     PassArgs a;
     a.spins = c->d.spins;
+    a.reps = c->d.reps;
+    a.pass_rep = c->d.pass_rep;
     a.thr = c->d.thr;
     a.list = c->d.list;
     a.list_count = c->d.counters + kListCount + colour;
     a.rec = rec;
     a.stats = c->d.stats;
-    a.K = c->p.K;
-    a.Kh = c->p.K / 2;
+    a.sweep = c->d.sweep;
     a.colour = colour;
-    a.Q = c->Q;
-    a.proposal = c->p.proposal;
-    a.sweep = sweep;
-    a.key0 = (uint32_t)(c->p.seed & 0xffffffffu);
-    a.key1 = (uint32_t)(c->p.seed >> 32);
-    a.n_active = c->n3 / c->colours;
-    const bool el = c->elastic_buffers && c->load_nonzero;
-    const dim3 grid(grid_for(a.n_active, 256, 0x7fffffffu)), block(256);
+    const dim3 grid((unsigned)c->pass_blocks), block(kSiteBlock);
     const int tok = prof_begin(c, kProfPotts);
-    if (c->p.neighbors == 26) {
-        if (el) hipLaunchKernelGGL((k_potts_pass<26, true>), grid, block, 0, c->stream, a);
-        else hipLaunchKernelGGL((k_potts_pass<26, false>), grid, block, 0, c->stream, a);
-    } else {
-        if (el) hipLaunchKernelGGL((k_potts_pass<6, true>), grid, block, 0, c->stream, a);
-        else hipLaunchKernelGGL((k_potts_pass<6, false>), grid, block, 0, c->stream, a);
-    }
+    if (c->p.neighbors == 26) hipLaunchKernelGGL(k_potts_pass<26>, grid, block, 0, c->stream, a);
+    else hipLaunchKernelGGL(k_potts_pass<6>, grid, block, 0, c->stream, a);
     prof_end(c, tok);
     return hipGetLastError();
 }
@@ -290,7 +311,7 @@ hipError_t launch_apply_pass(hmc_ctx_s* c, int colour)
 {
     const unsigned g = grid_for(c->max_list, 256, 2048);
     const int tok = prof_begin(c, kProfApply);
-    hipLaunchKernelGGL(k_apply, dim3(g), dim3(256), 0, c->stream, c->d.spins, c->d.list, c->d.accept,
+    hipLaunchKernelGGL(k_apply, dim3(g), dim3(256), 0, c->stream, c->d.spins, c->d.reps, c->d.list, c->d.accept,
                        c->d.counters + kListCount + colour);
     prof_end(c, tok);
     return hipGetLastError();

@@ -23,21 +23,45 @@
 namespace hmc {
 
 struct ZoneArgs {
-    const int16_t* spins;
+    const int16_t* spins;           // all replicas, end to end
     const float* Ctab;
     const float* Stab;
-    const float* sigma;
+    const float* sigma;             // 6 planes of `plane` floats
+    const RepDev* reps;
     const TrialEntry* list;
     const uint32_t* count;
     uint8_t* acc;
-    hmc_trial_record* rec;
+    hmc_trial_record* rec;          // indexed by site_off + site, or null
     unsigned long long* stats;
-    int K;
     int nr;
-    int64_t n3;
+    int64_t plane;
     float alpha, beta;
+};
+
+// The trial's replica, its lattice, grain tables and decision constants.
+struct TrialCtx {
+    const int16_t* spins;
+    const float* Ctab;
+    const float* Stab;
+    int64_t site_off;
+    int K;
     double J, kT, lambda;
 };
+
+__device__ __forceinline__ TrialCtx trial_ctx(const ZoneArgs& a, uint32_t qr)
+{
+    const RepDev& R = a.reps[qr >> 16];
+    TrialCtx c;
+    c.spins = a.spins + R.site_off;
+    c.Ctab = a.Ctab + R.grain_off * kTab;
+    c.Stab = a.Stab + R.grain_off * kTab;
+    c.site_off = R.site_off;
+    c.K = R.K;
+    c.J = R.J;
+    c.kT = R.kT;
+    c.lambda = R.lambda;
+    return c;
+}
 
 __device__ __forceinline__ void load_sym(const float* __restrict__ t, float c[21])
 {
@@ -92,27 +116,28 @@ __global__ __launch_bounds__(64) void k_zone(ZoneArgs a)
 
     const int lane = threadIdx.x;
     const uint32_t count = *a.count;
-    const int K = a.K;
 
     for (uint32_t e = blockIdx.x; e < count; e += gridDim.x) {
         const TrialEntry ent = a.list[e];
+        const TrialCtx tc = trial_ctx(a, ent.qr);
+        const int K = tc.K;
         const int px = (int)(ent.site % (uint32_t)K);
         const int py = (int)((ent.site / (uint32_t)K) % (uint32_t)K);
         const int pz = (int)(ent.site / ((uint32_t)K * (uint32_t)K));
-        const int q_old = a.spins[ent.site];
-        const int q_new = ent.q_new;
+        const int q_old = tc.spins[ent.site];
+        const int q_new = (int)(ent.qr & 0xffffu);
 
         // centre: eps_p = S_old sigma_p, t = (C_new - C_old) eps_p
         float sp[6], eps[6], t[6];
         {
             float c[21], s[6];
 #pragma unroll
-            for (int I = 0; I < 6; ++I) sp[I] = a.sigma[(int64_t)I * a.n3 + ent.site];
-            load_sym(a.Stab + (int64_t)q_old * kTab, c);
+            for (int I = 0; I < 6; ++I) sp[I] = a.sigma[(int64_t)I * a.plane + tc.site_off + ent.site];
+            load_sym(tc.Stab + (int64_t)q_old * kTab, c);
             symv(c, sp, eps);
-            load_sym(a.Ctab + (int64_t)q_new * kTab, c);
+            load_sym(tc.Ctab + (int64_t)q_new * kTab, c);
             symv(c, eps, t);
-            load_sym(a.Ctab + (int64_t)q_old * kTab, c);
+            load_sym(tc.Ctab + (int64_t)q_old * kTab, c);
             symv(c, eps, s);
 #pragma unroll
             for (int I = 0; I < 6; ++I) t[I] -= s[I];
@@ -133,9 +158,9 @@ __global__ __launch_bounds__(64) void k_zone(ZoneArgs a)
                     gx = (gx % K + K) % K;
                     gy = (gy % K + K) % K;
                     gz = (gz % K + K) % K;
-                    g = a.spins[gx + K * (gy + K * gz)];
+                    g = tc.spins[gx + K * (gy + K * gz)];
                 }
-                load_sym(a.Ctab + (int64_t)g * kTab, Cv[m]);
+                load_sym(tc.Ctab + (int64_t)g * kTab, Cv[m]);
             }
         }
 
@@ -239,17 +264,283 @@ __global__ __launch_bounds__(64) void k_zone(ZoneArgs a)
 #pragma unroll
             for (int I = 0; I < 6; ++I) base += 0.5 * (double)eps[I] * (double)t[I];
             const double dPi = base + part;
-            const double dE = a.J * (double)ent.gb + a.lambda * dPi;
-            const bool accept = (dE <= 0.0) || ((double)ent.r1 < ldexp(exp(-dE / a.kT), 32));
+            const double dE = tc.J * (double)ent.gb + tc.lambda * dPi;
+            const bool accept = (dE <= 0.0) || ((double)ent.r1 < ldexp(exp(-dE / tc.kT), 32));
             a.acc[e] = accept ? 1 : 0;
             if (a.rec) {
-                a.rec[ent.site].dPi = (float)dPi;
-                a.rec[ent.site].flags = 1 | 4 | (accept ? 2 : 0);
+                a.rec[tc.site_off + ent.site].dPi = (float)dPi;
+                a.rec[tc.site_off + ent.site].flags = 1 | 4 | (accept ? 2 : 0);
             }
             atomicAdd(&a.stats[kStatSolves], 1ull);
             if (accept) atomicAdd(&a.stats[kStatAccepted], 1ull);
         }
         __syncthreads();   // LDS is reused by the next trial
+    }
+}
+
+
+// ------------------------------------------------------------------------------------
+// Column variant.  A work-group of 256 lanes holds Z = 256 / (2h+2)^2 trials at once.
+// Within a trial, lane (cx, cy) owns the z-column of (2h+2) nodes at (cx, cy) and, when
+// cx, cy < 2h+1, the z-column of (2h+1) voxels whose lowest corner column it is.  The
+// strain of a voxel needs the node columns (cx, cy), (cx+1, cy), (cx, cy+1), (cx+1, cy+1):
+// per node layer the lane forms the x-difference, y-difference and sum of those four
+// nodes, and two consecutive layers give the voxel's nine displacement gradients (all
+// with the factor 1/4 left out).  The corner forces are the transpose: per node layer the
+// lane sums its voxels' stress rows over the two voxels sharing the layer and splits the
+// result into its four node columns; its own column stays in registers, the other three
+// go through LDS to their owners.  Two barriers per step: after the displacements are
+// published and after the forces are.
+//
+// Scaling: with B = B'/4, sigma'' = C (B' du) + 4 t = 4 (C B du + t) and the true
+// gradient is B'^T sigma'' / 16, so the step uses alpha / 16.
+// ------------------------------------------------------------------------------------
+template <int H>
+__global__ __launch_bounds__(256, 2) void k_zone_col(ZoneArgs a)
+{
+    constexpr int N = 2 * H + 1, NN = 2 * H + 2, NC = NN * NN;
+    constexpr int Z = 256 / NC;
+    static_assert(Z >= 1, "zone too large for one work-group");
+
+    __shared__ float s_u[Z][3][NN][NC];          // node displacements
+    __shared__ float s_f[3][Z][3][NN][NC];       // force contributions: from (x-1,y), (x,y-1), (x-1,y-1)
+    __shared__ double s_red[256];
+    __shared__ float s_ctr[Z][12];               // per trial: eps_p[6], t[6]
+
+    const int t = threadIdx.x;
+    const int zs = t / NC;
+    const int col = t - zs * NC;
+    const int cx = col % NN, cy = col / NN;
+    const bool in_zone = zs < Z;
+    const bool vox = in_zone && cx < N && cy < N;
+    const bool centre_col = vox && cx == H && cy == H;
+    const int zsafe = in_zone ? zs : 0;
+    const uint32_t count = *a.count;
+    const float alpha16 = a.alpha * 0.0625f, beta = a.beta;
+
+    for (uint32_t base = blockIdx.x * (uint32_t)Z; base < count; base += gridDim.x * (uint32_t)Z) {
+        const uint32_t e = base + (uint32_t)zsafe;
+        const bool active = in_zone && e < count;
+
+        TrialEntry ent{0u, 0u, 0, 0u};
+        TrialCtx tc{};
+        float Cv[N][21];
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+#pragma unroll
+            for (int i = 0; i < 21; ++i) Cv[k][i] = 0.f;
+        if (active) {
+            ent = a.list[e];
+            tc = trial_ctx(a, ent.qr);
+            const int K = tc.K;
+            const int q_new = (int)(ent.qr & 0xffffu);
+            const int px = (int)(ent.site % (uint32_t)K);
+            const int py = (int)((ent.site / (uint32_t)K) % (uint32_t)K);
+            const int pz = (int)(ent.site / ((uint32_t)K * (uint32_t)K));
+            if (col == 0) {
+                // eps_p = S_old sigma_p, t = (C_new - C_old) eps_p, shared through LDS
+                const int q_old = tc.spins[ent.site];
+                float c[21], sp[6], s[6], eps[6], tt[6];
+#pragma unroll
+                for (int I = 0; I < 6; ++I) sp[I] = a.sigma[(int64_t)I * a.plane + tc.site_off + ent.site];
+                load_sym(tc.Stab + (int64_t)q_old * kTab, c);
+                symv(c, sp, eps);
+                load_sym(tc.Ctab + (int64_t)q_new * kTab, c);
+                symv(c, eps, tt);
+                load_sym(tc.Ctab + (int64_t)q_old * kTab, c);
+                symv(c, eps, s);
+#pragma unroll
+                for (int I = 0; I < 6; ++I) {
+                    s_ctr[zs][I] = eps[I];
+                    s_ctr[zs][6 + I] = tt[I] - s[I];
+                }
+            }
+            if (vox) {
+                const int gx = ((px + cx - H) % K + K) % K, gy = ((py + cy - H) % K + K) % K;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const int gz = ((pz + k - H) % K + K) % K;
+                    const int g = (centre_col && k == H) ? q_new : (int)tc.spins[gx + K * (gy + K * gz)];
+                    load_sym(tc.Ctab + (int64_t)g * kTab, Cv[k]);
+                }
+            }
+        }
+        float du[NN][3], w[NN][3];
+#pragma unroll
+        for (int z = 0; z < NN; ++z)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                du[z][j] = 0.f;
+                w[z][j] = 0.f;
+                if (in_zone) {
+                    s_u[zs][j][z][col] = 0.f;
+                    s_f[0][zs][j][z][col] = 0.f;
+                    s_f[1][zs][j][z][col] = 0.f;
+                    s_f[2][zs][j][z][col] = 0.f;
+                }
+            }
+        __syncthreads();
+
+        const int cE = col + 1, cN = col + NN, cNE = col + NN + 1;
+        for (int step = 0; step < a.nr; ++step) {
+            // ---- voxels: strain, stress, corner forces ----
+            float fo[NN][3];
+            if (vox && active) {
+                float Lp[3][3];     // previous node layer: (dx, dy, sum) x comp
+                float Pp[3] = {0.f, 0.f, 0.f}, Qp[3] = {0.f, 0.f, 0.f}, Rp[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                for (int z = 0; z < NN; ++z) {
+                    float Lc[3][3];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const float ua = du[z][j];
+                        const float ub = s_u[zs][j][z][cE];
+                        const float uc = s_u[zs][j][z][cN];
+                        const float ud = s_u[zs][j][z][cNE];
+                        const float s1 = ua + ub, s2 = uc + ud, d1 = ub - ua, d2 = ud - uc;
+                        Lc[0][j] = d1 + d2;   // x-difference
+                        Lc[1][j] = s2 - s1;   // y-difference
+                        Lc[2][j] = s1 + s2;   // sum
+                    }
+                    float P[3] = {0.f, 0.f, 0.f}, Q[3] = {0.f, 0.f, 0.f}, R[3] = {0.f, 0.f, 0.f};
+                    if (z >= 1) {
+                        const int k = z - 1;   // voxel between layers z-1 and z
+                        float g[3][3];
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            g[j][0] = Lp[0][j] + Lc[0][j];
+                            g[j][1] = Lp[1][j] + Lc[1][j];
+                            g[j][2] = Lc[2][j] - Lp[2][j];
+                        }
+                        const float ev[6] = {g[0][0], g[1][1], g[2][2], g[1][2] + g[2][1], g[0][2] + g[2][0],
+                                             g[0][1] + g[1][0]};
+                        float sv[6];
+                        symv(Cv[k], ev, sv);
+                        if (centre_col && k == H) {
+#pragma unroll
+                            for (int I = 0; I < 6; ++I) sv[I] += 4.f * s_ctr[zs][6 + I];
+                        }
+                        P[0] = sv[0]; P[1] = sv[5]; P[2] = sv[4];
+                        Q[0] = sv[5]; Q[1] = sv[1]; Q[2] = sv[3];
+                        R[0] = sv[4]; R[1] = sv[3]; R[2] = sv[2];
+                        // node layer k collects voxel k-1 (its upper corners) and voxel k (lower)
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            const float PL = Pp[j] + P[j], QL = Qp[j] + Q[j], RL = Rp[j] - R[j];
+                            const float U = QL + RL, V = RL - QL;
+                            fo[k][j] = V - PL;
+                            s_f[0][zs][j][k][cE] = PL + V;
+                            s_f[1][zs][j][k][cN] = U - PL;
+                            s_f[2][zs][j][k][cNE] = PL + U;
+                            Pp[j] = P[j];
+                            Qp[j] = Q[j];
+                            Rp[j] = R[j];
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+#pragma unroll
+                        for (int r = 0; r < 3; ++r) Lp[r][j] = Lc[r][j];
+                }
+                // top node layer: only voxel N-1 below it
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const float PL = Pp[j], QL = Qp[j], RL = Rp[j];
+                    const float U = QL + RL, V = RL - QL;
+                    fo[NN - 1][j] = V - PL;
+                    s_f[0][zs][j][NN - 1][cE] = PL + V;
+                    s_f[1][zs][j][NN - 1][cN] = U - PL;
+                    s_f[2][zs][j][NN - 1][cNE] = PL + U;
+                }
+            } else {
+#pragma unroll
+                for (int z = 0; z < NN; ++z)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) fo[z][j] = 0.f;
+            }
+            __syncthreads();
+            // ---- nodes: gather forces, heavy-ball step, publish displacement ----
+            if (active) {
+#pragma unroll
+                for (int z = 0; z < NN; ++z)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const float f = ((fo[z][j] + s_f[0][zs][j][z][col]) + s_f[1][zs][j][z][col]) +
+                                        s_f[2][zs][j][z][col];
+                        w[z][j] = beta * w[z][j] - alpha16 * f;
+                        du[z][j] += w[z][j];
+                        s_u[zs][j][z][col] = du[z][j];
+                    }
+            }
+            __syncthreads();
+        }
+
+        // ---- energy at the final displacement: 1/2 e.C e over the zone + t.e at the centre ----
+        double part = 0.0;
+        if (vox && active) {
+            float Lp[3][3];
+#pragma unroll
+            for (int z = 0; z < NN; ++z) {
+                float Lc[3][3];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const float ua = du[z][j];
+                    const float ub = s_u[zs][j][z][cE];
+                    const float uc = s_u[zs][j][z][cN];
+                    const float ud = s_u[zs][j][z][cNE];
+                    const float s1 = ua + ub, s2 = uc + ud, d1 = ub - ua, d2 = ud - uc;
+                    Lc[0][j] = d1 + d2;
+                    Lc[1][j] = s2 - s1;
+                    Lc[2][j] = s1 + s2;
+                }
+                if (z >= 1) {
+                    const int k = z - 1;
+                    float g[3][3];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        g[j][0] = 0.25f * (Lp[0][j] + Lc[0][j]);
+                        g[j][1] = 0.25f * (Lp[1][j] + Lc[1][j]);
+                        g[j][2] = 0.25f * (Lc[2][j] - Lp[2][j]);
+                    }
+                    const float ev[6] = {g[0][0], g[1][1], g[2][2], g[1][2] + g[2][1], g[0][2] + g[2][0],
+                                         g[0][1] + g[1][0]};
+                    float sv[6];
+                    symv(Cv[k], ev, sv);
+                    double d = 0.0;
+#pragma unroll
+                    for (int I = 0; I < 6; ++I) d += 0.5 * (double)ev[I] * (double)sv[I];
+                    if (centre_col && k == H) {
+#pragma unroll
+                        for (int I = 0; I < 6; ++I) d += (double)s_ctr[zs][6 + I] * (double)ev[I];
+                    }
+                    part += d;
+                }
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) Lp[r][j] = Lc[r][j];
+            }
+        }
+        s_red[t] = part;
+        __syncthreads();
+        if (active && col == 0) {
+            double sum = 0.0;
+            for (int i = 0; i < NC; ++i) sum += s_red[zs * NC + i];
+            double base_e = 0.0;
+#pragma unroll
+            for (int I = 0; I < 6; ++I) base_e += 0.5 * (double)s_ctr[zs][I] * (double)s_ctr[zs][6 + I];
+            const double dPi = base_e + sum;
+            const double dE = tc.J * (double)ent.gb + tc.lambda * dPi;
+            const bool accept = (dE <= 0.0) || ((double)ent.r1 < ldexp(exp(-dE / tc.kT), 32));
+            a.acc[e] = accept ? 1 : 0;
+            if (a.rec) {
+                a.rec[tc.site_off + ent.site].dPi = (float)dPi;
+                a.rec[tc.site_off + ent.site].flags = 1 | 4 | (accept ? 2 : 0);
+            }
+            atomicAdd(&a.stats[kStatSolves], 1ull);
+            if (accept) atomicAdd(&a.stats[kStatAccepted], 1ull);
+        }
+        __syncthreads();   // LDS is reused by the next group of trials
     }
 }
 
@@ -260,30 +551,46 @@ hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
     a.Ctab = c->d.Ctab;
     a.Stab = c->d.Stab;
     a.sigma = c->d.sigma;
+    a.reps = c->d.reps;
     a.list = c->d.list;
     a.count = c->d.counters + kListCount + colour;
     a.acc = c->d.accept;
     a.rec = rec;
     a.stats = c->d.stats;
-    a.K = c->p.K;
     a.nr = c->p.zone_steps;
-    a.n3 = c->n3;
+    a.plane = c->total_sites;
     a.alpha = (float)c->p.zone_alpha;
     a.beta = (float)c->p.zone_beta;
-    a.J = c->p.J;
-    a.kT = c->p.kT;
-    a.lambda = c->p.lambda_el;
-    int64_t g = c->max_list;
-    if (g > 256 * 40) g = 256 * 40;
-    if (g < 1) g = 1;
-    const dim3 grid((unsigned)g), block(64);
+    const int h = c->p.zone_h;
+    // column variant for h <= 2 unless the wavefront-per-trial variant is asked for
+    const bool column = (c->p.zone_variant == 0 && h <= 2) || (c->p.zone_variant == 2 && h <= 2);
     const int tok = prof_begin(c, kProfZone);
-    switch (c->p.zone_h) {
-        case 0: hipLaunchKernelGGL(k_zone<0>, grid, block, 0, c->stream, a); break;
-        case 1: hipLaunchKernelGGL(k_zone<1>, grid, block, 0, c->stream, a); break;
-        case 2: hipLaunchKernelGGL(k_zone<2>, grid, block, 0, c->stream, a); break;
-        case 3: hipLaunchKernelGGL(k_zone<3>, grid, block, 0, c->stream, a); break;
-        default: return hipErrorInvalidValue;
+    if (column) {
+        const int nn = 2 * h + 2, per_wg = 256 / (nn * nn);
+        int64_t g = (c->max_list + per_wg - 1) / per_wg;
+        const int64_t cap = 256 * 2 * 4;   // a few resident work-groups per CU
+        if (g > cap) g = cap;
+        if (g < 1) g = 1;
+        const dim3 grid((unsigned)g), block(256);
+        switch (h) {
+            case 0: hipLaunchKernelGGL(k_zone_col<0>, grid, block, 0, c->stream, a); break;
+            case 1: hipLaunchKernelGGL(k_zone_col<1>, grid, block, 0, c->stream, a); break;
+            case 2: hipLaunchKernelGGL(k_zone_col<2>, grid, block, 0, c->stream, a); break;
+            default: return hipErrorInvalidValue;   // h = 3 does not fit two work-groups per CU
+
+        }
+    } else {
+        int64_t g = c->max_list;
+        if (g > 256 * 40) g = 256 * 40;
+        if (g < 1) g = 1;
+        const dim3 grid((unsigned)g), block(64);
+        switch (h) {
+            case 0: hipLaunchKernelGGL(k_zone<0>, grid, block, 0, c->stream, a); break;
+            case 1: hipLaunchKernelGGL(k_zone<1>, grid, block, 0, c->stream, a); break;
+            case 2: hipLaunchKernelGGL(k_zone<2>, grid, block, 0, c->stream, a); break;
+            case 3: hipLaunchKernelGGL(k_zone<3>, grid, block, 0, c->stream, a); break;
+            default: return hipErrorInvalidValue;
+        }
     }
     prof_end(c, tok);
     return hipGetLastError();

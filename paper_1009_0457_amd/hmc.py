@@ -29,7 +29,7 @@ class HmcError(RuntimeError):
 class hmc_params(C.Structure):
     _fields_ = [("K", C.c_int32), ("neighbors", C.c_int32), ("proposal", C.c_int32), ("zone_h", C.c_int32),
                 ("zone_steps", C.c_int32), ("refresh_every", C.c_int32), ("refresh_steps", C.c_int32),
-                ("cold_steps", C.c_int32),
+                ("cold_steps", C.c_int32), ("zone_variant", C.c_int32), ("reserved0", C.c_int32),
                 ("J", C.c_double), ("kT", C.c_double), ("C11", C.c_double), ("C12", C.c_double),
                 ("C44", C.c_double), ("lambda_el", C.c_double), ("zone_alpha", C.c_double),
                 ("zone_beta", C.c_double), ("glob_alpha", C.c_double), ("glob_beta", C.c_double),
@@ -46,6 +46,12 @@ class hmc_kernel_time(C.Structure):
 class hmc_kernel_times(C.Structure):
     _fields_ = [("potts", hmc_kernel_time), ("zone", hmc_kernel_time), ("apply", hmc_kernel_time),
                 ("refresh_step", hmc_kernel_time), ("refresh_other", hmc_kernel_time)]
+
+
+class hmc_replica(C.Structure):
+    _fields_ = [("K", C.c_int32), ("Q", C.c_int32), ("kT", C.c_double), ("lambda_el", C.c_double),
+                ("glob_alpha", C.c_double), ("glob_beta", C.c_double), ("glob_alphaE", C.c_double),
+                ("sigma_MPa", C.c_double * 6), ("seed", C.c_uint64)]
 
 
 class hmc_stats(C.Structure):
@@ -87,8 +93,25 @@ _SIGS = [
     ("hmc_reset_stats", C.c_int, [C.c_void_p]),
     ("hmc_set_profiling", C.c_int, [C.c_void_p, C.c_int32]),
     ("hmc_get_kernel_times", C.c_int, [C.c_void_p, C.POINTER(hmc_kernel_times)]),
+    ("hmc_set_graphs", C.c_int, [C.c_void_p, C.c_int32]),
+    ("hmc_default_replica", C.c_int, [C.POINTER(hmc_replica), C.POINTER(hmc_params), C.c_int32, C.c_int32]),
+    ("hmc_batch_workspace_bytes", C.c_size_t, [C.POINTER(hmc_params), C.c_int32, C.POINTER(hmc_replica)]),
+    ("hmc_batch_create", C.c_int, [C.POINTER(hmc_params), C.c_int32, C.POINTER(hmc_replica), C.c_void_p,
+                                   C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("hmc_batch_set_replica", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    ("hmc_batch_get_spins", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    ("hmc_batch_get_stress", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    ("hmc_batch_energy", C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    ("hmc_batch_texture_histogram", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_int32,
+                                              C.c_void_p]),
+    ("hmc_adjoint_workspace_bytes", C.c_size_t, [C.c_void_p, C.c_int32, C.c_int32]),
+    ("hmc_elastic_forward", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t,
+                                      C.POINTER(C.c_double)]),
+    ("hmc_elastic_backward", C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_double, C.c_void_p, C.c_void_p]),
     ("hmc_grain_tables", C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_void_p,
                                    C.c_void_p]),
+    ("hmc_grain_table_derivatives", C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                              C.c_void_p, C.c_void_p]),
 ]
 
 
@@ -249,6 +272,62 @@ def hmc_get_kernel_times(ctx) -> dict:
             for k, _ in kt._fields_}
 
 
+def hmc_set_graphs(ctx, enable):
+    _check(lib().hmc_set_graphs(ctx, int(bool(enable))), ctx)
+
+
+def hmc_default_replica(common: hmc_params, K, Q) -> hmc_replica:
+    r = hmc_replica()
+    _check(lib().hmc_default_replica(C.byref(r), C.byref(common), K, Q))
+    return r
+
+
+def _rep_array(reps):
+    arr = (hmc_replica * len(reps))()
+    for i, r in enumerate(reps):
+        arr[i] = r
+    return arr
+
+
+def hmc_batch_workspace_bytes(common: hmc_params, reps) -> int:
+    return int(lib().hmc_batch_workspace_bytes(C.byref(common), len(reps), _rep_array(reps)))
+
+
+def hmc_batch_create(common: hmc_params, reps, workspace, stream_handle: int):
+    ctx = C.c_void_p()
+    _check(lib().hmc_batch_create(C.byref(common), len(reps), _rep_array(reps), _ptr(workspace), workspace.numel(),
+                                  C.c_void_p(stream_handle), C.byref(ctx)))
+    return ctx
+
+
+def hmc_batch_set_replica(ctx, r, euler, spins_dev):
+    e = np.ascontiguousarray(euler, np.float64)
+    _check(lib().hmc_batch_set_replica(ctx, int(r), e.ctypes.data_as(C.c_void_p), _ptr(spins_dev)), ctx)
+
+
+def hmc_batch_get_spins(ctx, r, out_dev):
+    _check(lib().hmc_batch_get_spins(ctx, int(r), _ptr(out_dev)), ctx)
+
+
+def hmc_batch_get_stress(ctx, r, out_dev):
+    _check(lib().hmc_batch_get_stress(ctx, int(r), _ptr(out_dev)), ctx)
+
+
+def hmc_batch_energy(ctx, r):
+    n = C.c_int64()
+    u = C.c_double()
+    _check(lib().hmc_batch_energy(ctx, int(r), C.byref(n), C.byref(u)), ctx)
+    return int(n.value), float(u.value)
+
+
+def hmc_batch_texture_histogram(ctx, r, axis, bin_deg=10.0, nbins=6):
+    a = np.ascontiguousarray(axis, np.float64)
+    out = np.zeros(nbins, np.int64)
+    _check(lib().hmc_batch_texture_histogram(ctx, int(r), a.ctypes.data_as(C.c_void_p), float(bin_deg), int(nbins),
+                                             out.ctypes.data_as(C.c_void_p)), ctx)
+    return out
+
+
 def hmc_grain_tables(euler, C11, C12, C44):
     e = np.ascontiguousarray(euler, np.float64)
     Q = e.shape[0]
@@ -257,6 +336,35 @@ def hmc_grain_tables(euler, C11, C12, C44):
     _check(lib().hmc_grain_tables(e.ctypes.data_as(C.c_void_p), Q, C11, C12, C44,
                                   Cl.ctypes.data_as(C.c_void_p), Sl.ctypes.data_as(C.c_void_p)))
     return Cl, Sl
+
+
+def hmc_adjoint_workspace_bytes(ctx, n_steps, ckpt_every) -> int:
+    return int(lib().hmc_adjoint_workspace_bytes(ctx, int(n_steps), int(ckpt_every)))
+
+
+def hmc_elastic_forward(ctx, n_steps, ckpt_every, adj_ws):
+    U = C.c_double()
+    _check(lib().hmc_elastic_forward(ctx, int(n_steps), int(ckpt_every), _ptr(adj_ws), adj_ws.numel(), C.byref(U)),
+           ctx)
+    return float(U.value)
+
+
+def hmc_elastic_backward(ctx, adj_ws, dU, Q):
+    ge = np.zeros((Q, 3))
+    gs = np.zeros(6)
+    _check(lib().hmc_elastic_backward(ctx, _ptr(adj_ws), adj_ws.numel(), float(dU), ge.ctypes.data_as(C.c_void_p),
+                                      gs.ctypes.data_as(C.c_void_p)), ctx)
+    return ge, gs
+
+
+def hmc_grain_table_derivatives(euler, C11, C12, C44):
+    e = np.ascontiguousarray(euler, np.float64)
+    Q = e.shape[0]
+    dC = np.zeros((Q, 3, 6, 6))
+    dS = np.zeros((Q, 3, 6, 6))
+    _check(lib().hmc_grain_table_derivatives(e.ctypes.data_as(C.c_void_p), Q, C11, C12, C44,
+                                             dC.ctypes.data_as(C.c_void_p), dS.ctypes.data_as(C.c_void_p)))
+    return dC, dS
 
 
 # ---- convenience owner ------------------------------------------------------------------
@@ -381,3 +489,116 @@ class Lattice:
 
     def kernel_times(self):
         return hmc_get_kernel_times(self.ctx)
+
+    def set_graphs(self, enable=True):
+        hmc_set_graphs(self.ctx, enable)
+
+    # adjoint of the global solve
+    def elastic_forward(self, n_steps, ckpt_every=50):
+        nbytes = hmc_adjoint_workspace_bytes(self.ctx, n_steps, ckpt_every)
+        if getattr(self, "adj_ws", None) is None or self.adj_ws.numel() < nbytes:
+            self.adj_ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+        return hmc_elastic_forward(self.ctx, n_steps, ckpt_every, self.adj_ws)
+
+    def elastic_backward(self, dU=1.0):
+        return hmc_elastic_backward(self.ctx, self.adj_ws, dU, self.Q)
+
+
+def _make_energy_function():
+    import torch
+
+    class StoredElasticEnergy(torch.autograd.Function):
+        """U(euler, sigma_MPa): stored elastic energy (GPa*voxel) after the global explicit
+        solve of ``n_steps`` from a cold start on ``lattice`` (its spins); the backward is the
+        library's hand-written adjoint with checkpoints every ``ckpt_every`` steps."""
+
+        @staticmethod
+        def forward(ctx, euler, sigma_MPa, lattice, n_steps, ckpt_every):
+            lattice.set_orientations(euler.detach().cpu().double().numpy())
+            lattice.set_load(sigma_MPa.detach().cpu().double().numpy())
+            U = lattice.elastic_forward(int(n_steps), int(ckpt_every))
+            ctx.lattice = lattice
+            ctx.shapes = (euler.shape, euler.dtype, sigma_MPa.dtype, euler.device, sigma_MPa.device)
+            return torch.tensor(U, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gU):
+            shape, edt, sdt, edev, sdev = ctx.shapes
+            ge, gs = ctx.lattice.elastic_backward(float(gU))
+            return (torch.from_numpy(ge).reshape(shape).to(dtype=edt, device=edev),
+                    torch.from_numpy(gs).to(dtype=sdt, device=sdev), None, None, None)
+
+    return StoredElasticEnergy
+
+
+_energy_fn = None
+
+
+def stored_elastic_energy(euler, sigma_MPa, lattice, n_steps=2000, ckpt_every=50):
+    """Differentiable stored elastic energy; ``euler`` (Q, 3) and ``sigma_MPa`` (6,) tensors."""
+    global _energy_fn
+    if _energy_fn is None:
+        _energy_fn = _make_energy_function()
+    return _energy_fn.apply(euler, sigma_MPa, lattice, n_steps, ckpt_every)
+
+
+def orientation_driving_force(lattice, euler, sigma_MPa, n_steps=2000, ckpt_every=50):
+    """-dU/dtheta per grain (Q, 3): the elastic driving force on each grain's orientation, the
+    term the texture rate equation of Sec. 7 is driven by (rotating a grain along it lowers
+    the stored energy)."""
+    lattice.set_orientations(np.asarray(euler, np.float64))
+    lattice.set_load(np.asarray(sigma_MPa, np.float64))
+    lattice.elastic_forward(n_steps, ckpt_every)
+    ge, _ = lattice.elastic_backward(1.0)
+    return -ge
+
+
+class Batch(Lattice):
+    """Many replicas fused into every launch (one context).  ``reps`` is a list of
+    hmc_replica; ``common`` an hmc_params.  Runs on its own (non-null) torch stream so that
+    sweeps can be captured into HIP graphs."""
+
+    def __init__(self, common, reps, device="cuda:0", stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HMC library needs a HIP device; none is visible")
+        self.torch = torch
+        self.device = torch.device(device)
+        self.params = common
+        self.reps = list(reps)
+        self.n3s = [r.K ** 3 for r in self.reps]
+        nbytes = hmc_batch_workspace_bytes(common, self.reps)
+        if nbytes == 0:
+            raise HmcError(HMC_EINVAL, "invalid batch description")
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            torch.cuda.synchronize(self.device)
+            self.ctx = hmc_batch_create(common, self.reps, self.workspace, self.stream.cuda_stream)
+
+    def set_replica(self, r, euler, spins):
+        t = self.torch.as_tensor(np.asarray(spins, np.int32)).to(self.device)
+        self.torch.cuda.synchronize(self.device)
+        hmc_batch_set_replica(self.ctx, r, euler, t)
+
+    def get_spins(self, r=0):
+        out = self.torch.empty(self.n3s[r], dtype=self.torch.int32, device=self.device)
+        hmc_batch_get_spins(self.ctx, r, out)
+        self.stream.synchronize()
+        return out
+
+    def get_stress(self, r=0):
+        out = self.torch.empty((6, self.n3s[r]), dtype=self.torch.float32, device=self.device)
+        hmc_batch_get_stress(self.ctx, r, out)
+        self.stream.synchronize()
+        return out
+
+    def energy(self, r=0):
+        return hmc_batch_energy(self.ctx, r)
+
+    def texture_histogram(self, axis, bin_deg=10.0, nbins=6, r=0):
+        return hmc_batch_texture_histogram(self.ctx, r, axis, bin_deg, nbins)
+
+    def synchronize(self):
+        self.stream.synchronize()

@@ -67,6 +67,22 @@ def test_grain_tables_agree_with_oracle_by_another_route():
     assert ei.value.status == H.HMC_ENUMERIC
 
 
+def test_grain_table_derivatives_match_central_differences_of_the_oracle():
+    _lib_or_skip()
+    rng = np.random.default_rng(18)
+    e = rng.uniform(0, 2 * math.pi, (6, 3))
+    dC, dS = H.hmc_grain_table_derivatives(e, 246.5, 147.3, 124.7)
+    h = 1e-6
+    for q in range(3):
+        ep, em = e.copy(), e.copy()
+        ep[:, q] += h
+        em[:, q] -= h
+        Cp, Sp, _ = O.tables(ep, 246.5, 147.3, 124.7)
+        Cm, Sm, _ = O.tables(em, 246.5, 147.3, 124.7)
+        assert np.abs(dC[:, q] - (Cp - Cm) / (2 * h)).max() < 1e-6
+        assert np.abs(dS[:, q] - (Sp - Sm) / (2 * h)).max() < 1e-10
+
+
 @pytest.mark.parametrize("field,value,status", [
     ("K", 15, H.HMC_ESHAPE), ("K", 0, H.HMC_ESHAPE), ("K", 2048, H.HMC_ESHAPE),
     ("neighbors", 8, H.HMC_EINVAL), ("zone_h", 4, H.HMC_EINVAL), ("kT", 0.0, H.HMC_EINVAL),

@@ -1,0 +1,132 @@
+"""GPU tests of the hand-written adjoint of the global explicit elastic solve.
+
+* Against FP64 central differences of the oracle's n-step stored energy (h = 1e-4 rad,
+  1e-3 MPa) on a lattice small enough for the oracle, with a step count far from
+  convergence (so the recurrence itself, not only its fixed point, is differentiated) and
+  a checkpoint interval that does not divide it.
+* At the 64^3 / 500-grain / 2000-step workload, where the relaxation has converged, the
+  envelope identities dU*/dtheta_g = -sum_{v in g} 1/2 eps_v.(dC_g/dtheta) eps_v and
+  dU*/dSigma = K^3 E* hold at any size and are checked on the GPU's own final state.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1009_0457_amd import hmc as H
+from paper_1009_0457_amd.synth import adjoint_config, voronoi_polycrystal
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_U(K, q, euler, sig_MPa, p, n):
+    Ct, St, _ = O.tables(euler, p.C11, p.C12, p.C44)
+    _, _, _, info = O.global_solve(K, q, Ct, St, np.asarray(sig_MPa) * 1e-3, n, True, p.glob_alpha, p.glob_beta,
+                                   p.glob_alphaE)
+    return info["U"]
+
+
+def test_adjoint_matches_oracle_central_differences():
+    K, n, every = 12, 100, 30
+    m = voronoi_polycrystal(K, 14, 77)
+    rng = np.random.default_rng(3)
+    sig = rng.uniform(-200, 200, 6)
+    p = H.hmc_default_params(K, 26, 1)
+    lat = H.Lattice(p, m.Q)
+    lat.set_orientations(m.euler)
+    lat.set_spins(m.spins)
+    lat.set_load(sig)
+    U_gpu = lat.elastic_forward(n, every)
+    ge, gs = lat.elastic_backward(1.0)
+    U_ora = oracle_U(K, m.spins, m.euler, sig, p, n)
+    say(f"[adjoint FD] U gpu {U_gpu:.8e} oracle {U_ora:.8e}")
+    assert U_gpu == pytest.approx(U_ora, rel=1e-5)
+    h = 1e-4
+    grains = rng.choice(m.Q, size=10, replace=False)
+    worst = 0.0
+    scale = np.abs(ge).max()
+    for g in grains:
+        for k in range(3):
+            ep, em = m.euler.copy(), m.euler.copy()
+            ep[g, k] += h
+            em[g, k] -= h
+            fd = (oracle_U(K, m.spins, ep, sig, p, n) - oracle_U(K, m.spins, em, sig, p, n)) / (2 * h)
+            err = abs(ge[g, k] - fd)
+            worst = max(worst, err / scale)
+            assert err <= 2e-4 * scale + 1e-4 * abs(fd), (g, k, ge[g, k], fd)
+    hs = 1e-3
+    gscale = np.abs(gs).max()
+    for I in range(6):
+        sp, sm = sig.copy(), sig.copy()
+        sp[I] += hs
+        sm[I] -= hs
+        fd = (oracle_U(K, m.spins, m.euler, sp, p, n) - oracle_U(K, m.spins, m.euler, sm, p, n)) / (2 * hs)
+        assert abs(gs[I] - fd) <= 2e-4 * gscale + 1e-4 * abs(fd), (I, gs[I], fd)
+    say(f"    worst |adjoint - FD| / max|grad| over 30 angles: {worst:.2e}")
+    # the context is left at the forward's final state
+    s1 = lat.get_stress().cpu().numpy()
+    lat.elastic_forward(n, every)
+    assert np.array_equal(lat.get_stress().cpu().numpy(), s1)
+    lat.close()
+
+
+def test_adjoint_envelope_identity_at_workload_size():
+    micro, sig, probe = adjoint_config()
+    K = micro.K
+    p = H.hmc_default_params(K, 26, 2)
+    lat = H.Lattice(p, micro.Q)
+    lat.set_orientations(micro.euler)
+    lat.set_spins(micro.spins)
+    lat.set_load(sig)
+    say(f"[adjoint envelope] K={K} grains={micro.Q} 2000 steps, checkpoints every 50")
+    U = lat.elastic_forward(2000, 50)
+    ge, gs = lat.elastic_backward(1.0)
+    s = lat.get_stress().cpu().numpy().astype(np.float64)
+    E = lat.macro_strain()
+    Cl, Sl = H.hmc_grain_tables(micro.euler, p.C11, p.C12, p.C44)
+    dC, _ = H.hmc_grain_table_derivatives(micro.euler, p.C11, p.C12, p.C44)
+    q = micro.spins
+    eps = np.einsum("nij,jn->in", Sl[q], s)                    # eps_v = S_q sigma_v
+    # -1/2 eps . dC eps summed per grain
+    contrib = -0.5 * np.einsum("in,nkij,jn->nk", eps, dC[q], eps)
+    env = np.zeros((micro.Q, 3))
+    np.add.at(env, q, contrib)
+    scale = np.abs(env).max()
+    err = np.abs(ge - env).max()
+    say(f"    U = {U:.6e}; max |adjoint - envelope| / max|grad| = {err / scale:.2e}")
+    assert err <= 1e-3 * scale
+    # probe grains as in the workload description
+    assert np.allclose(ge[probe], env[probe], rtol=2e-3, atol=1e-3 * scale)
+    env_sig = K ** 3 * E * 1e-3          # dU*/dSigma = K^3 E* (per MPa)
+    assert np.abs(gs - env_sig).max() <= 1e-3 * np.abs(env_sig).max()
+    lat.close()
+
+
+def test_autograd_function_matches_direct_adjoint():
+    K, n = 10, 60
+    m = voronoi_polycrystal(K, 6, 5)
+    p = H.hmc_default_params(K, 26, 1)
+    lat = H.Lattice(p, m.Q)
+    lat.set_orientations(m.euler)
+    lat.set_spins(m.spins)
+    sig = np.array([100.0, -50.0, 80.0, 10.0, 0.0, 20.0])
+    lat.set_load(sig)
+    lat.elastic_forward(n, 25)
+    ge, gs = lat.elastic_backward(2.5)
+    eu = torch.tensor(m.euler, dtype=torch.float64, requires_grad=True)
+    st = torch.tensor(sig, dtype=torch.float64, requires_grad=True)
+    U = H.stored_elastic_energy(eu, st, lat, n_steps=n, ckpt_every=25)
+    (2.5 * U).backward()
+    assert np.array_equal(eu.grad.numpy(), ge)
+    assert np.array_equal(st.grad.numpy(), gs)
+    lat.close()

@@ -1,0 +1,161 @@
+"""GPU tests of fused multi-replica batches and of graph-captured sweeps.
+
+A batch launches every replica's colour pass, zone solves and refresh steps together;
+each replica must end exactly where it ends when run alone with the same parameters
+(same kernels, same per-replica arithmetic and reduction order), at zero load and with
+the elastic term on.  Graph replays must reproduce eager sweeps after every replay.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1009_0457_amd import hmc as H
+from paper_1009_0457_amd.synth import voronoi_polycrystal
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def common_params(h=2, R=3, refresh_steps=60):
+    p = H.hmc_default_params(16, 26, h)
+    p.refresh_every = R
+    p.refresh_steps = refresh_steps
+    p.cold_steps = 300
+    p.zone_steps = 120
+    return p
+
+
+def replica_set(common, n=5, seed=0):
+    rng = np.random.default_rng(seed)
+    reps, micros = [], []
+    for r in range(n):
+        K = int((8, 10, 12, 16)[rng.integers(0, 4)])
+        m = voronoi_polycrystal(K, int(rng.integers(3, 20)), 100 + r)
+        rep = H.hmc_default_replica(common, K, m.Q)
+        rep.kT = float(rng.uniform(0.3, 1.0))
+        rep.seed = r + 1
+        axis = rng.normal(size=3)
+        axis /= np.linalg.norm(axis)
+        s = 0.0 if r == 2 else float(rng.uniform(50, 300))   # replica 2: zero load
+        sig = s * np.outer(axis, axis)
+        for i, v in enumerate([sig[0, 0], sig[1, 1], sig[2, 2], sig[1, 2], sig[0, 2], sig[0, 1]]):
+            rep.sigma_MPa[i] = v
+        reps.append(rep)
+        micros.append(m)
+    return reps, micros
+
+
+def run_alone(common, rep, micro, sweeps):
+    p = H.hmc_params.from_buffer_copy(common)
+    p.K, p.kT, p.lambda_el, p.seed = rep.K, rep.kT, rep.lambda_el, rep.seed
+    p.glob_alpha, p.glob_beta, p.glob_alphaE = rep.glob_alpha, rep.glob_beta, rep.glob_alphaE
+    lat = H.Lattice(p, micro.Q)
+    lat.set_orientations(micro.euler)
+    lat.set_spins(micro.spins)
+    load = list(rep.sigma_MPa)
+    lat.set_load(load)
+    elastic = any(v != 0 for v in load)
+    if elastic:
+        lat.stress_refresh(-1, True)
+    lat.sweep(sweeps)
+    spins = lat.get_spins().cpu().numpy()
+    sig = lat.get_stress().cpu().numpy() if elastic else None
+    st = lat.stats()
+    lat.close()
+    return spins, sig, st
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_batch_equals_replicas_run_alone(graphs):
+    common = common_params()
+    reps, micros = replica_set(common)
+    say(f"[batch] {len(reps)} replicas K={[r.K for r in reps]} graphs={graphs}")
+    b = H.Batch(common, reps)
+    for r, m in enumerate(micros):
+        b.set_replica(r, m.euler, m.spins)
+    b.stress_refresh(-1, True)
+    if graphs:
+        b.set_graphs(True)
+    sweeps = 7
+    b.sweep(sweeps)
+    b.synchronize()
+    tot = b.stats()
+    for r, (rep, m) in enumerate(zip(reps, micros)):
+        spins, sig, st = run_alone(common, rep, m, sweeps)
+        got = b.get_spins(r).cpu().numpy()
+        say(f"    replica {r}: K={rep.K} changed {int(np.count_nonzero(spins != m.spins))} sites")
+        assert np.array_equal(got, spins), r
+        if sig is not None:
+            assert np.array_equal(b.get_stress(r).cpu().numpy(), sig), r
+    assert tot["site_trials"] == sweeps * sum(r.K ** 3 for r in reps)
+    b.close()
+
+
+def test_batch_zero_load_matches_oracle():
+    """Zero-load replicas of a batch against the oracle, bit for bit."""
+    common = common_params(h=1)
+    common.proposal = 1
+    reps, micros = [], []
+    for r, K in enumerate((6, 10, 8, 12)):
+        m = voronoi_polycrystal(K, 5, 40 + r)
+        rep = H.hmc_default_replica(common, K, m.Q)
+        rep.kT, rep.seed = 0.4 + 0.2 * r, 7 + r
+        reps.append(rep)
+        micros.append(m)
+    b = H.Batch(common, reps)
+    for r, m in enumerate(micros):
+        b.set_replica(r, m.euler, m.spins)
+    b.set_graphs(True)
+    b.sweep(6)
+    b.synchronize()
+    for r, (rep, m) in enumerate(zip(reps, micros)):
+        q = m.spins.copy()
+        prm = O.make_params(rep.K, 26, m.Q, proposal=1, elastic=False, J=common.J, kT=rep.kT, seed=rep.seed)
+        d = np.zeros(1)
+        O.sweeps(prm, q, np.zeros(36 * m.Q), np.zeros(36 * m.Q), d, np.zeros(6), d, 0, 6)
+        assert np.array_equal(b.get_spins(r).cpu().numpy(), q), r
+    b.close()
+
+
+def test_graph_replays_match_eager_sweeps():
+    """A single lattice on its own stream: every graph replay (sweeps with and without the
+    refresh) equals the eager sweep, with eager work and synchronisation in between."""
+    K = 16
+    m = voronoi_polycrystal(K, 10, 5)
+    p = H.hmc_default_params(K, 26, 1)
+    p.refresh_every = 2
+    p.refresh_steps = 50
+    p.kT = 0.7
+    outs = {}
+    for mode in ("eager", "graph"):
+        s = torch.cuda.Stream()
+        lat = H.Lattice(p, m.Q, stream=s)
+        with torch.cuda.stream(s):
+            lat.set_orientations(m.euler)
+            lat.set_spins(m.spins)
+            lat.set_load([0, 0, 150.0, 0, 0, 0])
+            lat.stress_refresh(300, True)
+            if mode == "graph":
+                lat.set_graphs(True)
+            seq = []
+            for k in range(6):
+                lat.sweep(1)
+                s.synchronize()
+                seq.append(lat.get_spins().cpu().numpy())
+                s.synchronize()
+                _ = lat.energy()        # eager work between replays
+            seq.append(lat.get_stress().cpu().numpy())
+        outs[mode] = seq
+        lat.close()
+    for k, (a, b) in enumerate(zip(outs["eager"], outs["graph"])):
+        assert np.array_equal(a, b), k

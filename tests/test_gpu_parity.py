@@ -195,11 +195,13 @@ def compare_pass(rec, ref, sites, p, tol, what):
     return int(solved.sum()), int(near.sum()), float((err / tol[solved]).max()) if solved.any() else 0.0
 
 
+@pytest.mark.parametrize("variant", [1, 2])
 @pytest.mark.parametrize("cfg", ["tiny", "tiny-uniform"])
-def test_elastic_lockstep_tiny_workload(cfg):
+def test_elastic_lockstep_tiny_workload(cfg, variant):
     c = tiny_config()
     micro = c.microstructure()
-    over = dict(kT=c.kT, refresh_every=c.refresh_every, proposal=1 if cfg == "tiny-uniform" else 0)
+    over = dict(kT=c.kT, refresh_every=c.refresh_every, proposal=1 if cfg == "tiny-uniform" else 0,
+                zone_variant=variant)
     p, lat = make_lattice(c.K, c.neighbors, c.zone_h, micro, **over)
     lat.set_load(c.sigma_MPa)
     lat.stress_refresh(-1, True)
@@ -214,7 +216,7 @@ def test_elastic_lockstep_tiny_workload(cfg):
             lat.stress_refresh(p.refresh_steps, False)
         sig = lat.get_stress().cpu().numpy().astype(np.float64)
         for col in range(O.num_colours(c.neighbors)):
-            say(f"[lockstep {cfg}] sweep {s} colour {col}")
+            say(f"[lockstep {cfg} variant {variant}] sweep {s} colour {col}")
             snap = lat.get_spins().cpu().numpy()
             rec = lat.colour_pass(col, records=True)
             q = snap.copy()
@@ -232,14 +234,16 @@ def test_elastic_lockstep_tiny_workload(cfg):
     lat.close()
 
 
-@pytest.mark.parametrize("which", ["full", "large"])
-def test_elastic_lockstep_sampled_at_workload_size(which):
-    """Full-size workloads in the benchmark's launch configuration: every trial of a
-    colour pass runs on the GPU; the oracle recomputes a seeded sample of them."""
+@pytest.mark.parametrize("which,variant", [("full", 1), ("full", 0), ("large", 0)])
+def test_elastic_lockstep_sampled_at_workload_size(which, variant):
+    """Full-size workloads in the benchmark's launch configuration (variant 0 = automatic,
+    what the benchmark runs): every trial of a colour pass runs on the GPU; the oracle
+    recomputes a seeded sample of them."""
     c = full_config() if which == "full" else large_config()
     micro = c.microstructure()
-    p, lat = make_lattice(c.K, c.neighbors, c.zone_h, micro, kT=c.kT, refresh_every=c.refresh_every)
-    say(f"[lockstep sampled {which}] K={c.K}: cold refresh")
+    p, lat = make_lattice(c.K, c.neighbors, c.zone_h, micro, kT=c.kT, refresh_every=c.refresh_every,
+                          zone_variant=variant)
+    say(f"[lockstep sampled {which} variant {variant}] K={c.K}: cold refresh")
     lat.set_load(c.sigma_MPa)
     lat.stress_refresh(-1, True)
     lat.sweep(2)          # leave the initial Voronoi state
@@ -259,6 +263,34 @@ def test_elastic_lockstep_sampled_at_workload_size(which):
         tol, _ = zone_tol(sig[:, pick], St, snap[pick], ref["dPi"])
         n, k, w = compare_pass(rec, ref, pick, p, tol, f"{which} colour {col}")
         say(f"    sampled {n} solves, flagged {k}, worst err/tol {w:.3f}; real flips in pass {real.size}")
+    lat.close()
+
+
+@pytest.mark.parametrize("h,variant", [(0, 0), (0, 1), (1, 0), (2, 1), (2, 2), (3, 0)])
+def test_elastic_lockstep_zone_sizes(h, variant):
+    """Every zone size the library accepts, both kernels, on a lattice whose edge is not a
+    multiple of the zone (ragged wrap-around), with uniform proposals (many solves)."""
+    K = 10
+    micro = voronoi_polycrystal(K, 12, 30 + h)
+    p, lat = make_lattice(K, 26, h, micro, kT=0.8, proposal=1, zone_variant=variant,
+                          zone_steps=(40, 50, 200, 120)[h])
+    lat.set_load([60.0, -90.0, 140.0, 25.0, 0.0, -35.0])
+    lat.stress_refresh(600, True)
+    sig = lat.get_stress().cpu().numpy().astype(np.float64)
+    Ct, St, _ = O.tables(micro.euler, p.C11, p.C12, p.C44)
+    prm = oracle_params(p, micro.Q, True)
+    cols = O.colour_of(K, 26)
+    for col in (0, 3, 7):
+        say(f"[lockstep zone h={h} variant={variant}] colour {col}")
+        snap = lat.get_spins().cpu().numpy()
+        rec = lat.colour_pass(col, records=True)
+        q = snap.copy()
+        ref = O.colour_pass(prm, q, Ct, St, sig, 0, col, want_records=True)
+        sites = np.nonzero(cols == col)[0]
+        tol, _ = zone_tol(sig[:, sites], St, snap[sites], ref["dPi"][sites])
+        n, k, w = compare_pass(rec, ref[sites], sites, p, tol, f"h={h} colour {col}")
+        say(f"    {n} solves, flagged {k}, worst err/tol {w:.3f}")
+        assert n > 50
     lat.close()
 
 
