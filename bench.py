@@ -43,6 +43,25 @@ def zone_flops_per_solve(h: int, nr: int) -> float:
 REFRESH_BYTES_PER_NODE_STEP = 50.0   # read u, w (24 B) + write u, w (24 B) + spin (2 B)
 
 
+def measured_traffic(key_bytes, key_hash, source):
+    """HBM bytes from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, valid only while
+    the kernel source still has the hash it had when the counters were taken (else None)."""
+    import hashlib
+
+    try:
+        vals = {}
+        for line in open(os.path.join(ROOT, "profiles", "counters_large128.md")):
+            if "=" in line and not line.startswith(("|", "`", "cd ")):
+                k, v = (t.strip() for t in line.split("=", 1))
+                vals[k] = v
+        h = hashlib.sha256(open(os.path.join(ROOT, "paper_1009_0457_amd", "csrc", source), "rb").read())
+        if h.hexdigest()[:16] != vals.get(key_hash):
+            return None
+        return float(vals[key_bytes])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,8 +198,12 @@ def main():
     zt = kt["zone"]
     fps = zone_flops_per_solve(p.zone_h, p.zone_steps)
     achieved = fps * solves / (zt["total_ms"] * 1e-3) / 1e12 if zt["total_ms"] > 0 else 0.0
+    per_solve = measured_traffic("zone_traffic_bytes_per_solve", "zone_source_sha256_16", "hmc_zone.hip")
+    spl = solves / max(1, zt["launches"])
     roof = {"kernel": "zone solve", "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "traffic": None if per_solve is None else round(per_solve * spl),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE, profiles/counters_large128.md)",
             "avg_launch_ms": round(zt["total_ms"] / max(1, zt["launches"]), 4),
             "flop_per_solve": fps, "solves_per_launch": round(solves / max(1, zt["launches"]), 1)}
     rs = kt["refresh_step"]
@@ -188,8 +211,10 @@ def main():
     if rs["launches"]:
         bytes_step = REFRESH_BYTES_PER_NODE_STEP * K ** 3
         ach = bytes_step * rs["launches"] / (rs["total_ms"] * 1e-3) / 1e9
+        rt = measured_traffic("refresh_step_traffic_bytes_per_launch", "elastic_source_sha256_16", "hmc_elastic.hip")
         refresh_roof = {"kernel": "global explicit step", "bound": "hbm", "achieved": round(ach, 1),
                         "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
+                        "traffic": None if (rt is None or K != 128) else round(rt),
                         "avg_launch_ms": round(rs["total_ms"] / rs["launches"], 4),
                         "note": f"working set {(13 * 4 + 2) * K ** 3 / 2 ** 20:.0f} MiB (cache-resident at 128^3)"}
     out = {
