@@ -242,6 +242,26 @@ def main():
         "refresh_roofline": refresh_roof,
         "kernel_ms": {k: round(v["total_ms"], 3) for k, v in kt.items()},
     }
+    # the same workload with the lower-bound screen (decision-exact; fewer zone solves)
+    lat.set_zone_screen(True)
+    lat.reset_stats()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(a.steps):
+        s = lat.sweep_index()
+        lat.sweep(1)
+        if cfg.histogram_every and (s + 1) % cfg.histogram_every == 0:
+            hist.append([lat.texture_histogram(ax, 10.0, 6).tolist() for ax in axes])
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    st2 = lat.stats()
+    lat.set_zone_screen(False)
+    out["screened"] = {
+        "value": trials / (t3 - t2), "unit": "site-trials/s", "ms_per_step": (t3 - t2) / a.steps * 1e3,
+        "zone_solve_fraction": st2["zone_solves"] / trials, "screened_fraction": st2["screened"] / trials,
+        "note": "same workload and sweep count, zone_screen=1: trials whose point-zone lower bound already "
+                "exceeds the Metropolis threshold are rejected without a solve (decisions unchanged)"}
+    log(f"[bench] screened: {out['screened']['value']:.4e} site-trials/s, stats {st2}")
     if not a.no_cpu_baseline:
         log("[bench] oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(lat, p, micro, a.cpu_seconds)

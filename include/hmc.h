@@ -65,7 +65,13 @@ typedef struct {
                                n_steps < 0 */
     int32_t zone_variant;   /* zone-solve kernel: 0 automatic, 1 one wavefront per trial,
                                2 node columns across a 256-lane work-group (h <= 2) */
-    int32_t reserved0;      /* must be 0 */
+    int32_t zone_screen;    /* 1: skip the zone solve of a trial whose rejection is already
+                               certain: the point-zone energy 1/2 sigma_p.(S_old - S_new) sigma_p
+                               is a lower bound of the zone's (its relaxation only adds
+                               stiffness), so J*gb + lambda_el * that bound above the trial's
+                               Metropolis threshold (plus a floating-point margin) rejects it.
+                               Decisions are those of the full solve; the trial's record then
+                               carries flag 8 and no dPi.  0: solve every real flip. */
     double J;               /* grain-boundary energy per unlike bond (MC units) */
     double kT;              /* Monte Carlo temperature T_mc (MC units), > 0 */
     double C11, C12, C44;   /* cubic stiffness in the crystal frame (GPa) */
@@ -84,7 +90,8 @@ typedef struct {
     float dPi;       /* zone energy change in GPa*voxel (0 unless a zone was solved) */
     uint32_t r1;     /* Metropolis variate: accept iff dE <= 0 or r1 < 2^32 exp(-dE/kT) */
     int32_t flags;   /* bit 0: q_new differs from the current state; bit 1: accepted;
-                        bit 2: a zone solve produced dPi */
+                        bit 2: a zone solve produced dPi; bit 3: rejected by the lower-bound
+                        screen without a zone solve */
     int32_t reserved;
 } hmc_trial_record;
 
@@ -94,6 +101,7 @@ typedef struct {
     int64_t real_flips;     /* trials whose proposal differs from the current state */
     int64_t zone_solves;    /* zone solves run */
     int64_t accepted;       /* accepted real flips */
+    int64_t screened;       /* real flips rejected by the lower-bound screen (zone_screen) */
     int64_t refresh_steps;  /* explicit global steps run */
 } hmc_stats;
 
@@ -187,6 +195,9 @@ hmc_status hmc_get_sweep_index(hmc_ctx ctx, int64_t* s);
 
 hmc_status hmc_get_stats(hmc_ctx ctx, hmc_stats* out);
 hmc_status hmc_reset_stats(hmc_ctx ctx);
+
+/* Turn the lower-bound screen of hmc_params.zone_screen on (1) or off (0) for later sweeps. */
+hmc_status hmc_set_zone_screen(hmc_ctx ctx, int32_t enable);
 
 /* Kernel timing.  While profiling is enabled the library records a pair of HIP events on
  * the context's stream around every launch of each kernel class below; hmc_get_kernel_times

@@ -29,8 +29,8 @@ hmc_status check_common(const hmc_params* p)
     if (p->neighbors != 6 && p->neighbors != 26) return HMC_EINVAL;
     if (p->proposal != 0 && p->proposal != 1) return HMC_EINVAL;
     if (p->zone_h < 0 || p->zone_h > 3) return HMC_EINVAL;
-    if (p->zone_variant < 0 || p->zone_variant > 2 || (p->zone_variant == 2 && p->zone_h > 2) || p->reserved0 != 0)
-        return HMC_EINVAL;
+    if (p->zone_variant < 0 || p->zone_variant > 2 || (p->zone_variant == 2 && p->zone_h > 2)) return HMC_EINVAL;
+    if (p->zone_screen != 0 && p->zone_screen != 1) return HMC_EINVAL;
     if (p->zone_steps < 0 || p->refresh_steps < 0 || p->cold_steps < 0 || p->refresh_every < 1) return HMC_EINVAL;
     const double vals[] = {p->J, p->kT, p->C11, p->C12, p->C44, p->lambda_el, p->zone_alpha, p->zone_beta,
                            p->glob_alpha, p->glob_beta, p->glob_alphaE};
@@ -73,9 +73,9 @@ hmc_replica replica_of_params(const hmc_params* p, int32_t Q)
 // ------------------------------------------------------------------------------------
 struct Layout {
     size_t spins, Ctab, Stab, sigma, u0, u1, w, list, accept, state, partials, counters, stats, thr, tex, hist,
-        bonds, reps, pass_rep, node_rep, sweep, total;
+        bonds, reps, pass_rep, node_rep, tile_rep, sweep, total;
     int64_t sites, grains, max_list;
-    int pass_blocks, node_blocks;
+    int pass_blocks, node_blocks, tile_blocks;
     bool elastic;
 };
 
@@ -94,6 +94,7 @@ Layout layout_of(const hmc_params* p, int n, const hmc_replica* r)
         int64_t nb = (n3 + kSiteBlock - 1) / kSiteBlock;
         if (nb > kMaxChunkBlocks) nb = kMaxChunkBlocks;
         L.node_blocks += (int)nb;
+        L.tile_blocks += tile_blocks_of(r[i].K);
         L.elastic = L.elastic || r[i].lambda_el != 0.0;
     }
     size_t o = 0;
@@ -113,7 +114,8 @@ Layout layout_of(const hmc_params* p, int n, const hmc_replica* r)
     L.list = L.elastic ? take((size_t)L.max_list * sizeof(TrialEntry)) : 0;
     L.accept = L.elastic ? take((size_t)L.max_list) : 0;
     L.state = take((size_t)n * kStateDoubles * sizeof(double));
-    L.partials = take((size_t)L.node_blocks * 8 * sizeof(double));
+    const int pblocks = L.node_blocks > L.tile_blocks ? L.node_blocks : L.tile_blocks;
+    L.partials = take((size_t)pblocks * 8 * sizeof(double));
     L.counters = take(kCounters * sizeof(uint32_t));
     L.stats = take(kStats * sizeof(unsigned long long));
     L.thr = take((size_t)n * 64 * sizeof(uint64_t));
@@ -123,6 +125,7 @@ Layout layout_of(const hmc_params* p, int n, const hmc_replica* r)
     L.reps = take((size_t)n * sizeof(RepDev));
     L.pass_rep = take((size_t)L.pass_blocks * sizeof(int32_t));
     L.node_rep = take((size_t)L.node_blocks * sizeof(int32_t));
+    L.tile_rep = take((size_t)L.tile_blocks * sizeof(int32_t));
     L.sweep = take(sizeof(int64_t));
     L.total = o;
     return L;
@@ -419,6 +422,7 @@ hmc_status build_context(const hmc_params* p, int n, const hmc_replica* r, void*
     c->max_list = L.max_list;
     c->pass_blocks = L.pass_blocks;
     c->node_blocks = L.node_blocks;
+    c->tile_blocks = L.tile_blocks;
     c->elastic_buffers = L.elastic;
     char* b = (char*)ws;
     c->d.spins = (int16_t*)(b + L.spins);
@@ -443,14 +447,16 @@ hmc_status build_context(const hmc_params* p, int n, const hmc_replica* r, void*
     c->d.reps = (RepDev*)(b + L.reps);
     c->d.pass_rep = (int32_t*)(b + L.pass_rep);
     c->d.node_rep = (int32_t*)(b + L.node_rep);
+    c->d.tile_rep = (int32_t*)(b + L.tile_rep);
     c->d.sweep = (int64_t*)(b + L.sweep);
 
     const int M = p->neighbors;
     const int C = c->colours;
     std::vector<uint64_t> thr((size_t)n * 64, 0);
-    std::vector<int32_t> pass_rep((size_t)L.pass_blocks), node_rep((size_t)L.node_blocks);
+    std::vector<int32_t> pass_rep((size_t)L.pass_blocks), node_rep((size_t)L.node_blocks),
+        tile_rep((size_t)L.tile_blocks);
     int64_t site_off = 0, grain_off = 0;
-    int pf = 0, nf = 0;
+    int pf = 0, nf = 0, tf = 0;
     c->reps.resize(n);
     c->rep_euler_off.resize(n);
     for (int i = 0; i < n; ++i) {
@@ -467,6 +473,8 @@ hmc_status build_context(const hmc_params* p, int n, const hmc_replica* r, void*
         R.node_first = nf;
         int64_t nb = (R.n3 + kSiteBlock - 1) / kSiteBlock;
         R.node_blocks = (int)(nb > kMaxChunkBlocks ? kMaxChunkBlocks : nb);
+        R.tile_first = tf;
+        R.tile_blocks = tile_blocks_of(R.K);
         R.J = p->J;
         R.kT = r[i].kT;
         R.lambda = r[i].lambda_el;
@@ -483,6 +491,8 @@ hmc_status build_context(const hmc_params* p, int n, const hmc_replica* r, void*
         R.key1 = (uint32_t)(r[i].seed >> 32);
         for (int k = 0; k < R.pass_blocks; ++k) pass_rep[(size_t)pf + k] = i;
         for (int k = 0; k < R.node_blocks; ++k) node_rep[(size_t)nf + k] = i;
+        for (int k = 0; k < R.tile_blocks; ++k) tile_rep[(size_t)tf + k] = i;
+        tf += R.tile_blocks;
         pf += R.pass_blocks;
         nf += R.node_blocks;
         // integer Metropolis thresholds for dE = J*gb: accept iff r1 < thr[gb + M] with
@@ -514,6 +524,9 @@ hmc_status build_context(const hmc_params* p, int n, const hmc_replica* r, void*
                            stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d.node_rep, node_rep.data(), node_rep.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d.tile_rep, tile_rep.data(), tile_rep.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                            stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d.reps, c->reps.data(), c->reps.size() * sizeof(RepDev), hipMemcpyHostToDevice, stream);
@@ -1021,6 +1034,7 @@ hmc_status hmc_get_stats(hmc_ctx c, hmc_stats* out)
     out->real_flips = (int64_t)s[kStatReal];
     out->zone_solves = (int64_t)s[kStatSolves];
     out->accepted = (int64_t)s[kStatAccepted];
+    out->screened = (int64_t)s[kStatScreened];
     out->refresh_steps = c->host_refresh_steps;
     return HMC_OK;
 }
@@ -1032,6 +1046,16 @@ hmc_status hmc_reset_stats(hmc_ctx c)
     HMC_TRY(c, hipMemsetAsync(c->d.stats, 0, kStats * sizeof(unsigned long long), c->stream), "reset_stats");
     c->host_site_trials = 0;
     c->host_refresh_steps = 0;
+    return HMC_OK;
+}
+
+hmc_status hmc_set_zone_screen(hmc_ctx c, int32_t enable)
+{
+    if (!c) return HMC_EINVAL;
+    c->err.clear();
+    if (enable != 0 && enable != 1) return state_fail(c, HMC_EINVAL, "enable must be 0 or 1");
+    c->p.zone_screen = enable;
+    drop_graphs(c);
     return HMC_OK;
 }
 

@@ -8,7 +8,7 @@
 // beta = 1 - c dt):
 //     r_n = -sum_{v at n} B_v(n)^T sigma_v,   w <- beta w + alpha r,   u <- u + w
 //     r_E = Sigma - mean_v sigma_v,          wE <- beta wE + alphaE r_E,  E <- E + wE
-// k_global_step does the node part for every node (reading u, writing the other u
+// k_global_step_tiled does the node part for every node (reading u, writing the other u
 // buffer, so no node sees a half-updated neighbour) and writes per-block sums of the
 // stresses it formed; k_global_E folds those sums in a fixed order (deterministic) and
 // advances E.  k_global_final writes the stress field the zone solves read.
@@ -26,52 +26,134 @@ struct GlobArgs {
     const double* state;
     const RepDev* reps;
     const int32_t* node_rep;
+    const int32_t* tile_rep;
     int64_t plane;
 };
 
-__global__ __launch_bounds__(256) void k_global_step(GlobArgs a)
+__device__ __forceinline__ int wrapm(int a, int K)
 {
-    const NodeRange nr = node_range(a.reps, a.node_rep);
-    const RepDev& R = nr.R;
+    a %= K;
+    return a < 0 ? a + K : a;
+}
+
+// Tiled explicit step.  A block owns a 32 x 8 tile of nodes in x, y and marches through 8
+// node layers in z.  Node layers (with a one-node halo) and voxel stress layers (with the
+// low halo voxel) live in two-slot LDS rings, so each voxel stress is formed once per tile
+// (1.3x with halos) instead of once per corner node (8x).  The arithmetic per voxel and per
+// node, and the order of the 8 corner contributions, are those of the untiled step.
+__global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
+{
+    constexpr int NX = kTileX + 2, NY = kTileY + 2, VX = kTileX + 1, VY = kTileY + 1;
+    __shared__ float su[2][3][NY][NX];
+    __shared__ float ss[2][6][VY][VX];
+
+    const int r = a.tile_rep[blockIdx.x];
+    const RepDev R = a.reps[r];
     const int K = R.K;
+    const int ntx = (K + kTileX - 1) / kTileX, nty = (K + kTileY - 1) / kTileY;
+    int b = (int)blockIdx.x - R.tile_first;
+    const int bx = b % ntx;
+    b /= ntx;
+    const int by = b % nty, bz = b / nty;
+    const int x0 = bx * kTileX, y0 = by * kTileY, z0 = bz * kTileZ;
+    const int z1 = (z0 + kTileZ < K) ? z0 + kTileZ : K;
     const int16_t* spins = a.spins + R.site_off;
     const float* Ctab = a.Ctab + R.grain_off * kTab;
     const float* uin = a.uin + R.site_off;
     float* uout = a.uout + R.site_off;
     float* w = a.w + R.site_off;
-    const double* st = a.state + (int64_t)a.node_rep[blockIdx.x] * kStateDoubles;
+    const int64_t P = a.plane;
+    const double* st = a.state + (int64_t)r * kStateDoubles;
     float E[6];
 #pragma unroll
     for (int I = 0; I < 6; ++I) E[I] = (float)st[kE + I];
     const float alpha = R.glob_alpha, beta = R.glob_beta;
+    const int t = threadIdx.x, lx = t % kTileX, ly = t / kTileX;
+    const int nx = x0 + lx, ny = y0 + ly;
+    const bool own = nx < K && ny < K;
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t n = nr.first; n < R.n3; n += nr.stride) {
-        const int x = (int)(n % K), y = (int)((n / K) % K), z = (int)(n / ((int64_t)K * K));
-        float f[3] = {0.f, 0.f, 0.f};
+
+    auto load_nodes = [&](int slot, int z) {
+        const int64_t zoff = (int64_t)K * K * wrapm(z, K);
+        for (int i = t; i < NX * NY; i += 256) {
+            const int ix = i % NX, iy = i / NX;
+            const int64_t n = wrapm(x0 - 1 + ix, K) + (int64_t)K * wrapm(y0 - 1 + iy, K) + zoff;
+            su[slot][0][iy][ix] = uin[n];
+            su[slot][1][iy][ix] = uin[P + n];
+            su[slot][2][iy][ix] = uin[2 * P + n];
+        }
+    };
+    // voxel layer z from node layers z (slot lo) and z + 1 (slot hi)
+    auto voxel_layer = [&](int vs, int lo, int hi, int z, bool owned_layer) {
+        const int64_t zoff = (int64_t)K * K * wrapm(z, K);
+        for (int i = t; i < VX * VY; i += 256) {
+            const int ix = i % VX, iy = i / VX;
+            float g[3][3];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int ca = c & 1, cb = (c >> 1) & 1, cc = c >> 2;
-            const int vx = wrapk(x - ca, K), vy = wrapk(y - cb, K), vz = wrapk(z - cc, K);
-            float e[6], s[6];
-            voxel_strain(uin, a.plane, K, vx, vy, vz, E, e);
-            const int g = spins[vx + (int64_t)K * (vy + (int64_t)K * vz)];
-            symv21(Ctab + (int64_t)g * kTab, e, s);
-            const float sx = ca ? 0.25f : -0.25f, sy = cb ? 0.25f : -0.25f, sz = cc ? 0.25f : -0.25f;
-            f[0] += sx * s[0] + sy * s[5] + sz * s[4];
-            f[1] += sx * s[5] + sy * s[1] + sz * s[3];
-            f[2] += sx * s[4] + sy * s[3] + sz * s[2];
-            if (c == 0) {
+            for (int j = 0; j < 3; ++j) {
+                const float c0 = su[lo][j][iy][ix], c1 = su[lo][j][iy][ix + 1];
+                const float c2 = su[lo][j][iy + 1][ix], c3 = su[lo][j][iy + 1][ix + 1];
+                const float c4 = su[hi][j][iy][ix], c5 = su[hi][j][iy][ix + 1];
+                const float c6 = su[hi][j][iy + 1][ix], c7 = su[hi][j][iy + 1][ix + 1];
+                g[j][0] = 0.25f * ((c1 - c0) + (c3 - c2) + (c5 - c4) + (c7 - c6));
+                g[j][1] = 0.25f * ((c2 + c3) - (c0 + c1) + (c6 + c7) - (c4 + c5));
+                g[j][2] = 0.25f * ((c4 + c5 + c6 + c7) - (c0 + c1 + c2 + c3));
+            }
+            float e[6], s6[6];
+            e[0] = E[0] + g[0][0];
+            e[1] = E[1] + g[1][1];
+            e[2] = E[2] + g[2][2];
+            e[3] = E[3] + g[1][2] + g[2][1];
+            e[4] = E[4] + g[0][2] + g[2][0];
+            e[5] = E[5] + g[0][1] + g[1][0];
+            const int gx = x0 - 1 + ix, gy = y0 - 1 + iy;
+            const int q = spins[wrapm(gx, K) + (int64_t)K * wrapm(gy, K) + zoff];
+            symv21(Ctab + (int64_t)q * kTab, e, s6);
 #pragma unroll
-                for (int I = 0; I < 6; ++I) acc[I] += (double)s[I];
+            for (int I = 0; I < 6; ++I) ss[vs][I][iy][ix] = s6[I];
+            if (owned_layer && ix >= 1 && iy >= 1 && gx < K && gy < K) {
+#pragma unroll
+                for (int I = 0; I < 6; ++I) acc[I] += (double)s6[I];
             }
         }
+    };
+
+    load_nodes(0, z0 - 1);
+    load_nodes(1, z0);
+    __syncthreads();
+    voxel_layer(0, 0, 1, z0 - 1, false);
+    int nlo = 1, vprev = 0;
+    for (int z = z0; z < z1; ++z) {
+        const int nhi = 1 - nlo, vcur = 1 - vprev;
+        __syncthreads();                       // node layer z-1 and voxel layer z-2 are free
+        load_nodes(nhi, z + 1);
+        __syncthreads();
+        voxel_layer(vcur, nlo, nhi, z, true);
+        __syncthreads();
+        if (own) {
+            float f[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int64_t idx = (int64_t)j * a.plane + n;
-            const float wn = beta * w[idx] - alpha * f[j];
-            w[idx] = wn;
-            uout[idx] = uin[idx] + wn;
+            for (int c = 0; c < 8; ++c) {
+                const int ca = c & 1, cb = (c >> 1) & 1, cc = c >> 2;
+                const int vx = lx + 1 - ca, vy = ly + 1 - cb, vsl = cc ? vprev : vcur;
+                const float s0 = ss[vsl][0][vy][vx], s1 = ss[vsl][1][vy][vx], s2 = ss[vsl][2][vy][vx];
+                const float s3 = ss[vsl][3][vy][vx], s4 = ss[vsl][4][vy][vx], s5 = ss[vsl][5][vy][vx];
+                const float sx = ca ? 0.25f : -0.25f, sy = cb ? 0.25f : -0.25f, sz = cc ? 0.25f : -0.25f;
+                f[0] += sx * s0 + sy * s5 + sz * s4;
+                f[1] += sx * s5 + sy * s1 + sz * s3;
+                f[2] += sx * s4 + sy * s3 + sz * s2;
+            }
+            const int64_t n = nx + (int64_t)K * (ny + (int64_t)K * z);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int64_t idx = (int64_t)j * P + n;
+                const float wn = beta * w[idx] - alpha * f[j];
+                w[idx] = wn;
+                uout[idx] = su[nlo][j][ly + 1][lx + 1] + wn;
+            }
         }
+        nlo = nhi;
+        vprev = vcur;
     }
     block_sum_to<6>(a.partials, acc);
 }
@@ -80,6 +162,7 @@ struct EArgs {
     double* state;
     const double* partials;
     const RepDev* reps;
+    int tiled;            // partial sums come from the tiled step's blocks
 };
 
 // One block per replica: folds its per-block stress sums (fixed order) and advances the
@@ -91,9 +174,10 @@ __global__ __launch_bounds__(256) void k_global_E(EArgs a)
     double* st = a.state + (int64_t)blockIdx.x * kStateDoubles;
     const int t = threadIdx.x;
     double s[6] = {0, 0, 0, 0, 0, 0};
-    for (int b = t; b < R.node_blocks; b += 256)
+    const int first = a.tiled ? R.tile_first : R.node_first, nblk = a.tiled ? R.tile_blocks : R.node_blocks;
+    for (int b = t; b < nblk; b += 256)
 #pragma unroll
-        for (int I = 0; I < 6; ++I) s[I] += a.partials[(int64_t)(R.node_first + b) * 8 + I];
+        for (int I = 0; I < 6; ++I) s[I] += a.partials[(int64_t)(first + b) * 8 + I];
 #pragma unroll
     for (int I = 0; I < 6; ++I) red[I][t] = s[I];
     __syncthreads();
@@ -297,16 +381,18 @@ hipError_t launch_global_steps(hmc_ctx_s* c, int n_steps)
     a.state = c->d.state;
     a.reps = c->d.reps;
     a.node_rep = c->d.node_rep;
+    a.tile_rep = c->d.tile_rep;
     a.plane = c->total_sites;
     EArgs ea;
     ea.state = c->d.state;
     ea.partials = c->d.partials;
     ea.reps = c->d.reps;
+    ea.tiled = 1;
     for (int s = 0; s < n_steps; ++s) {
         a.uin = c->d.u[c->cur_u];
         a.uout = c->d.u[1 - c->cur_u];
         int tok = prof_begin(c, kProfRefreshStep);
-        hipLaunchKernelGGL(k_global_step, dim3(c->node_blocks), dim3(256), 0, c->stream, a);
+        hipLaunchKernelGGL(k_global_step_tiled, dim3(c->tile_blocks), dim3(256), 0, c->stream, a);
         prof_end(c, tok);
         tok = prof_begin(c, kProfRefreshOther);
         hipLaunchKernelGGL(k_global_E, dim3(c->n_rep), dim3(256), 0, c->stream, ea);
@@ -330,12 +416,14 @@ hipError_t launch_global_step_ptrs(hmc_ctx_s* c, const float* uin, float* uout)
     a.state = c->d.state;
     a.reps = c->d.reps;
     a.node_rep = c->d.node_rep;
+    a.tile_rep = c->d.tile_rep;
     a.plane = c->total_sites;
     EArgs ea;
     ea.state = c->d.state;
     ea.partials = c->d.partials;
     ea.reps = c->d.reps;
-    hipLaunchKernelGGL(k_global_step, dim3(c->node_blocks), dim3(256), 0, c->stream, a);
+    ea.tiled = 1;
+    hipLaunchKernelGGL(k_global_step_tiled, dim3(c->tile_blocks), dim3(256), 0, c->stream, a);
     hipLaunchKernelGGL(k_global_E, dim3(c->n_rep), dim3(256), 0, c->stream, ea);
     return hipGetLastError();
 }

@@ -35,6 +35,12 @@ struct TrialEntry {
 constexpr int kMaxReplicas = 4096;
 constexpr int kSiteBlock = 256;        // sites (or nodes) per block of site-parallel kernels
 constexpr int kMaxChunkBlocks = 8192;  // blocks per replica of node-parallel reductions
+constexpr int kTileX = 32, kTileY = 8, kTileZ = 8;   // node tile of the explicit step
+
+__host__ __device__ constexpr int tile_blocks_of(int K)
+{
+    return ((K + kTileX - 1) / kTileX) * ((K + kTileY - 1) / kTileY) * ((K + kTileZ - 1) / kTileZ);
+}
 
 // Device description of one replica.
 struct RepDev {
@@ -46,6 +52,7 @@ struct RepDev {
     int64_t grain_off;               // into Ctab / Stab (grains)
     int32_t pass_first, pass_blocks; // blocks of a colour pass (active sites / 256, rounded up)
     int32_t node_first, node_blocks; // blocks of node-parallel kernels (<= kMaxChunkBlocks)
+    int32_t tile_first, tile_blocks; // blocks of the tiled explicit step (32 x 8 x 8 nodes each)
     double J, kT, lambda;
     float glob_alpha, glob_beta;
     double glob_alphaE;
@@ -65,7 +72,7 @@ enum StateSlot {
 enum CounterSlot { kListCount = 0, kErrFlag = 8, kCounters = 16 };
 
 // 64-bit statistics slots.
-enum StatSlot { kStatReal = 0, kStatSolves = 1, kStatAccepted = 2, kStats = 8 };
+enum StatSlot { kStatReal = 0, kStatSolves = 1, kStatAccepted = 2, kStatScreened = 3, kStats = 8 };
 
 struct DeviceState {
     int16_t* spins = nullptr;        // sum of n3
@@ -87,6 +94,7 @@ struct DeviceState {
     RepDev* reps = nullptr;          // n_rep
     int32_t* pass_rep = nullptr;     // block -> replica for colour passes
     int32_t* node_rep = nullptr;     // block -> replica for node kernels
+    int32_t* tile_rep = nullptr;     // block -> replica for the tiled explicit step
     int64_t* sweep = nullptr;        // device copy of the sweep index (Philox counter)
 };
 
@@ -106,6 +114,7 @@ struct hmc_ctx_s {
     int64_t max_list = 0;
     int pass_blocks = 0;            // total blocks of a colour pass
     int node_blocks = 0;            // total blocks of node kernels
+    int tile_blocks = 0;            // total blocks of the tiled explicit step
     bool elastic_buffers = false;
     bool have_orient = false, have_spins = false, have_load = false, have_stress = false;
     bool have_state = false;

@@ -58,8 +58,29 @@ struct PassArgs {
     hmc_trial_record* rec;          // indexed by site_off + site, or null
     unsigned long long* stats;
     const int64_t* sweep;           // Philox counter word 1 (low 32 bits)
+    const float* Stab;              // compliance tables (lower-bound screen)
+    const float* sigma;             // stress planes of `plane` floats (lower-bound screen)
+    int64_t plane;
     int colour;
+    int screen;
 };
+
+// Point-zone energy 1/2 sigma.(S_old - S_new) sigma of the trial site: a lower bound of the
+// zone energy change for every zone size.
+__device__ __forceinline__ double point_zone_energy(const float* __restrict__ So, const float* __restrict__ Sn,
+                                                    const float s[6])
+{
+    double d = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i; j < 6; ++j) {
+            const int k = sym_index(i, j);
+            const double w = (i == j ? 0.5 : 1.0) * (double)s[i] * (double)s[j];
+            d += w * ((double)So[k] - (double)Sn[k]);
+        }
+    return d;
+}
 
 // Site of thread t within colour `colour` of a K^3 lattice.
 template <int M>
@@ -128,7 +149,7 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
     const int64_t n_active = R.n3 / (M == 26 ? 8 : 2);
     const bool elastic = R.elastic != 0;
     int16_t* spins = a.spins + R.site_off;
-    bool real = false, accepted = false;
+    bool real = false, accepted = false, screened = false;
     uint32_t site = 0, r1 = 0;
     int q_new = 0, gb = 0;
     if (t < n_active) {
@@ -157,7 +178,27 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
                 const int qn = spins[wrapi(x + dx, K) + K * (wrapi(y + dy, K) + K * wrapi(z + dz, K))];
                 gb += (qn == q_old) - (qn == q_new);
             }
-            if (!elastic) accepted = (uint64_t)r1 < a.thr[(int64_t)r * 64 + gb + M];
+            if (!elastic) {
+                accepted = (uint64_t)r1 < a.thr[(int64_t)r * 64 + gb + M];
+            } else if (a.screen && r1 != 0u) {
+                // reject without a solve when even the lowest possible zone energy loses:
+                // dE >= J gb + lambda dPi_0 > max(0, E*(r1)) + margin
+                float sp[6];
+#pragma unroll
+                for (int I = 0; I < 6; ++I) sp[I] = a.sigma[(int64_t)I * a.plane + R.site_off + site];
+                const float* So = a.Stab + (R.grain_off + q_old) * kTab;
+                const float* Sn = a.Stab + (R.grain_off + q_new) * kTab;
+                const double lo = R.J * (double)gb + R.lambda * point_zone_energy(So, Sn, sp);
+                const double estar = -R.kT * log((double)r1 * 2.3283064365386963e-10);
+                double W = 0.0;   // stored-energy scale of the site for the margin
+#pragma unroll
+                for (int i = 0; i < 6; ++i)
+#pragma unroll
+                    for (int j = i; j < 6; ++j)
+                        W += (i == j ? 0.5 : 1.0) * (double)sp[i] * (double)sp[j] * fabs((double)So[sym_index(i, j)]);
+                const double margin = 1e-4 * fabs(R.lambda) * W + 1e-9 * (1.0 + fabs(lo));
+                screened = lo > fmax(0.0, estar) + margin;
+            }
         }
         if (a.rec) {
             hmc_trial_record rc;
@@ -165,7 +206,7 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
             rc.gb = gb;
             rc.dPi = 0.0f;
             rc.r1 = r1;
-            rc.flags = (real ? 1 : 0) | (accepted ? 2 : 0);
+            rc.flags = (real ? 1 : 0) | (accepted ? 2 : 0) | (screened ? 8 : 0);
             rc.reserved = 0;
             a.rec[R.site_off + site] = rc;
         }
@@ -174,8 +215,10 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
     }
     // wave-collective tail, reached by every lane of the wave (replica uniform per block)
     if (elastic) {
-        const uint32_t slot = wave_append(a.list_count, real);
-        if (real) {
+        const bool solve = real && !screened;
+        const uint32_t slot = wave_append(a.list_count, solve);
+        wave_count(&a.stats[kStatScreened], screened);
+        if (solve) {
             TrialEntry e;
             e.site = site;
             e.qr = (uint32_t)q_new | ((uint32_t)r << 16);
@@ -298,7 +341,11 @@ hipError_t launch_potts_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
     a.rec = rec;
     a.stats = c->d.stats;
     a.sweep = c->d.sweep;
+    a.Stab = c->d.Stab;
+    a.sigma = c->d.sigma;
+    a.plane = c->total_sites;
     a.colour = colour;
+    a.screen = (c->p.zone_screen != 0 && c->d.sigma != nullptr) ? 1 : 0;
     const dim3 grid((unsigned)c->pass_blocks), block(kSiteBlock);
     const int tok = prof_begin(c, kProfPotts);
     if (c->p.neighbors == 26) hipLaunchKernelGGL(k_potts_pass<26>, grid, block, 0, c->stream, a);

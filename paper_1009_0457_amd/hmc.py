@@ -29,7 +29,7 @@ class HmcError(RuntimeError):
 class hmc_params(C.Structure):
     _fields_ = [("K", C.c_int32), ("neighbors", C.c_int32), ("proposal", C.c_int32), ("zone_h", C.c_int32),
                 ("zone_steps", C.c_int32), ("refresh_every", C.c_int32), ("refresh_steps", C.c_int32),
-                ("cold_steps", C.c_int32), ("zone_variant", C.c_int32), ("reserved0", C.c_int32),
+                ("cold_steps", C.c_int32), ("zone_variant", C.c_int32), ("zone_screen", C.c_int32),
                 ("J", C.c_double), ("kT", C.c_double), ("C11", C.c_double), ("C12", C.c_double),
                 ("C44", C.c_double), ("lambda_el", C.c_double), ("zone_alpha", C.c_double),
                 ("zone_beta", C.c_double), ("glob_alpha", C.c_double), ("glob_beta", C.c_double),
@@ -56,7 +56,7 @@ class hmc_replica(C.Structure):
 
 class hmc_stats(C.Structure):
     _fields_ = [("site_trials", C.c_int64), ("real_flips", C.c_int64), ("zone_solves", C.c_int64),
-                ("accepted", C.c_int64), ("refresh_steps", C.c_int64)]
+                ("accepted", C.c_int64), ("screened", C.c_int64), ("refresh_steps", C.c_int64)]
 
 
 # numpy view of hmc_trial_record (24 bytes)
@@ -91,6 +91,7 @@ _SIGS = [
     ("hmc_get_sweep_index", C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     ("hmc_get_stats", C.c_int, [C.c_void_p, C.POINTER(hmc_stats)]),
     ("hmc_reset_stats", C.c_int, [C.c_void_p]),
+    ("hmc_set_zone_screen", C.c_int, [C.c_void_p, C.c_int32]),
     ("hmc_set_profiling", C.c_int, [C.c_void_p, C.c_int32]),
     ("hmc_get_kernel_times", C.c_int, [C.c_void_p, C.POINTER(hmc_kernel_times)]),
     ("hmc_set_graphs", C.c_int, [C.c_void_p, C.c_int32]),
@@ -259,6 +260,10 @@ def hmc_get_stats(ctx) -> dict:
 
 def hmc_reset_stats(ctx):
     _check(lib().hmc_reset_stats(ctx), ctx)
+
+
+def hmc_set_zone_screen(ctx, enable):
+    _check(lib().hmc_set_zone_screen(ctx, int(bool(enable))), ctx)
 
 
 def hmc_set_profiling(ctx, enable):
@@ -483,6 +488,9 @@ class Lattice:
 
     def reset_stats(self):
         hmc_reset_stats(self.ctx)
+
+    def set_zone_screen(self, enable=True):
+        hmc_set_zone_screen(self.ctx, enable)
 
     def set_profiling(self, enable=True):
         hmc_set_profiling(self.ctx, enable)

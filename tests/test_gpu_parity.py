@@ -294,6 +294,45 @@ def test_elastic_lockstep_zone_sizes(h, variant):
     lat.close()
 
 
+@pytest.mark.parametrize("which", ["full", "large"])
+def test_zone_screen_preserves_every_decision(which):
+    """The lower-bound screen skips solves but not decisions: the same colour passes with and
+    without it, from the same state, give identical records' decisions and spins, and every
+    screened trial is a rejection of the full solve."""
+    c = full_config() if which == "full" else large_config()
+    micro = c.microstructure()
+    lats = []
+    for screen in (0, 1):
+        p, lat = make_lattice(c.K, c.neighbors, c.zone_h, micro, kT=c.kT, zone_screen=screen)
+        lat.set_load(c.sigma_MPa)
+        lats.append(lat)
+    say(f"[screen {which}] cold refresh")
+    lats[0].stress_refresh(-1, True)
+    lats[0].sweep(1)
+    spins = lats[0].get_spins()
+    sig = lats[0].get_stress()
+    lats[1].set_spins(spins)
+    lats[1].set_stress(sig)
+    for lat in lats:
+        lat.set_sweep_index(1)
+    n_scr = n_real = 0
+    for col in range(8):
+        r0 = lats[0].colour_pass(col, records=True)
+        r1 = lats[1].colour_pass(col, records=True)
+        assert np.array_equal(r0["flags"] & 3, r1["flags"] & 3), col
+        scr = (r1["flags"] & 8) != 0
+        assert not np.any(r0["flags"][scr] & 2)
+        n_scr += int(scr.sum())
+        n_real += int(((r1["flags"] & 1) != 0).sum())
+        assert np.array_equal(lats[0].get_spins().cpu().numpy(), lats[1].get_spins().cpu().numpy())
+    st = lats[1].stats()
+    say(f"    screened {n_scr} of {n_real} real flips; solves {st['zone_solves']}")
+    assert st["screened"] == n_scr and st["zone_solves"] == n_real - n_scr
+    assert n_scr > n_real // 4
+    for lat in lats:
+        lat.close()
+
+
 def test_elastic_sweeps_are_deterministic():
     c = tiny_config()
     micro = c.microstructure()
