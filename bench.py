@@ -73,6 +73,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--K", type=int, default=0, help="override the lattice edge (diagnostics only)")
+    ap.add_argument("--workload", choices=["large", "batched", "adjoint"], default="large",
+                    help="large: the headline 128^3 workload; batched: the 64-replica ensemble in fused "
+                         "graph-captured launches vs the same replicas run one by one; adjoint: 64^3 "
+                         "forward 2000 steps + backward with checkpoints every 50")
+    ap.add_argument("--replicas", type=int, default=64)
+    ap.add_argument("--zone-variant", type=int, default=0, help="zone-solve kernel (0 = automatic)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -129,12 +135,160 @@ def cpu_baseline(lat, p, micro, seconds):
     }
 
 
+def bench_batched(a):
+    """The replica ensemble: every replica of the batch in each launch, sweeps replayed from
+    HIP graphs, against the same replicas run one after another as single lattices."""
+    import numpy as np
+    import torch
+
+    from paper_1009_0457_amd import hmc as H
+    from paper_1009_0457_amd.synth import batched_configs
+
+    cfgs = batched_configs(a.replicas)
+    log(f"[bench] building {len(cfgs)} replica microstructures")
+    micros = []
+    for i, c in enumerate(cfgs):
+        micros.append(c.microstructure())
+        if i % 16 == 15:
+            log(f"[bench]   {i + 1} replicas built")
+    common = H.hmc_default_params(16, 26, 2)
+    common.refresh_every = cfgs[0].refresh_every
+    reps = []
+    for c, m in zip(cfgs, micros):
+        r = H.hmc_default_replica(common, c.K, m.Q)
+        r.kT, r.seed = c.kT, c.philox_seed
+        for i in range(6):
+            r.sigma_MPa[i] = float(c.sigma_MPa[i])
+        reps.append(r)
+    sites = sum(c.K ** 3 for c in cfgs)
+    b = H.Batch(common, reps)
+    for i, m in enumerate(micros):
+        b.set_replica(i, m.euler, m.spins)
+    log(f"[bench] {sites} sites; cold refresh")
+    b.stress_refresh(-1, True)
+    b.set_graphs(True)
+    for _ in range(a.warmup):
+        b.sweep(1)
+    b.synchronize()
+    b.reset_stats()
+    t0 = time.perf_counter()
+    b.sweep(a.steps)
+    b.synchronize()
+    t_batch = time.perf_counter() - t0
+    st = b.stats()
+    b.set_zone_screen(True)
+    b.reset_stats()
+    t0 = time.perf_counter()
+    b.sweep(a.steps)
+    b.synchronize()
+    t_scr = time.perf_counter() - t0
+    st_scr = b.stats()
+    b.close()
+    log(f"[bench] batch {t_batch:.3f} s ({sites * a.steps / t_batch:.4e} site-trials/s), screened {t_scr:.3f} s")
+    # the same replicas one after another, each a single lattice with graph-replayed sweeps
+    # (cold refresh and warm-up untimed)
+    t_plain = 0.0
+    for c, m, r in zip(cfgs, micros, reps):
+        p = H.hmc_params.from_buffer_copy(common)
+        p.K, p.kT, p.lambda_el, p.seed = r.K, r.kT, r.lambda_el, r.seed
+        p.glob_alpha, p.glob_beta, p.glob_alphaE = r.glob_alpha, r.glob_beta, r.glob_alphaE
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            lat = H.Lattice(p, m.Q, stream=s)
+            lat.set_orientations(m.euler)
+            lat.set_spins(m.spins)
+            lat.set_load(list(r.sigma_MPa))
+            lat.stress_refresh(-1, True)
+            lat.set_graphs(True)
+            for _ in range(a.warmup):
+                lat.sweep(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lat.sweep(a.steps)
+            s.synchronize()
+            t_plain += time.perf_counter() - t0
+            lat.close()
+    log(f"[bench] replicas alone: {t_plain:.3f} s")
+    trials = sites * a.steps
+    out = {
+        "metric": "site-trials/sec of the replica ensemble (fused launches, graph-replayed sweeps)",
+        "value": trials / t_batch, "unit": "site-trials/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": t_batch / a.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched: {len(cfgs)} replicas, K in {{32,48,64,96}}, 8 grains per 16^3, uniaxial "
+                               f"0-300 MPa on random axes, kT 0.3-1.0, 26 neighbours, 5^3 zone x 200, refresh every "
+                               f"{common.refresh_every}", "sites": sites},
+        "replicas_alone": {"value": trials / t_plain, "ms_per_step": t_plain / a.steps * 1e3},
+        "batched_over_alone": t_plain / t_batch,
+        "zone_solve_fraction": st["zone_solves"] / trials,
+        "screened": {"value": trials / t_scr, "zone_solve_fraction": st_scr["zone_solves"] / trials},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(a):
+    """Forward (cold start + 2000 explicit steps, checkpoint every 50) and backward of the
+    stored elastic energy on the 64^3 / 500-grain workload."""
+    import numpy as np
+    import torch
+
+    from paper_1009_0457_amd import hmc as H
+    from paper_1009_0457_amd.synth import adjoint_config
+
+    micro, sig, probe = adjoint_config()
+    K = micro.K
+    p = H.hmc_default_params(K, 26, 2)
+    lat = H.Lattice(p, micro.Q)
+    lat.set_orientations(micro.euler)
+    lat.set_spins(micro.spins)
+    lat.set_load(sig)
+    lat.elastic_forward(2000, 50)          # warm-up (allocates the adjoint workspace)
+    lat.elastic_backward(1.0)
+    tf, tb = [], []
+    for _ in range(max(1, a.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U = lat.elastic_forward(2000, 50)
+        t1 = time.perf_counter()
+        ge, gs = lat.elastic_backward(1.0)
+        t2 = time.perf_counter()
+        tf.append(t1 - t0)
+        tb.append(t2 - t1)
+    lat.set_profiling(True)
+    lat.kernel_times()
+    lat.elastic_forward(2000, 50)
+    kf = lat.kernel_times()
+    lat.elastic_backward(1.0)
+    kb = lat.kernel_times()
+    lat.close()
+    f, bk = float(np.median(tf)), float(np.median(tb))
+    step_bytes = REFRESH_BYTES_PER_NODE_STEP * K ** 3
+    fs = kf["refresh_step"]
+    out = {
+        "metric": "forward+backward of dU/d(Euler angles, load) per second (64^3, 2000 steps, checkpoint 50)",
+        "value": 1.0 / (f + bk), "unit": "gradients/s", "n_gpus": 1, "steps": len(tf), "warmup": 1,
+        "ms_per_step": (f + bk) * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"adjoint: {K}^3, {micro.Q} grains, 6 stress components U(+-200 MPa), 2000 explicit "
+                               f"steps, checkpoint every 50"},
+        "forward_s": f, "backward_s": bk, "backward_over_forward": bk / f, "U": U,
+        "forward_step_GBs": step_bytes * fs["launches"] / (fs["total_ms"] * 1e-3) / 1e9 if fs["launches"] else None,
+        "adjoint_step_ms": kb["refresh_step"]["total_ms"] / max(1, kb["refresh_step"]["launches"]),
+        "forward_step_ms": fs["total_ms"] / max(1, fs["launches"]),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in "
                                    "DESIGN.md but not built", "n_gpus": a.gpus}))
         sys.exit(2)
+    if a.workload == "batched":
+        return bench_batched(a)
+    if a.workload == "adjoint":
+        return bench_adjoint(a)
     import numpy as np
     import torch
 
@@ -160,6 +314,7 @@ def main():
     p.refresh_every = cfg.refresh_every
     p.proposal = 0 if a.proposal == "neighbor" else 1
     p.seed = cfg.philox_seed
+    p.zone_variant = a.zone_variant
     lat = H.Lattice(p, micro.Q)
     lat.set_orientations(micro.euler)
     lat.set_spins(micro.spins)
@@ -234,7 +389,7 @@ def main():
                                f"biaxial 150/150 MPa, kT {p.kT}, 5^3 zone x {p.zone_steps} steps, refresh every "
                                f"{p.refresh_every} sweeps x {p.refresh_steps} steps, proposal {a.proposal}",
                    "K": K, "neighbors": p.neighbors, "zone_h": p.zone_h, "zone_steps": p.zone_steps,
-                   "proposal": a.proposal},
+                   "proposal": a.proposal, "zone_variant": a.zone_variant},
         "zone_solve_fraction": solves / trials,
         "zone_solves_per_s": solves / elapsed,
         "acceptance": st["accepted"] / max(1, st["real_flips"]),

@@ -29,7 +29,9 @@ hmc_status check_common(const hmc_params* p)
     if (p->neighbors != 6 && p->neighbors != 26) return HMC_EINVAL;
     if (p->proposal != 0 && p->proposal != 1) return HMC_EINVAL;
     if (p->zone_h < 0 || p->zone_h > 3) return HMC_EINVAL;
-    if (p->zone_variant < 0 || p->zone_variant > 2 || (p->zone_variant == 2 && p->zone_h > 2)) return HMC_EINVAL;
+    if (p->zone_variant < 0 || p->zone_variant > 3 || (p->zone_variant == 2 && p->zone_h > 2) ||
+        (p->zone_variant == 3 && (p->zone_h < 1 || p->zone_h > 2)))
+        return HMC_EINVAL;
     if (p->zone_screen != 0 && p->zone_screen != 1) return HMC_EINVAL;
     if (p->zone_steps < 0 || p->refresh_steps < 0 || p->cold_steps < 0 || p->refresh_every < 1) return HMC_EINVAL;
     const double vals[] = {p->J, p->kT, p->C11, p->C12, p->C44, p->lambda_el, p->zone_alpha, p->zone_beta,

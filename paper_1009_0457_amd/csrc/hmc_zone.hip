@@ -544,6 +544,314 @@ __global__ __launch_bounds__(256, 2) void k_zone_col(ZoneArgs a)
     }
 }
 
+// ------------------------------------------------------------------------------------
+// Lane-shift variant (1 <= h <= 2).  Each trial occupies LT = (2h+2)(2h+1) consecutive lanes
+// of one wavefront, laid out as lane l = x + (2h+2) y over node columns x in [0, 2h+2),
+// y in [0, 2h+1); a wavefront holds 64 / LT trials and never splits one.  Lane (x, y) owns
+// node column (x, y) in registers and, for x < 2h+1, the voxel column (x, y); the top row
+// of node columns (y = 2h+1) is split into (column, component) items held by the trial's
+// first 3(2h+2) lanes, their displacements in LDS.
+//
+// Neighbours in x are the next lane, so they move through the wavefront with DPP shifts
+// (no LDS):  the +x node column's displacement, the +x+y column's (the +x lane's +y
+// read), the force a voxel sends to its +x node column, and the force it sends to its
+// +x+y column, which the receiving lane folds into its own +y force.  Only the +y
+// exchange goes through LDS: one read and one write per node and component per phase, at
+// lane-consecutive addresses, with the trials of a wavefront placed 30 (mod 64) floats
+// apart for h = 2 (12 for h = 1) so that no access has a bank conflict.  Lanes with
+// x = 2h+1 and lanes beyond the last trial of a wavefront carry zero stiffness, so they
+// run the same instructions and produce zero forces; the control flow is uniform across
+// the work-group, which the cross-lane moves need.  Stiffnesses are pre-scaled by
+// -alpha/16 (see the column variant for the 1/16), so a stress evaluation
+// yields the step's force directly and the heavy-ball update is w <- beta w + f; the final
+// energy undoes the scale in FP64.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ float from_next_lane(float v)   // lane i receives lane i+1's v (0 at the end)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
+__device__ __forceinline__ float from_prev_lane(float v)   // lane i receives lane i-1's v (0 at lane 0)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+
+// Corner forces of one node layer of a voxel column, from the layer sums PL, U = QL + RL,
+// V = RL - QL of its stress rows: the own node column gets V - PL, the +x column PL + V, the
+// +y column U - PL and the +x+y column PL + U.  The receiving side of the +x moves is
+// folded in here: the own column adds what lane l-1 sends it, and the +y force written
+// to LDS includes lane l-1's +x+y share.
+__device__ __forceinline__ void node_forces(float PL, float U, float V, float beta, float& w, float& ny)
+{
+    const float m = from_prev_lane(PL) - PL;
+    w = beta * w + ((V + from_prev_lane(V)) + m);
+    ny = (U + from_prev_lane(U)) + m;
+}
+
+template <int H>
+struct LaneShiftShape {
+    static constexpr int N = 2 * H + 1, NN = N + 1;
+    static constexpr int LT = NN * N;                   // lanes per trial
+    static constexpr int TW = 64 / LT;                  // trials per wavefront
+    static constexpr int Z = 4 * TW;                    // trials per work-group
+    static constexpr int ROW = NN * NN;                 // floats per (component, layer) row
+    static constexpr int BODY = 3 * NN * ROW;
+    // block stride: >= BODY + NN (zero gap), and = LT (mod 64) for conflict-free addressing
+    static constexpr int TB = BODY + NN + ((LT - (BODY + NN) % 64) % 64 + 64) % 64;
+    static constexpr int PAD = 8;                       // leading zeros of the force array
+};
+
+template <int H>
+__global__ __launch_bounds__(256, 2) void k_zone_lane(ZoneArgs a)
+{
+    using S = LaneShiftShape<H>;
+    constexpr int N = S::N, NN = S::NN, LT = S::LT, TW = S::TW, Z = S::Z, ROW = S::ROW, TB = S::TB;
+    static_assert(H >= 1 && TW >= 1 && 3 * NN <= LT, "lane-shift variant needs 1 <= h <= 2");
+    static_assert(TB % 64 == LT % 64 && TB >= S::BODY + NN, "block stride");
+
+    // blocks 0..Z-1 belong to trials, block Z to lanes outside every trial
+    __shared__ float s_u[(Z + 1) * TB];                   // node displacements
+    __shared__ __align__(16) float s_n[S::PAD + (Z + 1) * TB];   // forces sent to the +y neighbour
+    __shared__ float s_ctr[Z][18];                        // eps_p[6], t[6], -alpha/4 t[6]
+    static_assert(sizeof(s_n) >= 256 * sizeof(double), "energy scratch does not fit");
+    double* s_red = reinterpret_cast<double*>(s_n);
+
+    const int t = threadIdx.x;
+    const int wave = t >> 6, li = t & 63;
+    const int slot = li / LT;
+    const bool member = slot < TW;
+    const int l = member ? li - slot * LT : li - TW * LT;
+    const int zs = member ? wave * TW + slot : Z;
+    const int x = l % NN, y = l / NN;
+    const bool vox = member && x < N;
+    const bool centre_col = vox && x == H && y == H;
+    const uint32_t count = *a.count;
+    const float alpha16 = a.alpha * 0.0625f, beta = a.beta;
+
+    float* const ub = s_u + zs * TB;                      // this lane's trial block
+    float* const nbk = s_n + S::PAD + zs * TB;
+    // top-row item: node column (l % NN, N), component l / NN, for the first 3 NN lanes
+    const bool xon = member && l < 3 * NN;
+    const int xcol = l % NN + NN * N, xj = xon ? l / NN : 0;
+
+    for (uint32_t base = blockIdx.x * (uint32_t)Z; base < count; base += gridDim.x * (uint32_t)Z) {
+        const uint32_t e = base + (uint32_t)(member ? zs : 0);
+        const bool active = member && e < count;
+
+        float Cv[N][21];
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+#pragma unroll
+            for (int i = 0; i < 21; ++i) Cv[k][i] = 0.f;
+        if (active) {
+            const TrialEntry ent = a.list[e];
+            const TrialCtx tc = trial_ctx(a, ent.qr);
+            const int K = tc.K;
+            const int q_new = (int)(ent.qr & 0xffffu);
+            const int px = (int)(ent.site % (uint32_t)K);
+            const int py = (int)((ent.site / (uint32_t)K) % (uint32_t)K);
+            const int pz = (int)(ent.site / ((uint32_t)K * (uint32_t)K));
+            if (l == 0) {
+                const int q_old = tc.spins[ent.site];
+                float c[21], sp[6], s[6], eps[6], tt[6];
+#pragma unroll
+                for (int I = 0; I < 6; ++I) sp[I] = a.sigma[(int64_t)I * a.plane + tc.site_off + ent.site];
+                load_sym(tc.Stab + (int64_t)q_old * kTab, c);
+                symv(c, sp, eps);
+                load_sym(tc.Ctab + (int64_t)q_new * kTab, c);
+                symv(c, eps, tt);
+                load_sym(tc.Ctab + (int64_t)q_old * kTab, c);
+                symv(c, eps, s);
+#pragma unroll
+                for (int I = 0; I < 6; ++I) {
+                    const float ti = tt[I] - s[I];
+                    s_ctr[zs][I] = eps[I];
+                    s_ctr[zs][6 + I] = ti;
+                    s_ctr[zs][12 + I] = (-4.f * alpha16) * ti;
+                }
+            }
+            if (vox) {
+                const int gx = ((px + x - H) % K + K) % K, gy = ((py + y - H) % K + K) % K;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const int gz = ((pz + k - H) % K + K) % K;
+                    const int g = (centre_col && k == H) ? q_new : (int)tc.spins[gx + K * (gy + K * gz)];
+                    load_sym(tc.Ctab + (int64_t)g * kTab, Cv[k]);
+#pragma unroll
+                    for (int i = 0; i < 21; ++i) Cv[k][i] *= -alpha16;
+                }
+            }
+        }
+        for (int i = t; i < (Z + 1) * TB; i += 256) s_u[i] = 0.f;
+        for (int i = t; i < S::PAD + (Z + 1) * TB; i += 256) s_n[i] = 0.f;
+        __syncthreads();
+        float ts[6];
+#pragma unroll
+        for (int I = 0; I < 6; ++I) ts[I] = (active && centre_col) ? s_ctr[zs][12 + I] : 0.f;
+
+        float du[NN][3], w[NN][3], xw[NN];
+#pragma unroll
+        for (int z = 0; z < NN; ++z) {
+            xw[z] = 0.f;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) du[z][j] = w[z][j] = 0.f;
+        }
+
+        for (int step = 0; step < a.nr; ++step) {
+            // ---- voxels: strain, (scaled) stress, corner forces ----
+            {
+                float cn[3], cnn[3];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) cn[j] = ub[(j * NN + 0) * ROW + l + NN];
+                float Lp[3][3], Pp[3], Qp[3], Rp[3];
+#pragma unroll
+                for (int z = 0; z < NN; ++z) {
+                    if (z + 1 < NN) {
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) cnn[j] = ub[(j * NN + z + 1) * ROW + l + NN];
+                    }
+                    // with A = u(x,y) + u(x,y+1) and D = u(x,y+1) - u(x,y), the +x lane's A and D
+                    // complete the four-column x-difference, y-difference and sum
+                    float Lc[3][3];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const float A = du[z][j] + cn[j], D = cn[j] - du[z][j];
+                        Lc[0][j] = from_next_lane(A) - A;
+                        Lc[1][j] = D + from_next_lane(D);
+                        Lc[2][j] = A + from_next_lane(A);
+                    }
+                    if (z >= 1) {
+                        const int k = z - 1;
+                        float g[3][3];
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            g[j][0] = Lp[0][j] + Lc[0][j];
+                            g[j][1] = Lp[1][j] + Lc[1][j];
+                            g[j][2] = Lc[2][j] - Lp[2][j];
+                        }
+                        const float ev[6] = {g[0][0], g[1][1], g[2][2], g[1][2] + g[2][1], g[0][2] + g[2][0],
+                                             g[0][1] + g[1][0]};
+                        float sv[6];
+                        symv(Cv[k], ev, sv);
+                        if (k == H) {
+#pragma unroll
+                            for (int I = 0; I < 6; ++I) sv[I] += ts[I];
+                        }
+                        const float P[3] = {sv[0], sv[5], sv[4]};
+                        const float Q[3] = {sv[5], sv[1], sv[3]};
+                        const float R[3] = {sv[4], sv[3], sv[2]};
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            const float PL = k == 0 ? P[j] : Pp[j] + P[j];
+                            const float QL = k == 0 ? Q[j] : Qp[j] + Q[j];
+                            const float RL = k == 0 ? -R[j] : Rp[j] - R[j];
+                            node_forces(PL, QL + RL, RL - QL, beta, w[k][j], nbk[(j * NN + k) * ROW + l]);
+                            Pp[j] = P[j];
+                            Qp[j] = Q[j];
+                            Rp[j] = R[j];
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        cn[j] = cnn[j];
+#pragma unroll
+                        for (int r = 0; r < 3; ++r) Lp[r][j] = Lc[r][j];
+                    }
+                }
+                // top node layer: only voxel N-1 below it
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    node_forces(Pp[j], Qp[j] + Rp[j], Rp[j] - Qp[j], beta, w[NN - 1][j],
+                                nbk[(j * NN + NN - 1) * ROW + l]);
+            }
+            __syncthreads();
+            // ---- nodes: add the force from the -y neighbour, step, publish ----
+#pragma unroll
+            for (int z = 0; z < NN; ++z)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    w[z][j] += nbk[(j * NN + z) * ROW + l - NN];
+                    du[z][j] += w[z][j];
+                    ub[(j * NN + z) * ROW + l] = du[z][j];
+                }
+            if (xon) {
+#pragma unroll
+                for (int z = 0; z < NN; ++z) {
+                    xw[z] = beta * xw[z] + nbk[(xj * NN + z) * ROW + xcol - NN];
+                    ub[(xj * NN + z) * ROW + xcol] += xw[z];
+                }
+            }
+            __syncthreads();
+        }
+
+        // ---- energy at the final displacement: 1/2 e.C e over the zone + t.e at the centre ----
+        double quad = 0.0, lin = 0.0;
+        {
+            float Lp[3][3];
+#pragma unroll
+            for (int z = 0; z < NN; ++z) {
+                float Lc[3][3];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const float uc = ub[(j * NN + z) * ROW + l + NN];
+                    const float A = du[z][j] + uc, D = uc - du[z][j];
+                    Lc[0][j] = from_next_lane(A) - A;
+                    Lc[1][j] = D + from_next_lane(D);
+                    Lc[2][j] = A + from_next_lane(A);
+                }
+                if (z >= 1) {
+                    const int k = z - 1;
+                    float g[3][3];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        g[j][0] = 0.25f * (Lp[0][j] + Lc[0][j]);
+                        g[j][1] = 0.25f * (Lp[1][j] + Lc[1][j]);
+                        g[j][2] = 0.25f * (Lc[2][j] - Lp[2][j]);
+                    }
+                    const float ev[6] = {g[0][0], g[1][1], g[2][2], g[1][2] + g[2][1], g[0][2] + g[2][0],
+                                         g[0][1] + g[1][0]};
+                    float sv[6];
+                    symv(Cv[k], ev, sv);
+#pragma unroll
+                    for (int I = 0; I < 6; ++I) quad += (double)ev[I] * (double)sv[I];
+                    if (k == H && centre_col) {
+#pragma unroll
+                        for (int I = 0; I < 6; ++I) lin += (double)s_ctr[zs][6 + I] * (double)ev[I];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) Lp[r][j] = Lc[r][j];
+            }
+        }
+        const double part = vox ? quad * (-0.5 / (double)alpha16) + lin : 0.0;
+        __syncthreads();   // the force array becomes the reduction scratch
+        s_red[t] = part;
+        __syncthreads();
+        if (active && l == 0) {
+            const TrialEntry ent = a.list[e];
+            const TrialCtx tc = trial_ctx(a, ent.qr);
+            double sum = 0.0;
+            for (int i = 0; i < LT; ++i) sum += s_red[t + i];
+            double base_e = 0.0;
+#pragma unroll
+            for (int I = 0; I < 6; ++I) base_e += 0.5 * (double)s_ctr[zs][I] * (double)s_ctr[zs][6 + I];
+            const double dPi = base_e + sum;
+            const double dE = tc.J * (double)ent.gb + tc.lambda * dPi;
+            const bool accept = (dE <= 0.0) || ((double)ent.r1 < ldexp(exp(-dE / tc.kT), 32));
+            a.acc[e] = accept ? 1 : 0;
+            if (a.rec) {
+                a.rec[tc.site_off + ent.site].dPi = (float)dPi;
+                a.rec[tc.site_off + ent.site].flags = 1 | 4 | (accept ? 2 : 0);
+            }
+            atomicAdd(&a.stats[kStatSolves], 1ull);
+            if (accept) atomicAdd(&a.stats[kStatAccepted], 1ull);
+        }
+        __syncthreads();   // LDS is reused by the next group of trials
+    }
+}
+
 hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
 {
     ZoneArgs a;
@@ -562,10 +870,24 @@ hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
     a.alpha = (float)c->p.zone_alpha;
     a.beta = (float)c->p.zone_beta;
     const int h = c->p.zone_h;
-    // column variant for h <= 2 unless the wavefront-per-trial variant is asked for
-    const bool column = (c->p.zone_variant == 0 && h <= 2) || (c->p.zone_variant == 2 && h <= 2);
+    // automatic: lane shifts for h = 1, 2; node columns for h = 0; a wavefront per trial for h = 3
+    const int v = c->p.zone_variant;
+    const bool laneshift = (v == 0 && (h == 1 || h == 2)) || v == 3;
+    const bool column = !laneshift && ((v == 0 && h <= 2) || v == 2);
     const int tok = prof_begin(c, kProfZone);
-    if (column) {
+    if (laneshift) {
+        const int per_wg = h == 1 ? LaneShiftShape<1>::Z : LaneShiftShape<2>::Z;
+        int64_t g = (c->max_list + per_wg - 1) / per_wg;
+        const int64_t cap = 256 * 2 * 4;
+        if (g > cap) g = cap;
+        if (g < 1) g = 1;
+        const dim3 grid((unsigned)g), block(256);
+        switch (h) {
+            case 1: hipLaunchKernelGGL(k_zone_lane<1>, grid, block, 0, c->stream, a); break;
+            case 2: hipLaunchKernelGGL(k_zone_lane<2>, grid, block, 0, c->stream, a); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else if (column) {
         const int nn = 2 * h + 2, per_wg = 256 / (nn * nn);
         int64_t g = (c->max_list + per_wg - 1) / per_wg;
         const int64_t cap = 256 * 2 * 4;   // a few resident work-groups per CU

@@ -87,7 +87,7 @@ def test_grain_table_derivatives_match_central_differences_of_the_oracle():
     ("K", 15, H.HMC_ESHAPE), ("K", 0, H.HMC_ESHAPE), ("K", 2048, H.HMC_ESHAPE),
     ("neighbors", 8, H.HMC_EINVAL), ("zone_h", 4, H.HMC_EINVAL), ("kT", 0.0, H.HMC_EINVAL),
     ("kT", float("nan"), H.HMC_ENUMERIC), ("proposal", 2, H.HMC_EINVAL), ("refresh_every", 0, H.HMC_EINVAL),
-    ("C44", -1.0, H.HMC_ENUMERIC),
+    ("C44", -1.0, H.HMC_ENUMERIC), ("zone_variant", 4, H.HMC_EINVAL), ("zone_variant", -1, H.HMC_EINVAL),
 ])
 def test_create_validates_before_touching_the_device(field, value, status):
     L = _lib_or_skip()
@@ -98,6 +98,15 @@ def test_create_validates_before_touching_the_device(field, value, status):
     buf = (C.c_char * 512)()
     st = L.hmc_create(C.byref(p), 8, C.cast(buf, C.c_void_p), 512, None, C.byref(ctx))
     assert st == status and not ctx.value
+
+
+def test_zone_variant_limits():
+    L = _lib_or_skip()
+    for h, variant, ok in ((0, 3, False), (3, 3, False), (3, 2, False), (1, 3, True), (2, 3, True), (3, 1, True),
+                           (0, 2, True)):
+        p = H.hmc_default_params(16, 26, h)
+        p.zone_variant = variant
+        assert (L.hmc_workspace_bytes(C.byref(p), 8) > 0) == ok, (h, variant)
 
 
 def test_shape_limits():

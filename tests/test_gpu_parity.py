@@ -195,7 +195,7 @@ def compare_pass(rec, ref, sites, p, tol, what):
     return int(solved.sum()), int(near.sum()), float((err / tol[solved]).max()) if solved.any() else 0.0
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 @pytest.mark.parametrize("cfg", ["tiny", "tiny-uniform"])
 def test_elastic_lockstep_tiny_workload(cfg, variant):
     c = tiny_config()
@@ -234,7 +234,7 @@ def test_elastic_lockstep_tiny_workload(cfg, variant):
     lat.close()
 
 
-@pytest.mark.parametrize("which,variant", [("full", 1), ("full", 0), ("large", 0)])
+@pytest.mark.parametrize("which,variant", [("full", 1), ("full", 2), ("full", 0), ("large", 0)])
 def test_elastic_lockstep_sampled_at_workload_size(which, variant):
     """Full-size workloads in the benchmark's launch configuration (variant 0 = automatic,
     what the benchmark runs): every trial of a colour pass runs on the GPU; the oracle
@@ -266,7 +266,7 @@ def test_elastic_lockstep_sampled_at_workload_size(which, variant):
     lat.close()
 
 
-@pytest.mark.parametrize("h,variant", [(0, 0), (0, 1), (1, 0), (2, 1), (2, 2), (3, 0)])
+@pytest.mark.parametrize("h,variant", [(0, 0), (0, 1), (1, 0), (1, 2), (2, 0), (2, 1), (2, 2), (3, 0)])
 def test_elastic_lockstep_zone_sizes(h, variant):
     """Every zone size the library accepts, both kernels, on a lattice whose edge is not a
     multiple of the zone (ragged wrap-around), with uniform proposals (many solves)."""
