@@ -79,6 +79,7 @@ def parse():
                          "forward 2000 steps + backward with checkpoints every 50")
     ap.add_argument("--replicas", type=int, default=64)
     ap.add_argument("--zone-variant", type=int, default=0, help="zone-solve kernel (0 = automatic)")
+    ap.add_argument("--tile-z", type=int, default=0, help="node layers per block of the explicit step (0 = automatic)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -153,6 +154,7 @@ def bench_batched(a):
             log(f"[bench]   {i + 1} replicas built")
     common = H.hmc_default_params(16, 26, 2)
     common.refresh_every = cfgs[0].refresh_every
+    common.refresh_tile_z = a.tile_z
     reps = []
     for c, m in zip(cfgs, micros):
         r = H.hmc_default_replica(common, c.K, m.Q)
@@ -238,6 +240,7 @@ def bench_adjoint(a):
     micro, sig, probe = adjoint_config()
     K = micro.K
     p = H.hmc_default_params(K, 26, 2)
+    p.refresh_tile_z = a.tile_z
     lat = H.Lattice(p, micro.Q)
     lat.set_orientations(micro.euler)
     lat.set_spins(micro.spins)
@@ -271,6 +274,7 @@ def bench_adjoint(a):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"adjoint: {K}^3, {micro.Q} grains, 6 stress components U(+-200 MPa), 2000 explicit "
                                f"steps, checkpoint every 50"},
+        "tile_z": a.tile_z,
         "forward_s": f, "backward_s": bk, "backward_over_forward": bk / f, "U": U,
         "forward_step_GBs": step_bytes * fs["launches"] / (fs["total_ms"] * 1e-3) / 1e9 if fs["launches"] else None,
         "adjoint_step_ms": kb["refresh_step"]["total_ms"] / max(1, kb["refresh_step"]["launches"]),
@@ -315,6 +319,7 @@ def main():
     p.proposal = 0 if a.proposal == "neighbor" else 1
     p.seed = cfg.philox_seed
     p.zone_variant = a.zone_variant
+    p.refresh_tile_z = a.tile_z
     lat = H.Lattice(p, micro.Q)
     lat.set_orientations(micro.euler)
     lat.set_spins(micro.spins)

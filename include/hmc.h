@@ -75,6 +75,12 @@ typedef struct {
                                Metropolis threshold (plus a floating-point margin) rejects it.
                                Decisions are those of the full solve; the trial's record then
                                carries flag 8 and no dPi.  0: solve every real flip. */
+    int32_t refresh_tile_z; /* node layers per work-group of the explicit global step and of its
+                               adjoint: 1, 2, 4 or 8, or 0 to pick the deepest tile that still
+                               gives at least 512 work-groups (shallower tiles recompute more
+                               halo voxels but fill the GPU on small lattices).  Other values:
+                               HMC_EINVAL. */
+    int32_t reserved0;      /* must be 0 */
     double J;               /* grain-boundary energy per unlike bond (MC units) */
     double kT;              /* Monte Carlo temperature T_mc (MC units), > 0 */
     double C11, C12, C44;   /* cubic stiffness in the crystal frame (GPa) */

@@ -16,11 +16,11 @@
 // term dU/dtheta_g += sum_{v in g} 1/2 eps_v . (dC_g/dtheta) eps_v; after step 0 the start
 // E_0 = mean(S_q) Sigma adds E^_0 . (n_g/K^3) (dS_g/dtheta) Sigma and mean(S) E^_0.
 //
-// The stiffness-derivative terms are accumulated per voxel as the symmetric 6x6 matrix
-// M_v = 1/2 eps_n eps_n^T - sum_t sym(eta_t eps_t^T) (FP64) and contracted with dC/dtheta
-// once at the end; per-grain sums use 64-bit fixed-point atomics (order-independent, so
-// the result is deterministic).  Forward states are recovered from checkpoints every
-// `ckpt_every` steps by recomputing one segment at a time.
+// The stiffness-derivative terms are contracted with the voxel's dC/dtheta (three angles)
+// as they arise and summed per voxel in FP64: G_v = 1/2 eps_n.dC eps_n - sum_t eta_t.dC eps_t;
+// per-grain sums of G use 64-bit fixed-point atomics (order-independent, so the result is
+// deterministic).  Forward states are recovered from checkpoints every `ckpt_every` steps
+// by recomputing one segment at a time.  The adjoint step is tiled like the forward step.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -32,7 +32,7 @@ namespace hmc {
 constexpr double kFixScale = 1099511627776.0;   // 2^40
 
 struct AdjLayout {
-    size_t ckpt, seg_u, seg_E, ub0, ub1, wb0, wb1, M, dC, dS, adj, grad, total;
+    size_t ckpt, seg_u, seg_E, ub0, ub1, wb0, wb1, G, dC, dS, adj, grad, total;
     int n_ck;          // checkpoints of segment starts
     size_t ck_bytes;   // bytes per checkpoint: u, w planes then 12 doubles
 };
@@ -59,7 +59,7 @@ static AdjLayout adj_layout(const hmc_ctx_s* c, int n_steps, int k)
     L.ub1 = take(3 * n3 * sizeof(float));
     L.wb0 = take(3 * n3 * sizeof(float));
     L.wb1 = take(3 * n3 * sizeof(float));
-    L.M = take(21 * n3 * sizeof(double));
+    L.G = take(3 * n3 * sizeof(double));
     L.dC = take(Q * 3 * kTab * sizeof(float));
     L.dS = take(Q * 3 * kTab * sizeof(float));
     L.adj = take(64 * sizeof(double));
@@ -71,35 +71,36 @@ static AdjLayout adj_layout(const hmc_ctx_s* c, int n_steps, int k)
 // Slots of the adjoint's small state block.
 enum AdjSlot { kEb = 0, kWEb = 6, kB = 12, kSigb = 18, kWEt = 24, kE0 = 30, kAdjDoubles = 64 };
 
-__device__ __forceinline__ void sym_acc(double* __restrict__ M, int64_t n3, int64_t v, const float x[6],
-                                        const float y[6], double scale)
+// eta . (dC_q eps) for the three angles q of grain g
+__device__ __forceinline__ void angle_contractions(const float* __restrict__ dC, int g, const float eta[6],
+                                                  const float eps[6], double out[3])
 {
-    // M_IJ += scale * (x_I y_J + x_J y_I) / 2 over the upper triangle
-    int k = 0;
 #pragma unroll
-    for (int I = 0; I < 6; ++I)
+    for (int q = 0; q < 3; ++q) {
+        float d6[6];
+        symv21(dC + ((int64_t)g * 3 + q) * kTab, eps, d6);
+        double v = 0.0;
 #pragma unroll
-        for (int J = I; J < 6; ++J) {
-            const double s = 0.5 * ((double)x[I] * (double)y[J] + (double)x[J] * (double)y[I]);
-            M[(int64_t)k * n3 + v] += scale * s;
-            ++k;
-        }
+        for (int I = 0; I < 6; ++I) v += (double)eta[I] * (double)d6[I];
+        out[q] = v;
+    }
 }
 
 struct AdjInitArgs {
     const int16_t* spins;
     const float* Ctab;
+    const float* dC;
     const float* u;
     float* ub;
     float* wb;
-    double* M;
+    double* G;
     double* partials;
     const double* state;
     int K;
     int64_t n3;
 };
 
-// Final-state adjoint: u^_n = sum_v B_v^T sigma_v, M_v = 1/2 eps eps^T, partial sums of sigma.
+// Final-state adjoint: u^_n = sum_v B_v^T sigma_v, G_v = 1/2 eps.dC eps, partial sums of sigma.
 __global__ __launch_bounds__(256) void k_adj_init(AdjInitArgs a)
 {
     const int K = a.K;
@@ -125,14 +126,10 @@ __global__ __launch_bounds__(256) void k_adj_init(AdjInitArgs a)
             if (c == 0) {
 #pragma unroll
                 for (int I = 0; I < 6; ++I) acc[I] += (double)s[I];
-                int k = 0;
+                double gq[3];
+                angle_contractions(a.dC, g, e, e, gq);
 #pragma unroll
-                for (int I = 0; I < 6; ++I)
-#pragma unroll
-                    for (int J = I; J < 6; ++J) {
-                        a.M[(int64_t)k * a.n3 + n] = 0.5 * (double)e[I] * (double)e[J];
-                        ++k;
-                    }
+                for (int q = 0; q < 3; ++q) a.G[(int64_t)q * a.n3 + n] = 0.5 * gq[q];
             }
         }
 #pragma unroll
@@ -147,6 +144,7 @@ __global__ __launch_bounds__(256) void k_adj_init(AdjInitArgs a)
 struct AdjStepArgs {
     const int16_t* spins;
     const float* Ctab;
+    const float* dC;         // Q x 3 x kTab
     const float* ub_in;
     float* ub_out;
     const float* wb_in;      // read at neighbour nodes: ping-pong like ub
@@ -154,85 +152,146 @@ struct AdjStepArgs {
     const float* u_t;        // forward displacement of step t
     const double* E_t;       // forward macroscopic strain of step t (6)
     const double* adj;       // b
-    double* M;
+    double* G;               // 3 planes
     double* partials;
-    int K;
-    int64_t n3;
+    const RepDev* reps;
     float alpha, beta;
 };
 
-__device__ __forceinline__ void adj_a_strain(const float* __restrict__ ub, const float* __restrict__ wb, int64_t n3,
-                                             int K, int vx, int vy, int vz, float alpha, const float b3[6],
-                                             float eta[6])
-{
-    // eta = B_v a + b/K^3 with a = alpha (w^ + u^) at the voxel's corners
-    const int x1 = wrapk(vx + 1, K), y1 = wrapk(vy + 1, K), z1 = wrapk(vz + 1, K);
-    const int64_t n[8] = {
-        vx + (int64_t)K * (vy + (int64_t)K * vz), x1 + (int64_t)K * (vy + (int64_t)K * vz),
-        vx + (int64_t)K * (y1 + (int64_t)K * vz), x1 + (int64_t)K * (y1 + (int64_t)K * vz),
-        vx + (int64_t)K * (vy + (int64_t)K * z1), x1 + (int64_t)K * (vy + (int64_t)K * z1),
-        vx + (int64_t)K * (y1 + (int64_t)K * z1), x1 + (int64_t)K * (y1 + (int64_t)K * z1)};
-    float g[3][3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const float* uj = ub + (int64_t)j * n3;
-        const float* wj = wb + (int64_t)j * n3;
-        float cv[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) cv[c] = alpha * (wj[n[c]] + uj[n[c]]);
-        g[j][0] = 0.25f * ((cv[1] - cv[0]) + (cv[3] - cv[2]) + (cv[5] - cv[4]) + (cv[7] - cv[6]));
-        g[j][1] = 0.25f * ((cv[2] + cv[3]) - (cv[0] + cv[1]) + (cv[6] + cv[7]) - (cv[4] + cv[5]));
-        g[j][2] = 0.25f * ((cv[4] + cv[5] + cv[6] + cv[7]) - (cv[0] + cv[1] + cv[2] + cv[3]));
-    }
-    eta[0] = b3[0] + g[0][0];
-    eta[1] = b3[1] + g[1][1];
-    eta[2] = b3[2] + g[2][2];
-    eta[3] = b3[3] + g[1][2] + g[2][1];
-    eta[4] = b3[4] + g[0][2] + g[2][0];
-    eta[5] = b3[5] + g[0][1] + g[1][0];
-}
-
+// One adjoint step, tiled as the forward step: a block owns a 32 x 8 x tile_z node tile;
+// the nodal field a = alpha (w~) and the forward displacement u_t pass through two-slot LDS
+// rings of node layers (one-node halo), the adjoint stresses tau through a ring of voxel
+// layers.  Each voxel's tau is formed once per tile; the voxels the block owns also add
+// their angle contractions to G and their tau to the block's partial sums.
 __global__ __launch_bounds__(256) void k_adj_step(AdjStepArgs a)
 {
-    const int K = a.K;
+    constexpr int NX = kTileX + 2, NY = kTileY + 2, VX = kTileX + 1, VY = kTileY + 1;
+    __shared__ float sa[2][3][NY][NX];
+    __shared__ float sf[2][3][NY][NX];
+    __shared__ float ss[2][6][VY][VX];
+
+    const RepDev R = a.reps[0];
+    const int K = R.K;
+    const int64_t n3 = R.n3;
+    const int ntx = (K + kTileX - 1) / kTileX, nty = (K + kTileY - 1) / kTileY, tz = R.tile_z;
+    int b = (int)blockIdx.x;
+    const int bx = b % ntx;
+    b /= ntx;
+    const int by = b % nty, bz = b / nty;
+    const int x0 = bx * kTileX, y0 = by * kTileY, z0 = bz * tz;
+    const int z1 = (z0 + tz < K) ? z0 + tz : K;
     float b3[6], E[6];
-    const double inv_n3 = 1.0 / (double)a.n3;
+    const double inv_n3 = 1.0 / (double)n3;
 #pragma unroll
     for (int I = 0; I < 6; ++I) {
         b3[I] = (float)(a.adj[kB + I] * inv_n3);
         E[I] = (float)a.E_t[I];
     }
+    const float alpha = a.alpha, beta = a.beta;
+    const int t = threadIdx.x, lx = t % kTileX, ly = t / kTileX;
+    const int nx = x0 + lx, ny = y0 + ly;
+    const bool own = nx < K && ny < K;
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < a.n3; n += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(n % K), y = (int)((n / K) % K), z = (int)(n / ((int64_t)K * K));
-        float f[3] = {0.f, 0.f, 0.f};
+
+    auto load_nodes = [&](int slot, int z) {
+        const int64_t zoff = (int64_t)K * K * wrapk(z, K);
+        for (int i = t; i < NX * NY; i += 256) {
+            const int ix = i % NX, iy = i / NX;
+            const int64_t n = wrapk(x0 - 1 + ix, K) + (int64_t)K * wrapk(y0 - 1 + iy, K) + zoff;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const int ca = c & 1, cb = (c >> 1) & 1, cc = c >> 2;
-            const int vx = wrapk(x - ca, K), vy = wrapk(y - cb, K), vz = wrapk(z - cc, K);
-            float eta[6], tau[6];
-            adj_a_strain(a.ub_in, a.wb_in, a.n3, K, vx, vy, vz, a.alpha, b3, eta);
-            const int g = a.spins[vx + (int64_t)K * (vy + (int64_t)K * vz)];
-            symv21(a.Ctab + (int64_t)g * kTab, eta, tau);
-            const float sx = ca ? 0.25f : -0.25f, sy = cb ? 0.25f : -0.25f, sz = cc ? 0.25f : -0.25f;
-            f[0] += sx * tau[0] + sy * tau[5] + sz * tau[4];
-            f[1] += sx * tau[5] + sy * tau[1] + sz * tau[3];
-            f[2] += sx * tau[4] + sy * tau[3] + sz * tau[2];
-            if (c == 0) {
-#pragma unroll
-                for (int I = 0; I < 6; ++I) acc[I] += (double)tau[I];
-                float eps[6];
-                voxel_strain(a.u_t, a.n3, K, vx, vy, vz, E, eps);
-                sym_acc(a.M, a.n3, n, eta, eps, -1.0);
+            for (int j = 0; j < 3; ++j) {
+                sa[slot][j][iy][ix] = alpha * (a.wb_in[j * n3 + n] + a.ub_in[j * n3 + n]);
+                sf[slot][j][iy][ix] = a.u_t[j * n3 + n];
             }
         }
+    };
+    // centre-point gradient of a node field held in two ring slots
+    auto gradient = [&](float (*f)[3][NY][NX], int lo, int hi, int ix, int iy, float g[3][3]) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            const int64_t idx = (int64_t)j * a.n3 + n;
-            const float u_in = a.ub_in[idx];
-            a.ub_out[idx] = u_in - f[j];
-            a.wb_out[idx] = a.beta * (a.wb_in[idx] + u_in);
+            const float c0 = f[lo][j][iy][ix], c1 = f[lo][j][iy][ix + 1];
+            const float c2 = f[lo][j][iy + 1][ix], c3 = f[lo][j][iy + 1][ix + 1];
+            const float c4 = f[hi][j][iy][ix], c5 = f[hi][j][iy][ix + 1];
+            const float c6 = f[hi][j][iy + 1][ix], c7 = f[hi][j][iy + 1][ix + 1];
+            g[j][0] = 0.25f * ((c1 - c0) + (c3 - c2) + (c5 - c4) + (c7 - c6));
+            g[j][1] = 0.25f * ((c2 + c3) - (c0 + c1) + (c6 + c7) - (c4 + c5));
+            g[j][2] = 0.25f * ((c4 + c5 + c6 + c7) - (c0 + c1 + c2 + c3));
         }
+    };
+    auto voxel_layer = [&](int vs, int lo, int hi, int z, bool owned_layer) {
+        const int64_t zoff = (int64_t)K * K * wrapk(z, K);
+        for (int i = t; i < VX * VY; i += 256) {
+            const int ix = i % VX, iy = i / VX;
+            float g[3][3];
+            gradient(sa, lo, hi, ix, iy, g);
+            float eta[6], tau[6];
+            eta[0] = b3[0] + g[0][0];
+            eta[1] = b3[1] + g[1][1];
+            eta[2] = b3[2] + g[2][2];
+            eta[3] = b3[3] + g[1][2] + g[2][1];
+            eta[4] = b3[4] + g[0][2] + g[2][0];
+            eta[5] = b3[5] + g[0][1] + g[1][0];
+            const int gx = x0 - 1 + ix, gy = y0 - 1 + iy;
+            const int64_t v = wrapk(gx, K) + (int64_t)K * wrapk(gy, K) + zoff;
+            const int q = a.spins[v];
+            symv21(a.Ctab + (int64_t)q * kTab, eta, tau);
+#pragma unroll
+            for (int I = 0; I < 6; ++I) ss[vs][I][iy][ix] = tau[I];
+            if (owned_layer && ix >= 1 && iy >= 1 && gx < K && gy < K) {
+#pragma unroll
+                for (int I = 0; I < 6; ++I) acc[I] += (double)tau[I];
+                gradient(sf, lo, hi, ix, iy, g);
+                float eps[6];
+                eps[0] = E[0] + g[0][0];
+                eps[1] = E[1] + g[1][1];
+                eps[2] = E[2] + g[2][2];
+                eps[3] = E[3] + g[1][2] + g[2][1];
+                eps[4] = E[4] + g[0][2] + g[2][0];
+                eps[5] = E[5] + g[0][1] + g[1][0];
+                double gq[3];
+                angle_contractions(a.dC, q, eta, eps, gq);
+#pragma unroll
+                for (int qa = 0; qa < 3; ++qa) a.G[(int64_t)qa * n3 + v] -= gq[qa];
+            }
+        }
+    };
+
+    load_nodes(0, z0 - 1);
+    load_nodes(1, z0);
+    __syncthreads();
+    voxel_layer(0, 0, 1, z0 - 1, false);
+    int nlo = 1, vprev = 0;
+    for (int z = z0; z < z1; ++z) {
+        const int nhi = 1 - nlo, vcur = 1 - vprev;
+        __syncthreads();
+        load_nodes(nhi, z + 1);
+        __syncthreads();
+        voxel_layer(vcur, nlo, nhi, z, true);
+        __syncthreads();
+        if (own) {
+            float f[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int ca = c & 1, cb = (c >> 1) & 1, cc = c >> 2;
+                const int vx = lx + 1 - ca, vy = ly + 1 - cb, vsl = cc ? vprev : vcur;
+                const float s0 = ss[vsl][0][vy][vx], s1 = ss[vsl][1][vy][vx], s2 = ss[vsl][2][vy][vx];
+                const float s3 = ss[vsl][3][vy][vx], s4 = ss[vsl][4][vy][vx], s5 = ss[vsl][5][vy][vx];
+                const float sx = ca ? 0.25f : -0.25f, sy = cb ? 0.25f : -0.25f, sz = cc ? 0.25f : -0.25f;
+                f[0] += sx * s0 + sy * s5 + sz * s4;
+                f[1] += sx * s5 + sy * s1 + sz * s3;
+                f[2] += sx * s4 + sy * s3 + sz * s2;
+            }
+            const int64_t n = nx + (int64_t)K * (ny + (int64_t)K * z);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int64_t idx = (int64_t)j * n3 + n;
+                const float u_in = a.ub_in[idx];
+                a.ub_out[idx] = u_in - f[j];
+                a.wb_out[idx] = beta * (a.wb_in[idx] + u_in);
+            }
+        }
+        nlo = nhi;
+        vprev = vcur;
     }
     block_sum_to<6>(a.partials, acc);
 }
@@ -277,9 +336,8 @@ __global__ __launch_bounds__(256) void k_adj_E(double* adj, const double* partia
 struct AdjGradArgs {
     const int16_t* spins;
     const float* Stab;
-    const float* dC;    // Q x 3 x kTab
-    const float* dS;
-    const double* M;
+    const float* dS;    // Q x 3 x kTab
+    const double* G;
     const double* adj;  // E^_0 at kEb
     double Sigma[6];
     unsigned long long* grad;   // Q x 3 fixed point
@@ -287,7 +345,7 @@ struct AdjGradArgs {
     int64_t n3;
 };
 
-// Per voxel: the three stiffness-angle contractions dC : M_v plus the start-strain term
+// Per voxel: the three stiffness-angle sums G_v plus the start-strain term
 // (1/K^3) E^_0 . dS Sigma into its grain (fixed-point atomics); partial sums of S E^_0.
 __global__ __launch_bounds__(256) void k_adj_grad(AdjGradArgs a)
 {
@@ -304,15 +362,13 @@ __global__ __launch_bounds__(256) void k_adj_grad(AdjGradArgs a)
         const int g = a.spins[v];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const float* dc = a.dC + ((int64_t)g * 3 + q) * kTab;
             const float* ds = a.dS + ((int64_t)g * 3 + q) * kTab;
-            double val = 0.0;
+            double val = a.G[(int64_t)q * a.n3 + v];
             int k = 0;
 #pragma unroll
             for (int I = 0; I < 6; ++I)
 #pragma unroll
                 for (int J = I; J < 6; ++J) {
-                    val += (I == J ? 1.0 : 2.0) * (double)dc[k] * a.M[(int64_t)k * a.n3 + v];
                     // start term: E^_0 . (dS Sigma) with the symmetric dS
                     const double sym = (I == J) ? Eb[I] * a.Sigma[I] : Eb[I] * a.Sigma[J] + Eb[J] * a.Sigma[I];
                     val += inv_n3 * (double)ds[k] * sym;
@@ -471,7 +527,7 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
     double* seg_E = (double*)(base + L.seg_E);
     float* ub[2] = {(float*)(base + L.ub0), (float*)(base + L.ub1)};
     float* wb[2] = {(float*)(base + L.wb0), (float*)(base + L.wb1)};
-    double* M = (double*)(base + L.M);
+    double* G = (double*)(base + L.G);
     float* dC = (float*)(base + L.dC);
     float* dS = (float*)(base + L.dS);
     double* adj = (double*)(base + L.adj);
@@ -503,7 +559,7 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
     if (st != HMC_OK) return st;
     c->cur_u = 0;
     {
-        AdjInitArgs a{c->d.spins, c->d.Ctab, c->d.u[0], ub[0], wb[0], M, c->d.partials, c->d.state, R.K, n3};
+        AdjInitArgs a{c->d.spins, c->d.Ctab, dC, c->d.u[0], ub[0], wb[0], G, c->d.partials, c->d.state, R.K, n3};
         hipLaunchKernelGGL(k_adj_init, dim3(nb), dim3(256), 0, c->stream, a);
         hipLaunchKernelGGL(k_adj_E, dim3(1), dim3(256), 0, c->stream, adj, c->d.partials, nb, 0, (double)R.glob_beta,
                            R.glob_alphaE);
@@ -528,6 +584,7 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
             AdjStepArgs a;
             a.spins = c->d.spins;
             a.Ctab = c->d.Ctab;
+            a.dC = dC;
             a.ub_in = ub[cur_b];
             a.ub_out = ub[1 - cur_b];
             a.wb_in = wb[cur_b];
@@ -535,16 +592,15 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
             a.u_t = seg_u + (size_t)(t - t0) * 3 * n3;
             a.E_t = seg_E + (size_t)(t - t0) * 8;
             a.adj = adj;
-            a.M = M;
+            a.G = G;
             a.partials = c->d.partials;
-            a.K = R.K;
-            a.n3 = n3;
+            a.reps = c->d.reps;
             a.alpha = R.glob_alpha;
             a.beta = R.glob_beta;
             const int tok = prof_begin(c, kProfRefreshStep);
-            hipLaunchKernelGGL(k_adj_step, dim3(nb), dim3(256), 0, c->stream, a);
+            hipLaunchKernelGGL(k_adj_step, dim3(c->tile_blocks), dim3(256), 0, c->stream, a);
             prof_end(c, tok);
-            hipLaunchKernelGGL(k_adj_E, dim3(1), dim3(256), 0, c->stream, adj, c->d.partials, nb, 1,
+            hipLaunchKernelGGL(k_adj_E, dim3(1), dim3(256), 0, c->stream, adj, c->d.partials, c->tile_blocks, 1,
                                (double)R.glob_beta, R.glob_alphaE);
             ATRY(hipGetLastError(), "backward: step");
             cur_b = 1 - cur_b;
@@ -555,9 +611,8 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
         AdjGradArgs a;
         a.spins = c->d.spins;
         a.Stab = c->d.Stab;
-        a.dC = dC;
         a.dS = dS;
-        a.M = M;
+        a.G = G;
         a.adj = adj;
         for (int I = 0; I < 6; ++I) a.Sigma[I] = R.Sigma[I];
         a.grad = grad;

@@ -33,6 +33,10 @@ hmc_status check_common(const hmc_params* p)
         (p->zone_variant == 3 && (p->zone_h < 1 || p->zone_h > 2)))
         return HMC_EINVAL;
     if (p->zone_screen != 0 && p->zone_screen != 1) return HMC_EINVAL;
+    if (p->refresh_tile_z != 0 && p->refresh_tile_z != 1 && p->refresh_tile_z != 2 && p->refresh_tile_z != 4 &&
+        p->refresh_tile_z != 8)
+        return HMC_EINVAL;
+    if (p->reserved0 != 0) return HMC_EINVAL;
     if (p->zone_steps < 0 || p->refresh_steps < 0 || p->cold_steps < 0 || p->refresh_every < 1) return HMC_EINVAL;
     const double vals[] = {p->J, p->kT, p->C11, p->C12, p->C44, p->lambda_el, p->zone_alpha, p->zone_beta,
                            p->glob_alpha, p->glob_beta, p->glob_alphaE};
@@ -77,16 +81,30 @@ struct Layout {
     size_t spins, Ctab, Stab, sigma, u0, u1, w, list, accept, state, partials, counters, stats, thr, tex, hist,
         bonds, reps, pass_rep, node_rep, tile_rep, sweep, total;
     int64_t sites, grains, max_list;
-    int pass_blocks, node_blocks, tile_blocks;
+    int pass_blocks, node_blocks, tile_blocks, tile_z;
     bool elastic;
 };
 
 int64_t n3_of(int K) { return (int64_t)K * K * K; }
 
+// Node layers per block of the tiled explicit step: the caller's choice, else the deepest
+// tile that still launches at least 512 blocks over all replicas (2 per compute unit).
+int tile_depth_of(const hmc_params* p, int n, const hmc_replica* r)
+{
+    if (p->refresh_tile_z > 0) return p->refresh_tile_z;
+    for (int tz = kTileZMax; tz > 1; tz /= 2) {
+        int64_t blocks = 0;
+        for (int i = 0; i < n; ++i) blocks += tile_blocks_of(r[i].K, tz);
+        if (blocks >= 512) return tz;
+    }
+    return 1;
+}
+
 Layout layout_of(const hmc_params* p, int n, const hmc_replica* r)
 {
     Layout L{};
     const int C = colours_of(p->neighbors);
+    L.tile_z = tile_depth_of(p, n, r);
     for (int i = 0; i < n; ++i) {
         const int64_t n3 = n3_of(r[i].K);
         L.sites += n3;
@@ -96,7 +114,7 @@ Layout layout_of(const hmc_params* p, int n, const hmc_replica* r)
         int64_t nb = (n3 + kSiteBlock - 1) / kSiteBlock;
         if (nb > kMaxChunkBlocks) nb = kMaxChunkBlocks;
         L.node_blocks += (int)nb;
-        L.tile_blocks += tile_blocks_of(r[i].K);
+        L.tile_blocks += tile_blocks_of(r[i].K, L.tile_z);
         L.elastic = L.elastic || r[i].lambda_el != 0.0;
     }
     size_t o = 0;
@@ -476,7 +494,8 @@ hmc_status build_context(const hmc_params* p, int n, const hmc_replica* r, void*
         int64_t nb = (R.n3 + kSiteBlock - 1) / kSiteBlock;
         R.node_blocks = (int)(nb > kMaxChunkBlocks ? kMaxChunkBlocks : nb);
         R.tile_first = tf;
-        R.tile_blocks = tile_blocks_of(R.K);
+        R.tile_z = L.tile_z;
+        R.tile_blocks = tile_blocks_of(R.K, R.tile_z);
         R.J = p->J;
         R.kT = r[i].kT;
         R.lambda = r[i].lambda_el;

@@ -36,8 +36,8 @@ __device__ __forceinline__ int wrapm(int a, int K)
     return a < 0 ? a + K : a;
 }
 
-// Tiled explicit step.  A block owns a 32 x 8 tile of nodes in x, y and marches through 8
-// node layers in z.  Node layers (with a one-node halo) and voxel stress layers (with the
+// Tiled explicit step.  A block owns a 32 x 8 tile of nodes in x, y and marches through
+// tile_z node layers in z.  Node layers (with a one-node halo) and voxel stress layers (with the
 // low halo voxel) live in two-slot LDS rings, so each voxel stress is formed once per tile
 // (1.3x with halos) instead of once per corner node (8x).  The arithmetic per voxel and per
 // node, and the order of the 8 corner contributions, are those of the untiled step.
@@ -50,13 +50,13 @@ __global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
     const int r = a.tile_rep[blockIdx.x];
     const RepDev R = a.reps[r];
     const int K = R.K;
-    const int ntx = (K + kTileX - 1) / kTileX, nty = (K + kTileY - 1) / kTileY;
+    const int ntx = (K + kTileX - 1) / kTileX, nty = (K + kTileY - 1) / kTileY, tz = R.tile_z;
     int b = (int)blockIdx.x - R.tile_first;
     const int bx = b % ntx;
     b /= ntx;
     const int by = b % nty, bz = b / nty;
-    const int x0 = bx * kTileX, y0 = by * kTileY, z0 = bz * kTileZ;
-    const int z1 = (z0 + kTileZ < K) ? z0 + kTileZ : K;
+    const int x0 = bx * kTileX, y0 = by * kTileY, z0 = bz * tz;
+    const int z1 = (z0 + tz < K) ? z0 + tz : K;
     const int16_t* spins = a.spins + R.site_off;
     const float* Ctab = a.Ctab + R.grain_off * kTab;
     const float* uin = a.uin + R.site_off;

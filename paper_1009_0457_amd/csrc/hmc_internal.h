@@ -35,24 +35,25 @@ struct TrialEntry {
 constexpr int kMaxReplicas = 4096;
 constexpr int kSiteBlock = 256;        // sites (or nodes) per block of site-parallel kernels
 constexpr int kMaxChunkBlocks = 8192;  // blocks per replica of node-parallel reductions
-constexpr int kTileX = 32, kTileY = 8, kTileZ = 8;   // node tile of the explicit step
+constexpr int kTileX = 32, kTileY = 8;   // node tile of the explicit step in x, y
+constexpr int kTileZMax = 8;             // deepest tile in z (node layers per block)
 
-__host__ __device__ constexpr int tile_blocks_of(int K)
+__host__ __device__ constexpr int tile_blocks_of(int K, int tz)
 {
-    return ((K + kTileX - 1) / kTileX) * ((K + kTileY - 1) / kTileY) * ((K + kTileZ - 1) / kTileZ);
+    return ((K + kTileX - 1) / kTileX) * ((K + kTileY - 1) / kTileY) * ((K + tz - 1) / tz);
 }
 
 // Device description of one replica.
 struct RepDev {
     int32_t K, Kh, Q, proposal;
     int32_t elastic;                 // elastic term on for this replica (lambda != 0, load != 0)
-    int32_t pad0;
+    int32_t tile_z;                  // node layers per block of the tiled explicit step
     int64_t n3;
     int64_t site_off;                // into spins / sigma / u / w planes (sites)
     int64_t grain_off;               // into Ctab / Stab (grains)
     int32_t pass_first, pass_blocks; // blocks of a colour pass (active sites / 256, rounded up)
     int32_t node_first, node_blocks; // blocks of node-parallel kernels (<= kMaxChunkBlocks)
-    int32_t tile_first, tile_blocks; // blocks of the tiled explicit step (32 x 8 x 8 nodes each)
+    int32_t tile_first, tile_blocks; // blocks of the tiled explicit step (32 x 8 x tile_z nodes)
     double J, kT, lambda;
     float glob_alpha, glob_beta;
     double glob_alphaE;

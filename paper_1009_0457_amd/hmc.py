@@ -30,6 +30,7 @@ class hmc_params(C.Structure):
     _fields_ = [("K", C.c_int32), ("neighbors", C.c_int32), ("proposal", C.c_int32), ("zone_h", C.c_int32),
                 ("zone_steps", C.c_int32), ("refresh_every", C.c_int32), ("refresh_steps", C.c_int32),
                 ("cold_steps", C.c_int32), ("zone_variant", C.c_int32), ("zone_screen", C.c_int32),
+                ("refresh_tile_z", C.c_int32), ("reserved0", C.c_int32),
                 ("J", C.c_double), ("kT", C.c_double), ("C11", C.c_double), ("C12", C.c_double),
                 ("C44", C.c_double), ("lambda_el", C.c_double), ("zone_alpha", C.c_double),
                 ("zone_beta", C.c_double), ("glob_alpha", C.c_double), ("glob_beta", C.c_double),

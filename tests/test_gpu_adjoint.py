@@ -36,12 +36,16 @@ def oracle_U(K, q, euler, sig_MPa, p, n):
     return info["U"]
 
 
-def test_adjoint_matches_oracle_central_differences():
+@pytest.mark.parametrize("tile_z", [0, 8])
+def test_adjoint_matches_oracle_central_differences(tile_z):
+    """tile_z 0 (automatic: one node layer per block at this size) and 8 (two blocks in z,
+    the second cut short by the lattice edge)."""
     K, n, every = 12, 100, 30
     m = voronoi_polycrystal(K, 14, 77)
     rng = np.random.default_rng(3)
     sig = rng.uniform(-200, 200, 6)
     p = H.hmc_default_params(K, 26, 1)
+    p.refresh_tile_z = tile_z
     lat = H.Lattice(p, m.Q)
     lat.set_orientations(m.euler)
     lat.set_spins(m.spins)

@@ -119,11 +119,13 @@ def test_zero_load_energy_and_resume():
 # --------------------------------------------------------------------------------------
 # global refresh
 # --------------------------------------------------------------------------------------
-@pytest.mark.parametrize("K,ng,steps", [(8, 5, 300), (16, 8, 500), (20, 30, 200)])
-def test_refresh_matches_oracle(K, ng, steps):
-    say(f"[refresh] K={K} grains={ng} steps={steps}")
+@pytest.mark.parametrize("K,ng,steps,tile_z", [(8, 5, 300, 0), (16, 8, 500, 0), (20, 30, 200, 0), (20, 30, 200, 2),
+                                               (20, 30, 200, 8), (18, 20, 150, 4), (18, 20, 150, 8)])
+def test_refresh_matches_oracle(K, ng, steps, tile_z):
+    """Every tile depth of the explicit step, including tiles cut short by the lattice edge."""
+    say(f"[refresh] K={K} grains={ng} steps={steps} tile_z={tile_z}")
     micro = voronoi_polycrystal(K, ng, 9)
-    p, lat = make_lattice(K, 26, 1, micro)
+    p, lat = make_lattice(K, 26, 1, micro, refresh_tile_z=tile_z)
     sig = np.array([120.0, -40.0, 80.0, 30.0, -20.0, 10.0])
     lat.set_load(sig)
     lat.stress_refresh(steps, True)
