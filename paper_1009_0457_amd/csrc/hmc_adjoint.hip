@@ -460,7 +460,7 @@ hmc_status check_adj(hmc_ctx c, int n_steps, int k, void* ws, size_t bytes, AdjL
 }  // namespace
 
 namespace hmc {
-hipError_t launch_global_step_ptrs(hmc_ctx_s* c, const float* uin, float* uout);
+hipError_t launch_global_step_ptrs(hmc_ctx_s* c, const float* uin, float* uout, double* E_record);
 }
 
 extern "C" {
@@ -574,10 +574,12 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
         if (st != HMC_OK) return st;
         for (int t = t0; t < t1; ++t) {
             float* ut = seg_u + (size_t)(t - t0) * 3 * n3;
-            ATRY(hipMemcpyAsync(seg_E + (size_t)(t - t0) * 8, c->d.state + kE, 6 * sizeof(double),
-                                hipMemcpyDeviceToDevice, c->stream),
-                 "backward: recompute");
-            if (t + 1 < t1) ATRY(launch_global_step_ptrs(c, ut, ut + 3 * n3), "backward: recompute");
+            double* Et = seg_E + (size_t)(t - t0) * 8;
+            if (t + 1 < t1)
+                ATRY(launch_global_step_ptrs(c, ut, ut + 3 * n3, Et), "backward: recompute");   // records E_t
+            else
+                ATRY(hipMemcpyAsync(Et, c->d.state + kE, 6 * sizeof(double), hipMemcpyDeviceToDevice, c->stream),
+                     "backward: recompute");
         }
         // adjoint steps t1-1 .. t0
         for (int t = t1 - 1; t >= t0; --t) {

@@ -24,6 +24,7 @@ struct GlobArgs {
     float* w;
     double* partials;
     const double* state;
+    double* E_record;        // optional: receives the step's input E (single lattice)
     const RepDev* reps;
     const int32_t* node_rep;
     const int32_t* tile_rep;
@@ -67,6 +68,7 @@ __global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
     float E[6];
 #pragma unroll
     for (int I = 0; I < 6; ++I) E[I] = (float)st[kE + I];
+    if (a.E_record && (int)blockIdx.x == R.tile_first && threadIdx.x < 6) a.E_record[threadIdx.x] = st[kE + threadIdx.x];
     const float alpha = R.glob_alpha, beta = R.glob_beta;
     const int t = threadIdx.x, lx = t % kTileX, ly = t / kTileX;
     const int nx = x0 + lx, ny = y0 + ly;
@@ -379,6 +381,7 @@ hipError_t launch_global_steps(hmc_ctx_s* c, int n_steps)
     a.w = c->d.w;
     a.partials = c->d.partials;
     a.state = c->d.state;
+    a.E_record = nullptr;
     a.reps = c->d.reps;
     a.node_rep = c->d.node_rep;
     a.tile_rep = c->d.tile_rep;
@@ -402,9 +405,9 @@ hipError_t launch_global_steps(hmc_ctx_s* c, int n_steps)
     return hipGetLastError();
 }
 
-// One explicit step from `uin` to `uout` (single-lattice contexts; used by the adjoint's
-// segment recomputation).
-hipError_t launch_global_step_ptrs(hmc_ctx_s* c, const float* uin, float* uout)
+// One explicit step from `uin` to `uout`, recording its input E into E_record (single-lattice
+// contexts; used by the adjoint's segment recomputation).
+hipError_t launch_global_step_ptrs(hmc_ctx_s* c, const float* uin, float* uout, double* E_record)
 {
     GlobArgs a;
     a.spins = c->d.spins;
@@ -414,6 +417,7 @@ hipError_t launch_global_step_ptrs(hmc_ctx_s* c, const float* uin, float* uout)
     a.w = c->d.w;
     a.partials = c->d.partials;
     a.state = c->d.state;
+    a.E_record = E_record;
     a.reps = c->d.reps;
     a.node_rep = c->d.node_rep;
     a.tile_rep = c->d.tile_rep;
