@@ -576,16 +576,19 @@ __device__ __forceinline__ float from_prev_lane(float v)   // lane i receives la
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 
-// Corner forces of one node layer of a voxel column, from the layer sums PL, U = QL + RL,
-// V = RL - QL of its stress rows: the own node column gets V - PL, the +x column PL + V, the
-// +y column U - PL and the +x+y column PL + U.  The receiving side of the +x moves is
-// folded in here: the own column adds what lane l-1 sends it, and the +y force written
-// to LDS includes lane l-1's +x+y share.
-__device__ __forceinline__ void node_forces(float PL, float U, float V, float beta, float& w, float& ny)
+// Corner forces of one node layer: the transpose of the strain pipeline.  L0, L1, L2 are
+// the layer's weights on its x-difference, y-difference and sum (PL, QL, RL: the stress rows
+// of the voxels below and above, summed or differenced).  Since the layer's x-difference and
+// sum combine A = u(x,y) + u(x,y+1) of this lane and the next, and its y-difference
+// D = u(x,y+1) - u(x,y) of both, A's weight is (L2 - L0) here plus (L2 + L0) of lane l-1 and
+// D's weight is L1 here plus L1 of lane l-1.  The own node gets A^ - D^, the +y node A^ + D^
+// (through LDS).
+__device__ __forceinline__ void node_forces(float L0, float L1, float L2, float beta, float& w, float& ny)
 {
-    const float m = from_prev_lane(PL) - PL;
-    w = beta * w + ((V + from_prev_lane(V)) + m);
-    ny = (U + from_prev_lane(U)) + m;
+    const float Ab = (L2 - L0) + from_prev_lane(L2 + L0);
+    const float Db = L1 + from_prev_lane(L1);
+    w = beta * w + (Ab - Db);
+    ny = Ab + Db;
 }
 
 template <int H>
@@ -745,7 +748,7 @@ __global__ __launch_bounds__(256, 2) void k_zone_lane(ZoneArgs a)
                             const float PL = k == 0 ? P[j] : Pp[j] + P[j];
                             const float QL = k == 0 ? Q[j] : Qp[j] + Q[j];
                             const float RL = k == 0 ? -R[j] : Rp[j] - R[j];
-                            node_forces(PL, QL + RL, RL - QL, beta, w[k][j], nbk[(j * NN + k) * ROW + l]);
+                            node_forces(PL, QL, RL, beta, w[k][j], nbk[(j * NN + k) * ROW + l]);
                             Pp[j] = P[j];
                             Qp[j] = Q[j];
                             Rp[j] = R[j];
@@ -761,7 +764,7 @@ __global__ __launch_bounds__(256, 2) void k_zone_lane(ZoneArgs a)
                 // top node layer: only voxel N-1 below it
 #pragma unroll
                 for (int j = 0; j < 3; ++j)
-                    node_forces(Pp[j], Qp[j] + Rp[j], Rp[j] - Qp[j], beta, w[NN - 1][j],
+                    node_forces(Pp[j], Qp[j], Rp[j], beta, w[NN - 1][j],
                                 nbk[(j * NN + NN - 1) * ROW + l]);
             }
             __syncthreads();
