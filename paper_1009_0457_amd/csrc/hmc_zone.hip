@@ -561,7 +561,8 @@ __global__ __launch_bounds__(256, 2) void k_zone_col(ZoneArgs a)
 // apart for h = 2 (12 for h = 1) so that no access has a bank conflict.  Lanes with
 // x = 2h+1 and lanes beyond the last trial of a wavefront carry zero stiffness, so they
 // run the same instructions and produce zero forces; the control flow is uniform across
-// the work-group, which the cross-lane moves need.  Stiffnesses are pre-scaled by
+// the work-group, which the cross-lane moves need.  A work-group is one wavefront, so its
+// barriers never wait for another wavefront.  Stiffnesses are pre-scaled by
 // -alpha/16 (see the column variant for the 1/16), so a stress evaluation
 // yields the step's force directly and the heavy-ball update is w <- beta w + f; the final
 // energy undoes the scale in FP64.
@@ -596,7 +597,8 @@ struct LaneShiftShape {
     static constexpr int N = 2 * H + 1, NN = N + 1;
     static constexpr int LT = NN * N;                   // lanes per trial
     static constexpr int TW = 64 / LT;                  // trials per wavefront
-    static constexpr int Z = 4 * TW;                    // trials per work-group
+    static constexpr int THREADS = 64;                  // one wavefront per work-group
+    static constexpr int Z = TW;                        // trials per work-group
     static constexpr int ROW = NN * NN;                 // floats per (component, layer) row
     static constexpr int BODY = 3 * NN * ROW;
     // block stride: >= BODY + NN (zero gap), and = LT (mod 64) for conflict-free addressing
@@ -605,7 +607,7 @@ struct LaneShiftShape {
 };
 
 template <int H>
-__global__ __launch_bounds__(256, 2) void k_zone_lane(ZoneArgs a)
+__global__ __launch_bounds__(64, 2) void k_zone_lane(ZoneArgs a)
 {
     using S = LaneShiftShape<H>;
     constexpr int N = S::N, NN = S::NN, LT = S::LT, TW = S::TW, Z = S::Z, ROW = S::ROW, TB = S::TB;
@@ -616,7 +618,8 @@ __global__ __launch_bounds__(256, 2) void k_zone_lane(ZoneArgs a)
     __shared__ float s_u[(Z + 1) * TB];                   // node displacements
     __shared__ __align__(16) float s_n[S::PAD + (Z + 1) * TB];   // forces sent to the +y neighbour
     __shared__ float s_ctr[Z][18];                        // eps_p[6], t[6], -alpha/4 t[6]
-    static_assert(sizeof(s_n) >= 256 * sizeof(double), "energy scratch does not fit");
+    static_assert(S::THREADS == 64, "one wavefront per work-group");
+    static_assert(sizeof(s_n) >= S::THREADS * sizeof(double), "energy scratch does not fit");
     double* s_red = reinterpret_cast<double*>(s_n);
 
     const int t = threadIdx.x;
@@ -685,8 +688,8 @@ __global__ __launch_bounds__(256, 2) void k_zone_lane(ZoneArgs a)
                 }
             }
         }
-        for (int i = t; i < (Z + 1) * TB; i += 256) s_u[i] = 0.f;
-        for (int i = t; i < S::PAD + (Z + 1) * TB; i += 256) s_n[i] = 0.f;
+        for (int i = t; i < (Z + 1) * TB; i += S::THREADS) s_u[i] = 0.f;
+        for (int i = t; i < S::PAD + (Z + 1) * TB; i += S::THREADS) s_n[i] = 0.f;
         __syncthreads();
         float ts[6];
 #pragma unroll
@@ -881,10 +884,10 @@ hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
     if (laneshift) {
         const int per_wg = h == 1 ? LaneShiftShape<1>::Z : LaneShiftShape<2>::Z;
         int64_t g = (c->max_list + per_wg - 1) / per_wg;
-        const int64_t cap = 256 * 2 * 4;
+        const int64_t cap = 256 * 4 * 2 * 4;   // a few resident wavefronts per SIMD
         if (g > cap) g = cap;
         if (g < 1) g = 1;
-        const dim3 grid((unsigned)g), block(256);
+        const dim3 grid((unsigned)g), block(LaneShiftShape<2>::THREADS);
         switch (h) {
             case 1: hipLaunchKernelGGL(k_zone_lane<1>, grid, block, 0, c->stream, a); break;
             case 2: hipLaunchKernelGGL(k_zone_lane<2>, grid, block, 0, c->stream, a); break;
