@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--replicas", type=int, default=64)
     ap.add_argument("--zone-variant", type=int, default=0, help="zone-solve kernel (0 = automatic)")
     ap.add_argument("--tile-z", type=int, default=0, help="node layers per block of the explicit step (0 = automatic)")
+    ap.add_argument("--zero-load", action="store_true",
+                    help="the same lattice with no load: the elastic term is off and every trial is decided "
+                         "by the integer threshold table inside the colour pass")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -308,6 +311,8 @@ def main():
         log(f"[bench] copy probe: {a.copy_probe_mib} MiB read + {a.copy_probe_mib} MiB written")
         del src, dst
     cfg = large_config()
+    if a.zero_load:
+        cfg = cfg.zero_load()
     K = a.K or cfg.K
     log(f"[bench] building {K}^3 microstructure with {cfg.n_grains} grains")
     micro = voronoi_polycrystal(K, cfg.n_grains if K == cfg.K else max(8, cfg.n_grains * K ** 3 // cfg.K ** 3),
@@ -324,8 +329,9 @@ def main():
     lat.set_orientations(micro.euler)
     lat.set_spins(micro.spins)
     lat.set_load(cfg.sigma_MPa)
-    log(f"[bench] cold refresh ({p.cold_steps} steps)")
-    lat.stress_refresh(-1, True)
+    if not a.zero_load:
+        log(f"[bench] cold refresh ({p.cold_steps} steps)")
+        lat.stress_refresh(-1, True)
     torch.cuda.synchronize()
     log(f"[bench] warmup {a.warmup} sweeps")
     for _ in range(a.warmup):
@@ -366,6 +372,16 @@ def main():
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE, profiles/counters_large128.md)",
             "avg_launch_ms": round(zt["total_ms"] / max(1, zt["launches"]), 4),
             "flop_per_solve": fps, "solves_per_launch": round(solves / max(1, zt["launches"]), 1)}
+    pk = kt["potts"]
+    potts_roof = None
+    if pk["launches"]:
+        colours = 8 if p.neighbors == 26 else 2
+        bytes_pass = (2 * colours + 2) * K ** 3 / colours      # (2C+2) B per site-trial of the class
+        ach = bytes_pass * pk["launches"] / (pk["total_ms"] * 1e-3) / 1e9
+        potts_roof = {"kernel": "colour pass", "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
+                      "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
+                      "avg_launch_ms": round(pk["total_ms"] / pk["launches"], 4),
+                      "note": "(2C+2) bytes of spins per site-trial (the lattice read once per pass)"}
     rs = kt["refresh_step"]
     refresh_roof = None
     if rs["launches"]:
@@ -391,7 +407,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"large-{K}: {K}^3 periodic, 26 neighbours / 8 colours, {micro.Q} Voronoi grains, "
-                               f"biaxial 150/150 MPa, kT {p.kT}, 5^3 zone x {p.zone_steps} steps, refresh every "
+                               f"{'no load (elastic term off)' if a.zero_load else 'biaxial 150/150 MPa'}, kT {p.kT}, "
+                               f"5^3 zone x {p.zone_steps} steps, refresh every "
                                f"{p.refresh_every} sweeps x {p.refresh_steps} steps, proposal {a.proposal}",
                    "K": K, "neighbors": p.neighbors, "zone_h": p.zone_h, "zone_steps": p.zone_steps,
                    "proposal": a.proposal, "zone_variant": a.zone_variant},
@@ -400,8 +417,13 @@ def main():
         "acceptance": st["accepted"] / max(1, st["real_flips"]),
         "roofline": roof,
         "refresh_roofline": refresh_roof,
+        "potts_roofline": potts_roof,
         "kernel_ms": {k: round(v["total_ms"], 3) for k, v in kt.items()},
     }
+    if a.zero_load:
+        lat.close()
+        print(json.dumps(out), flush=True)
+        return
     # the same workload with the lower-bound screen (decision-exact; fewer zone solves)
     lat.set_zone_screen(True)
     lat.reset_stats()

@@ -118,28 +118,45 @@ __device__ __forceinline__ void slot_offset(int k, int& dx, int& dy, int& dz)
     }
 }
 
-// Wave-aggregated append: returns this lane's slot (valid where pred is true).
-__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred)
+// Block-aggregated append and counts (256 threads, 4 wavefronts): one atomic per block
+// for the list and one per statistic, instead of one per wavefront -- same-address
+// atomics serialise in L2, and a colour pass has thousands of wavefronts.  Returns this
+// thread's list slot (valid where `append` is true).  Reached by every thread of the block.
+__device__ __forceinline__ uint32_t block_append_and_count(uint32_t* list_count, bool append,
+                                                           unsigned long long* stats, int slot_a, bool count_a,
+                                                           int slot_b, bool count_b)
 {
-    const unsigned long long mask = __ballot(pred);
-    if (mask == 0) return 0;
-    const int lane = __lane_id();
-    const int leader = __ffsll((long long)mask) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
-    base = __shfl(base, leader);
-    const unsigned long long below = (lane == 0) ? 0ull : (mask & ((~0ull) >> (64 - lane)));
-    return base + (uint32_t)__popcll(below);
-}
-
-__device__ __forceinline__ void wave_count(unsigned long long* ctr, bool pred)
-{
-    const unsigned long long mask = __ballot(pred);
-    if (mask != 0 && __lane_id() == __ffsll((long long)mask) - 1)
-        atomicAdd(ctr, (unsigned long long)__popcll(mask));
+    __shared__ uint32_t s_n[3][4];
+    __shared__ uint32_t s_base;
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const unsigned long long m = __ballot(append);
+    const unsigned long long ma = __ballot(count_a);
+    const unsigned long long mb = __ballot(count_b);
+    if (lane == 0) {
+        s_n[0][wid] = (uint32_t)__popcll(m);
+        s_n[1][wid] = (uint32_t)__popcll(ma);
+        s_n[2][wid] = (uint32_t)__popcll(mb);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t n = s_n[0][0] + s_n[0][1] + s_n[0][2] + s_n[0][3];
+        s_base = n ? atomicAdd(list_count, n) : 0u;
+    } else if (threadIdx.x == 64) {
+        const uint32_t n = s_n[1][0] + s_n[1][1] + s_n[1][2] + s_n[1][3];
+        if (n) atomicAdd(&stats[slot_a], (unsigned long long)n);
+    } else if (threadIdx.x == 128) {
+        const uint32_t n = s_n[2][0] + s_n[2][1] + s_n[2][2] + s_n[2][3];
+        if (n) atomicAdd(&stats[slot_b], (unsigned long long)n);
+    }
+    __syncthreads();
+    uint32_t off = s_base;
+    for (int w = 0; w < wid; ++w) off += s_n[0][w];
+    const unsigned long long below = (lane == 0) ? 0ull : (m & ((~0ull) >> (64 - lane)));
+    return off + (uint32_t)__popcll(below);
 }
 
 // One block covers 256 active sites of one replica (the replica is uniform per block).
+static_assert(kSiteBlock == 256, "the block-aggregated append assumes four wavefronts");
 template <int M>
 __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
 {
@@ -213,23 +230,19 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
         // same-colour sites are never neighbours: nothing else in this pass reads `site`
         if (accepted) spins[site] = (int16_t)q_new;
     }
-    // wave-collective tail, reached by every lane of the wave (replica uniform per block)
-    if (elastic) {
-        const bool solve = real && !screened;
-        const uint32_t slot = wave_append(a.list_count, solve);
-        wave_count(&a.stats[kStatScreened], screened);
-        if (solve) {
-            TrialEntry e;
-            e.site = site;
-            e.qr = (uint32_t)q_new | ((uint32_t)r << 16);
-            e.gb = gb;
-            e.r1 = r1;
-            a.list[slot] = e;
-        }
-    } else {
-        wave_count(&a.stats[kStatAccepted], accepted);
+    // block-collective tail, reached by every thread (replica uniform per block)
+    const bool solve = elastic && real && !screened;
+    const uint32_t slot = block_append_and_count(a.list_count, solve, a.stats, kStatReal, real,
+                                                 elastic ? kStatScreened : kStatAccepted,
+                                                 elastic ? screened : accepted);
+    if (solve) {
+        TrialEntry e;
+        e.site = site;
+        e.qr = (uint32_t)q_new | ((uint32_t)r << 16);
+        e.gb = gb;
+        e.r1 = r1;
+        a.list[slot] = e;
     }
-    wave_count(&a.stats[kStatReal], real);
 }
 
 // Deferred update of an elastic pass: every accepted entry writes its new state.

@@ -640,6 +640,9 @@ __global__ __launch_bounds__(64, 2) void k_zone_lane(ZoneArgs a)
     const bool xon = member && l < 3 * NN;
     const int xcol = l % NN + NN * N, xj = xon ? l / NN : 0;
 
+    // solves and acceptances are counted per lane and added to the statistics once per
+    // work-group at the end (same-address atomics per trial would serialise in L2)
+    uint32_t n_solved = 0, n_accepted = 0;
     for (uint32_t base = blockIdx.x * (uint32_t)Z; base < count; base += gridDim.x * (uint32_t)Z) {
         const uint32_t e = base + (uint32_t)(member ? zs : 0);
         const bool active = member && e < count;
@@ -851,10 +854,19 @@ __global__ __launch_bounds__(64, 2) void k_zone_lane(ZoneArgs a)
                 a.rec[tc.site_off + ent.site].dPi = (float)dPi;
                 a.rec[tc.site_off + ent.site].flags = 1 | 4 | (accept ? 2 : 0);
             }
-            atomicAdd(&a.stats[kStatSolves], 1ull);
-            if (accept) atomicAdd(&a.stats[kStatAccepted], 1ull);
+            n_solved += 1;
+            n_accepted += accept ? 1 : 0;
         }
         __syncthreads();   // LDS is reused by the next group of trials
+    }
+    // one wavefront per work-group: sum the lane counts across it
+    for (int off = 32; off > 0; off >>= 1) {
+        n_solved += __shfl_xor(n_solved, off);
+        n_accepted += __shfl_xor(n_accepted, off);
+    }
+    if (t == 0 && n_solved) {
+        atomicAdd(&a.stats[kStatSolves], (unsigned long long)n_solved);
+        if (n_accepted) atomicAdd(&a.stats[kStatAccepted], (unsigned long long)n_accepted);
     }
 }
 
