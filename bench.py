@@ -73,10 +73,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--K", type=int, default=0, help="override the lattice edge (diagnostics only)")
-    ap.add_argument("--workload", choices=["large", "batched", "adjoint"], default="large",
+    ap.add_argument("--workload", choices=["large", "batched", "adjoint", "potts", "refresh"], default="large",
                     help="large: the headline 128^3 workload; batched: the 64-replica ensemble in fused "
                          "graph-captured launches vs the same replicas run one by one; adjoint: 64^3 "
-                         "forward 2000 steps + backward with checkpoints every 50")
+                         "forward 2000 steps + backward with checkpoints every 50; potts: zero-load colour "
+                         "passes on a lattice larger than the caches (default 512^3); refresh: explicit global "
+                         "steps on such a lattice")
     ap.add_argument("--replicas", type=int, default=64)
     ap.add_argument("--zone-variant", type=int, default=0, help="zone-solve kernel (0 = automatic)")
     ap.add_argument("--tile-z", type=int, default=0, help="node layers per block of the explicit step (0 = automatic)")
@@ -286,6 +288,116 @@ def bench_adjoint(a):
     print(json.dumps(out), flush=True)
 
 
+def big_lattice(a, default_K=512):
+    """The large workload's grain structure on a bigger lattice (K a multiple of 128: each
+    128^3 Voronoi site refined into a block), for bandwidth measurements beyond the caches."""
+    from paper_1009_0457_amd.synth import large_config, refined_polycrystal, voronoi_polycrystal
+
+    cfg = large_config()
+    K = a.K or default_K
+    if K % cfg.K == 0:
+        micro = refined_polycrystal(K, K // cfg.K, cfg.n_grains, cfg.seed)
+    else:
+        micro = voronoi_polycrystal(K, max(8, cfg.n_grains * K ** 3 // cfg.K ** 3), cfg.seed)
+    return cfg, K, micro
+
+
+def bench_potts(a):
+    """Zero-load colour passes (integer thresholds decide inside the pass) on a lattice whose
+    spins (2 B per site) exceed the 256 MB Infinity Cache."""
+    import numpy as np
+    import torch
+
+    from paper_1009_0457_amd import hmc as H
+
+    cfg, K, micro = big_lattice(a)
+    log(f"[bench] potts: {K}^3, {micro.Q} grains, zero load")
+    p = H.hmc_default_params(K, cfg.neighbors, cfg.zone_h)
+    p.kT = cfg.kT
+    p.proposal = 0 if a.proposal == "neighbor" else 1
+    p.seed = cfg.philox_seed
+    lat = H.Lattice(p, micro.Q)
+    lat.set_orientations(micro.euler)
+    lat.set_spins(micro.spins)
+    lat.set_load(np.zeros(6))
+    for _ in range(a.warmup):
+        lat.sweep(1)
+    torch.cuda.synchronize()
+    lat.reset_stats()
+    lat.kernel_times()
+    lat.set_profiling(True)
+    t0 = time.perf_counter()
+    lat.sweep(a.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    lat.set_profiling(False)
+    kt = lat.kernel_times()["potts"]
+    st = lat.stats()
+    lat.close()
+    colours = 8 if p.neighbors == 26 else 2
+    bytes_pass = (2 * colours + 2) * K ** 3 / colours
+    ms = kt["total_ms"] / max(1, kt["launches"])
+    ach = bytes_pass / (ms * 1e-3) / 1e9
+    out = {"metric": "site-trials/sec at zero load (colour passes, integer Metropolis thresholds)",
+           "value": a.steps * K ** 3 / el, "unit": "site-trials/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": el / a.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "int16", "data": "synthetic",
+           "config": {"workload": f"potts-{K}: {K}^3 periodic, 26 neighbours / 8 colours, the 128^3 4000-grain "
+                                  f"Voronoi structure refined x{K // 128 if K % 128 == 0 else 1}, no load, kT {p.kT}, "
+                                  f"proposal {a.proposal}", "K": K},
+           "roofline": {"kernel": "colour pass", "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+                        "avg_launch_ms": round(ms, 4),
+                        "note": f"(2C+2) bytes of spins per site-trial; lattice {2 * K ** 3 / 2 ** 20:.0f} MiB"},
+           "real_flip_fraction": st["real_flips"] / max(1, st["site_trials"]),
+           "acceptance": st["accepted"] / max(1, st["real_flips"])}
+    print(json.dumps(out), flush=True)
+
+
+def bench_refresh(a):
+    """Explicit global steps (Sec. 5 relaxation) on a lattice whose 54 B/site working set
+    exceeds the 256 MB Infinity Cache."""
+    import torch
+
+    from paper_1009_0457_amd import hmc as H
+
+    cfg, K, micro = big_lattice(a)
+    n = a.steps * 10
+    log(f"[bench] refresh: {K}^3, {micro.Q} grains, {n} steps")
+    p = H.hmc_default_params(K, cfg.neighbors, cfg.zone_h)
+    p.refresh_tile_z = a.tile_z
+    lat = H.Lattice(p, micro.Q)
+    lat.set_orientations(micro.euler)
+    lat.set_spins(micro.spins)
+    lat.set_load(cfg.sigma_MPa)
+    lat.stress_refresh(max(1, a.warmup * 10), True)
+    torch.cuda.synchronize()
+    lat.kernel_times()
+    lat.set_profiling(True)
+    t0 = time.perf_counter()
+    lat.stress_refresh(n, False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    lat.set_profiling(False)
+    kt = lat.kernel_times()
+    lat.close()
+    ks = kt["refresh_step"]
+    ms = ks["total_ms"] / max(1, ks["launches"])
+    ach = REFRESH_BYTES_PER_NODE_STEP * K ** 3 / (ms * 1e-3) / 1e9
+    out = {"metric": "explicit global stress-refresh steps/sec", "value": n / el, "unit": "steps/s", "n_gpus": 1,
+           "steps": n, "warmup": a.warmup * 10, "ms_per_step": el / n * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"refresh-{K}: {K}^3 periodic, the 128^3 4000-grain Voronoi structure refined "
+                                  f"x{K // 128 if K % 128 == 0 else 1}, biaxial 150/150 MPa, warm steps", "K": K,
+                      "tile_z": a.tile_z},
+           "roofline": {"kernel": "global explicit step", "bound": "hbm", "achieved": round(ach, 1),
+                        "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+                        "avg_launch_ms": round(ms, 4),
+                        "note": f"50 B per node-step; working set {(13 * 4 + 2) * K ** 3 / 2 ** 30:.2f} GiB"},
+           "fold_ms": round(kt["refresh_other"]["total_ms"] / max(1, kt["refresh_other"]["launches"]), 4)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -296,6 +408,10 @@ def main():
         return bench_batched(a)
     if a.workload == "adjoint":
         return bench_adjoint(a)
+    if a.workload == "potts":
+        return bench_potts(a)
+    if a.workload == "refresh":
+        return bench_refresh(a)
     import numpy as np
     import torch
 

@@ -174,7 +174,8 @@ __global__ __launch_bounds__(256) void k_adj_step(AdjStepArgs a)
     const int K = R.K;
     const int64_t n3 = R.n3;
     const int ntx = (K + kTileX - 1) / kTileX, nty = (K + kTileY - 1) / kTileY, tz = R.tile_z;
-    int b = (int)blockIdx.x;
+    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    int b = lb;
     const int bx = b % ntx;
     b /= ntx;
     const int by = b % nty, bz = b / nty;
@@ -293,7 +294,7 @@ __global__ __launch_bounds__(256) void k_adj_step(AdjStepArgs a)
         nlo = nhi;
         vprev = vcur;
     }
-    block_sum_to<6>(a.partials, acc);
+    block_sum_to<6>(a.partials, acc, lb);
 }
 
 // Folds the per-block sums (fixed order).  mode 0 (start): E^ = sum sigma, wE^ = 0,

@@ -110,7 +110,7 @@ Layout layout_of(const hmc_params* p, int n, const hmc_replica* r)
         L.sites += n3;
         L.grains += r[i].Q;
         L.max_list += n3 / C;
-        L.pass_blocks += (int)((n3 / C + kSiteBlock - 1) / kSiteBlock);
+        L.pass_blocks += (int)((n3 / C + kPassSites - 1) / kPassSites);
         int64_t nb = (n3 + kSiteBlock - 1) / kSiteBlock;
         if (nb > kMaxChunkBlocks) nb = kMaxChunkBlocks;
         L.node_blocks += (int)nb;
@@ -137,7 +137,7 @@ Layout layout_of(const hmc_params* p, int n, const hmc_replica* r)
     const int pblocks = L.node_blocks > L.tile_blocks ? L.node_blocks : L.tile_blocks;
     L.partials = take((size_t)pblocks * 8 * sizeof(double));
     L.counters = take(kCounters * sizeof(uint32_t));
-    L.stats = take(kStats * sizeof(unsigned long long));
+    L.stats = take(kStats * kStatCopies * sizeof(unsigned long long));
     L.thr = take((size_t)n * 64 * sizeof(uint64_t));
     L.tex = take((size_t)L.grains * sizeof(int32_t));
     L.hist = take(64 * sizeof(unsigned long long));
@@ -489,7 +489,7 @@ hmc_status build_context(const hmc_params* p, int n, const hmc_replica* r, void*
         R.site_off = site_off;
         R.grain_off = grain_off;
         R.pass_first = pf;
-        R.pass_blocks = (int)((R.n3 / C + kSiteBlock - 1) / kSiteBlock);
+        R.pass_blocks = (int)((R.n3 / C + kPassSites - 1) / kPassSites);
         R.node_first = nf;
         int64_t nb = (R.n3 + kSiteBlock - 1) / kSiteBlock;
         R.node_blocks = (int)(nb > kMaxChunkBlocks ? kMaxChunkBlocks : nb);
@@ -531,7 +531,7 @@ hmc_status build_context(const hmc_params* p, int n, const hmc_replica* r, void*
     c->euler.assign((size_t)3 * L.grains, 0.0);
     std::vector<double> state0((size_t)n * kStateDoubles, 0.0);
     std::vector<uint32_t> ctr0(kCounters, 0u);
-    std::vector<unsigned long long> st0(kStats, 0ull);
+    std::vector<unsigned long long> st0((size_t)kStats * kStatCopies, 0ull);
     const int64_t zero = 0;
     hipError_t e = hipMemcpyAsync(c->d.thr, thr.data(), thr.size() * sizeof(uint64_t), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
@@ -539,7 +539,8 @@ hmc_status build_context(const hmc_params* p, int n, const hmc_replica* r, void*
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d.counters, ctr0.data(), kCounters * sizeof(uint32_t), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(c->d.stats, st0.data(), kStats * sizeof(unsigned long long), hipMemcpyHostToDevice, stream);
+        e = hipMemcpyAsync(c->d.stats, st0.data(), st0.size() * sizeof(unsigned long long), hipMemcpyHostToDevice,
+                           stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d.pass_rep, pass_rep.data(), pass_rep.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                            stream);
@@ -1048,9 +1049,12 @@ hmc_status hmc_get_stats(hmc_ctx c, hmc_stats* out)
     if (!c) return HMC_EINVAL;
     c->err.clear();
     if (!out) return state_fail(c, HMC_EINVAL, "null output");
-    unsigned long long s[kStats];
-    HMC_TRY(c, hipMemcpyAsync(s, c->d.stats, sizeof s, hipMemcpyDeviceToHost, c->stream), "get_stats");
+    unsigned long long all[kStats * kStatCopies];
+    HMC_TRY(c, hipMemcpyAsync(all, c->d.stats, sizeof all, hipMemcpyDeviceToHost, c->stream), "get_stats");
     HMC_TRY(c, hipStreamSynchronize(c->stream), "get_stats");
+    unsigned long long s[kStats] = {};
+    for (int k = 0; k < kStatCopies; ++k)
+        for (int i = 0; i < kStats; ++i) s[i] += all[k * kStats + i];
     out->site_trials = c->host_site_trials;
     out->real_flips = (int64_t)s[kStatReal];
     out->zone_solves = (int64_t)s[kStatSolves];
@@ -1064,7 +1068,8 @@ hmc_status hmc_reset_stats(hmc_ctx c)
 {
     if (!c) return HMC_EINVAL;
     c->err.clear();
-    HMC_TRY(c, hipMemsetAsync(c->d.stats, 0, kStats * sizeof(unsigned long long), c->stream), "reset_stats");
+    HMC_TRY(c, hipMemsetAsync(c->d.stats, 0, kStats * kStatCopies * sizeof(unsigned long long), c->stream),
+            "reset_stats");
     c->host_site_trials = 0;
     c->host_refresh_steps = 0;
     return HMC_OK;

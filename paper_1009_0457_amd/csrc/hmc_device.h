@@ -45,12 +45,15 @@ __device__ __forceinline__ void voxel_strain(const float* __restrict__ u, int64_
     e[5] = E[5] + g[0][1] + g[1][0];
 }
 
-// Deterministic block sum of NV doubles per thread into partials[blockIdx.x * 8 + k].
+// Deterministic block sum of NV doubles per thread into partials[slot * 8 + k] (slot: the
+// block's logical index, blockIdx.x by default).
 template <int NVALS>
-__device__ __forceinline__ void block_sum_to(double* __restrict__ partials, const double v[NVALS])
+__device__ __forceinline__ void block_sum_to(double* __restrict__ partials, const double v[NVALS],
+                                             int slot = -1)
 {
     __shared__ double red[NVALS][256];
     const int t = threadIdx.x;
+    if (slot < 0) slot = (int)blockIdx.x;
 #pragma unroll
     for (int k = 0; k < NVALS; ++k) red[k][t] = v[k];
     __syncthreads();
@@ -61,7 +64,7 @@ __device__ __forceinline__ void block_sum_to(double* __restrict__ partials, cons
         }
         __syncthreads();
     }
-    if (t < NVALS) partials[(int64_t)blockIdx.x * 8 + t] = red[t][0];
+    if (t < NVALS) partials[(int64_t)slot * 8 + t] = red[t][0];
 }
 
 // Node-parallel kernels: block b belongs to replica node_rep[b]; within a replica the

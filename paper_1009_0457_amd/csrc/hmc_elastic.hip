@@ -48,11 +48,12 @@ __global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
     __shared__ float su[2][3][NY][NX];
     __shared__ float ss[2][6][VY][VX];
 
-    const int r = a.tile_rep[blockIdx.x];
+    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);   // neighbouring tiles share an L2
+    const int r = a.tile_rep[lb];
     const RepDev R = a.reps[r];
     const int K = R.K;
     const int ntx = (K + kTileX - 1) / kTileX, nty = (K + kTileY - 1) / kTileY, tz = R.tile_z;
-    int b = (int)blockIdx.x - R.tile_first;
+    int b = lb - R.tile_first;
     const int bx = b % ntx;
     b /= ntx;
     const int by = b % nty, bz = b / nty;
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
     float E[6];
 #pragma unroll
     for (int I = 0; I < 6; ++I) E[I] = (float)st[kE + I];
-    if (a.E_record && (int)blockIdx.x == R.tile_first && threadIdx.x < 6) a.E_record[threadIdx.x] = st[kE + threadIdx.x];
+    if (a.E_record && lb == R.tile_first && threadIdx.x < 6) a.E_record[threadIdx.x] = st[kE + threadIdx.x];
     const float alpha = R.glob_alpha, beta = R.glob_beta;
     const int t = threadIdx.x, lx = t % kTileX, ly = t / kTileX;
     const int nx = x0 + lx, ny = y0 + ly;
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
         nlo = nhi;
         vprev = vcur;
     }
-    block_sum_to<6>(a.partials, acc);
+    block_sum_to<6>(a.partials, acc, lb);
 }
 
 struct EArgs {

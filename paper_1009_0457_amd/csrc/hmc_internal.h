@@ -33,10 +33,22 @@ struct TrialEntry {
 };
 
 constexpr int kMaxReplicas = 4096;
-constexpr int kSiteBlock = 256;        // sites (or nodes) per block of site-parallel kernels
+constexpr int kSiteBlock = 256;        // nodes per block of node-parallel kernels
+constexpr int kPassSites = 1024;       // active sites per block of a colour pass
 constexpr int kMaxChunkBlocks = 8192;  // blocks per replica of node-parallel reductions
 constexpr int kTileX = 32, kTileY = 8;   // node tile of the explicit step in x, y
 constexpr int kTileZMax = 8;             // deepest tile in z (node layers per block)
+
+// Work-groups are dispatched to the 8 XCDs round-robin by their index, and each XCD has its
+// own L2.  Launches whose neighbouring blocks share data (halo rows, neighbour planes) use
+// this bijection of [0, G) as their logical block index, so that each XCD receives one
+// contiguous eighth of the logical blocks and the shared rows stay in one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int G)
+{
+    const int x = b % kXcds, i = b / kXcds, q = G / kXcds, rm = G % kXcds;
+    return x * q + (x < rm ? x : rm) + i;
+}
 
 __host__ __device__ constexpr int tile_blocks_of(int K, int tz)
 {
@@ -51,7 +63,7 @@ struct RepDev {
     int64_t n3;
     int64_t site_off;                // into spins / sigma / u / w planes (sites)
     int64_t grain_off;               // into Ctab / Stab (grains)
-    int32_t pass_first, pass_blocks; // blocks of a colour pass (active sites / 256, rounded up)
+    int32_t pass_first, pass_blocks; // blocks of a colour pass (active sites / kPassSites, rounded up)
     int32_t node_first, node_blocks; // blocks of node-parallel kernels (<= kMaxChunkBlocks)
     int32_t tile_first, tile_blocks; // blocks of the tiled explicit step (32 x 8 x tile_z nodes)
     double J, kT, lambda;
@@ -72,8 +84,11 @@ enum StateSlot {
 // Counters (uint32): list counts per colour, error flag.
 enum CounterSlot { kListCount = 0, kErrFlag = 8, kCounters = 16 };
 
-// 64-bit statistics slots.
+// 64-bit statistics slots, kept in kStatCopies copies that blocks pick by index (fewer
+// same-address atomics) and that the host sums.
 enum StatSlot { kStatReal = 0, kStatSolves = 1, kStatAccepted = 2, kStatScreened = 3, kStats = 8 };
+constexpr int kStatCopies = 64;
+__host__ __device__ constexpr int stat_copy(unsigned block) { return (int)(block & (kStatCopies - 1)) * kStats; }
 
 struct DeviceState {
     int16_t* spins = nullptr;        // sum of n3
@@ -87,7 +102,7 @@ struct DeviceState {
     double* state = nullptr;         // n_rep x kStateDoubles
     double* partials = nullptr;      // total node blocks x 8
     uint32_t* counters = nullptr;    // kCounters
-    unsigned long long* stats = nullptr;  // kStats
+    unsigned long long* stats = nullptr;  // kStats x kStatCopies
     uint64_t* thr = nullptr;         // n_rep x 64 integer Metropolis thresholds
     int32_t* tex_bin = nullptr;      // sum of Q
     unsigned long long* hist = nullptr;  // 64

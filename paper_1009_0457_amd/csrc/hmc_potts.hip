@@ -25,10 +25,11 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t a = 0xD2511F53u * c0;
-        const uint32_t ah = __umulhi(0xD2511F53u, c0);
-        const uint32_t b = 0xCD9E8D57u * c2;
-        const uint32_t bh = __umulhi(0xCD9E8D57u, c2);
+        // one 32 x 32 -> 64-bit product gives both halves (a single v_mad_u64_u32)
+        const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t a = (uint32_t)pa, ah = (uint32_t)(pa >> 32);
+        const uint32_t b = (uint32_t)pb, bh = (uint32_t)(pb >> 32);
         const uint32_t n0 = bh ^ c1 ^ k0;
         const uint32_t n2 = ah ^ c3 ^ k1;
         c0 = n0;
@@ -82,25 +83,6 @@ __device__ __forceinline__ double point_zone_energy(const float* __restrict__ So
     return d;
 }
 
-// Site of thread t within colour `colour` of a K^3 lattice.
-template <int M>
-__device__ __forceinline__ void active_site(int K, int Kh, int colour, int64_t t, int& x, int& y, int& z)
-{
-    if (M == 26) {
-        const int i = (int)(t % Kh);
-        const int j = (int)((t / Kh) % Kh);
-        const int k = (int)(t / ((int64_t)Kh * Kh));
-        x = 2 * i + (colour & 1);
-        y = 2 * j + ((colour >> 1) & 1);
-        z = 2 * k + ((colour >> 2) & 1);
-    } else {
-        const int i = (int)(t % Kh);
-        y = (int)((t / Kh) % K);
-        z = (int)(t / ((int64_t)Kh * K));
-        x = 2 * i + ((y + z + colour) & 1);
-    }
-}
-
 // Offset of neighbour slot k.  6: -x,+x,-y,+y,-z,+z.  26: (dz,dy,dx) lexicographic over
 // {-1,0,1}^3 without the centre.
 template <int M>
@@ -118,131 +100,179 @@ __device__ __forceinline__ void slot_offset(int k, int& dx, int& dy, int& dz)
     }
 }
 
-// Block-aggregated append and counts (256 threads, 4 wavefronts): one atomic per block
-// for the list and one per statistic, instead of one per wavefront -- same-address
-// atomics serialise in L2, and a colour pass has thousands of wavefronts.  Returns this
-// thread's list slot (valid where `append` is true).  Reached by every thread of the block.
-__device__ __forceinline__ uint32_t block_append_and_count(uint32_t* list_count, bool append,
-                                                           unsigned long long* stats, int slot_a, bool count_a,
-                                                           int slot_b, bool count_b)
+// Site of active index t (32-bit: K <= 1024) within colour `colour` of a K^3 lattice.
+template <int M>
+__device__ __forceinline__ void active_site32(int K, uint32_t Kh, int colour, uint32_t t, int& x, int& y, int& z)
 {
-    __shared__ uint32_t s_n[3][4];
-    __shared__ uint32_t s_base;
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const unsigned long long m = __ballot(append);
-    const unsigned long long ma = __ballot(count_a);
-    const unsigned long long mb = __ballot(count_b);
-    if (lane == 0) {
-        s_n[0][wid] = (uint32_t)__popcll(m);
-        s_n[1][wid] = (uint32_t)__popcll(ma);
-        s_n[2][wid] = (uint32_t)__popcll(mb);
+    if (M == 26) {
+        const uint32_t row = t / Kh, plane = row / Kh;
+        x = 2 * (int)(t - row * Kh) + (colour & 1);
+        y = 2 * (int)(row - plane * Kh) + ((colour >> 1) & 1);
+        z = 2 * (int)plane + ((colour >> 2) & 1);
+    } else {
+        const uint32_t row = t / Kh, plane = row / (uint32_t)K;
+        y = (int)(row - plane * (uint32_t)K);
+        z = (int)plane;
+        x = 2 * (int)(t - row * Kh) + ((y + z + colour) & 1);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t n = s_n[0][0] + s_n[0][1] + s_n[0][2] + s_n[0][3];
-        s_base = n ? atomicAdd(list_count, n) : 0u;
-    } else if (threadIdx.x == 64) {
-        const uint32_t n = s_n[1][0] + s_n[1][1] + s_n[1][2] + s_n[1][3];
-        if (n) atomicAdd(&stats[slot_a], (unsigned long long)n);
-    } else if (threadIdx.x == 128) {
-        const uint32_t n = s_n[2][0] + s_n[2][1] + s_n[2][2] + s_n[2][3];
-        if (n) atomicAdd(&stats[slot_b], (unsigned long long)n);
-    }
-    __syncthreads();
-    uint32_t off = s_base;
-    for (int w = 0; w < wid; ++w) off += s_n[0][w];
-    const unsigned long long below = (lane == 0) ? 0ull : (m & ((~0ull) >> (64 - lane)));
-    return off + (uint32_t)__popcll(below);
 }
 
-// One block covers 256 active sites of one replica (the replica is uniform per block).
-static_assert(kSiteBlock == 256, "the block-aggregated append assumes four wavefronts");
+// Block-wide exclusive prefix sum of v (256 threads), with the block total.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t& total)
+{
+    __shared__ uint32_t s_w[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t n = __shfl_up(inc, off);
+        if (lane >= off) inc += n;
+    }
+    if (lane == 63) s_w[wid] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wid; ++w) before += s_w[w];
+    total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    __syncthreads();
+    return before + inc - v;
+}
+
+// Block-wide sums of two counts (256 threads), valid in thread 0.
+__device__ __forceinline__ void block_sum2(uint32_t& a, uint32_t& b)
+{
+    __shared__ uint32_t s_a[4], s_b[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+    }
+    if (lane == 0) {
+        s_a[wid] = a;
+        s_b[wid] = b;
+    }
+    __syncthreads();
+    a = s_a[0] + s_a[1] + s_a[2] + s_a[3];
+    b = s_b[0] + s_b[1] + s_b[2] + s_b[3];
+}
+
+// One block covers kPassSites = 4 x 256 active sites of one replica (the replica is uniform
+// per block); each thread takes four of them, 256 apart.  A colour pass has tens of thousands
+// of blocks on large lattices, so the block appends its elastic trials with one atomic on the
+// list counter and adds its statistics to one of the spread counter copies.
+static_assert(kPassSites == 4 * 256, "four sites per thread of a 256-thread block");
 template <int M>
 __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
 {
-    const int r = a.pass_rep[blockIdx.x];
+    constexpr int SPT = kPassSites / 256;
+    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);   // neighbouring rows share an L2
+    const int r = a.pass_rep[lb];
     const RepDev R = a.reps[r];
-    const int64_t t = (int64_t)(blockIdx.x - R.pass_first) * kSiteBlock + threadIdx.x;
-    const int64_t n_active = R.n3 / (M == 26 ? 8 : 2);
+    const uint32_t first = (uint32_t)(lb - R.pass_first) * (uint32_t)kPassSites + threadIdx.x;
+    const uint32_t n_active = (uint32_t)(R.n3 / (M == 26 ? 8 : 2));
     const bool elastic = R.elastic != 0;
     int16_t* spins = a.spins + R.site_off;
-    bool real = false, accepted = false, screened = false;
-    uint32_t site = 0, r1 = 0;
-    int q_new = 0, gb = 0;
-    if (t < n_active) {
-        int x, y, z;
-        const int K = R.K;
-        active_site<M>(K, R.Kh, a.colour, t, x, y, z);
-        site = (uint32_t)(x + K * (y + K * z));
-        const Philox4 rn = philox4x32_10(site, (uint32_t)(*a.sweep), 0u, 0u, R.key0, R.key1);
-        r1 = rn.v[1];
-        const int q_old = spins[site];
-        if (R.proposal == 0) {
-            const int k = (int)__umulhi(rn.v[0], (uint32_t)M);
-            int dx, dy, dz;
-            slot_offset<M>(k, dx, dy, dz);
-            q_new = spins[wrapi(x + dx, K) + K * (wrapi(y + dy, K) + K * wrapi(z + dz, K))];
-        } else {
-            const uint32_t step = __umulhi(rn.v[0], (uint32_t)(R.Q - 1));
-            q_new = (int)(((uint32_t)q_old + 1u + step) % (uint32_t)R.Q);
-        }
-        real = (q_new != q_old);
-        if (real) {
+    const int K = R.K;
+    const uint32_t sweep = (uint32_t)(*a.sweep);
+    TrialEntry ent[SPT];
+    bool solve[SPT];
+    uint32_t n_solve = 0, n_real = 0, n_other = 0;
 #pragma unroll
-            for (int k = 0; k < M; ++k) {
+    for (int it = 0; it < SPT; ++it) {
+        const uint32_t t = first + (uint32_t)it * 256u;
+        bool real = false, accepted = false, screened = false;
+        uint32_t site = 0, r1 = 0;
+        int q_new = 0, gb = 0;
+        if (t < n_active) {
+            int x, y, z;
+            active_site32<M>(K, (uint32_t)R.Kh, a.colour, t, x, y, z);
+            site = (uint32_t)(x + K * (y + K * z));
+            // wrapped coordinates of the -1, 0, +1 neighbours, rows and planes as offsets
+            const int xs[3] = {wrapi(x - 1, K), x, wrapi(x + 1, K)};
+            const int ys[3] = {wrapi(y - 1, K) * K, y * K, wrapi(y + 1, K) * K};
+            const int KK = K * K;
+            const int zs[3] = {wrapi(z - 1, K) * KK, z * KK, wrapi(z + 1, K) * KK};
+            const Philox4 rn = philox4x32_10(site, sweep, 0u, 0u, R.key0, R.key1);
+            r1 = rn.v[1];
+            const int q_old = spins[site];
+            if (R.proposal == 0) {
+                const int k = (int)__umulhi(rn.v[0], (uint32_t)M);
                 int dx, dy, dz;
                 slot_offset<M>(k, dx, dy, dz);
-                const int qn = spins[wrapi(x + dx, K) + K * (wrapi(y + dy, K) + K * wrapi(z + dz, K))];
-                gb += (qn == q_old) - (qn == q_new);
+                q_new = spins[xs[dx + 1] + ys[dy + 1] + zs[dz + 1]];
+            } else {
+                const uint32_t step = __umulhi(rn.v[0], (uint32_t)(R.Q - 1));
+                q_new = (int)(((uint32_t)q_old + 1u + step) % (uint32_t)R.Q);
             }
-            if (!elastic) {
-                accepted = (uint64_t)r1 < a.thr[(int64_t)r * 64 + gb + M];
-            } else if (a.screen && r1 != 0u) {
-                // reject without a solve when even the lowest possible zone energy loses:
-                // dE >= J gb + lambda dPi_0 > max(0, E*(r1)) + margin
-                float sp[6];
+            real = (q_new != q_old);
+            if (real) {
 #pragma unroll
-                for (int I = 0; I < 6; ++I) sp[I] = a.sigma[(int64_t)I * a.plane + R.site_off + site];
-                const float* So = a.Stab + (R.grain_off + q_old) * kTab;
-                const float* Sn = a.Stab + (R.grain_off + q_new) * kTab;
-                const double lo = R.J * (double)gb + R.lambda * point_zone_energy(So, Sn, sp);
-                const double estar = -R.kT * log((double)r1 * 2.3283064365386963e-10);
-                double W = 0.0;   // stored-energy scale of the site for the margin
+                for (int k = 0; k < M; ++k) {
+                    int dx, dy, dz;
+                    slot_offset<M>(k, dx, dy, dz);
+                    const int qn = spins[xs[dx + 1] + ys[dy + 1] + zs[dz + 1]];
+                    gb += (qn == q_old) - (qn == q_new);
+                }
+                if (!elastic) {
+                    accepted = (uint64_t)r1 < a.thr[(int64_t)r * 64 + gb + M];
+                } else if (a.screen && r1 != 0u) {
+                    // reject without a solve when even the lowest possible zone energy loses:
+                    // dE >= J gb + lambda dPi_0 > max(0, E*(r1)) + margin
+                    float sp[6];
 #pragma unroll
-                for (int i = 0; i < 6; ++i)
+                    for (int I = 0; I < 6; ++I) sp[I] = a.sigma[(int64_t)I * a.plane + R.site_off + site];
+                    const float* So = a.Stab + (R.grain_off + q_old) * kTab;
+                    const float* Sn = a.Stab + (R.grain_off + q_new) * kTab;
+                    const double lo = R.J * (double)gb + R.lambda * point_zone_energy(So, Sn, sp);
+                    const double estar = -R.kT * log((double)r1 * 2.3283064365386963e-10);
+                    double W = 0.0;   // stored-energy scale of the site for the margin
 #pragma unroll
-                    for (int j = i; j < 6; ++j)
-                        W += (i == j ? 0.5 : 1.0) * (double)sp[i] * (double)sp[j] * fabs((double)So[sym_index(i, j)]);
-                const double margin = 1e-4 * fabs(R.lambda) * W + 1e-9 * (1.0 + fabs(lo));
-                screened = lo > fmax(0.0, estar) + margin;
+                    for (int i = 0; i < 6; ++i)
+#pragma unroll
+                        for (int j = i; j < 6; ++j)
+                            W += (i == j ? 0.5 : 1.0) * (double)sp[i] * (double)sp[j] *
+                                 fabs((double)So[sym_index(i, j)]);
+                    const double margin = 1e-4 * fabs(R.lambda) * W + 1e-9 * (1.0 + fabs(lo));
+                    screened = lo > fmax(0.0, estar) + margin;
+                }
             }
+            if (a.rec) {
+                hmc_trial_record rc;
+                rc.q_new = q_new;
+                rc.gb = gb;
+                rc.dPi = 0.0f;
+                rc.r1 = r1;
+                rc.flags = (real ? 1 : 0) | (accepted ? 2 : 0) | (screened ? 8 : 0);
+                rc.reserved = 0;
+                a.rec[R.site_off + site] = rc;
+            }
+            // same-colour sites are never neighbours: nothing else in this pass reads `site`
+            if (accepted) spins[site] = (int16_t)q_new;
         }
-        if (a.rec) {
-            hmc_trial_record rc;
-            rc.q_new = q_new;
-            rc.gb = gb;
-            rc.dPi = 0.0f;
-            rc.r1 = r1;
-            rc.flags = (real ? 1 : 0) | (accepted ? 2 : 0) | (screened ? 8 : 0);
-            rc.reserved = 0;
-            a.rec[R.site_off + site] = rc;
-        }
-        // same-colour sites are never neighbours: nothing else in this pass reads `site`
-        if (accepted) spins[site] = (int16_t)q_new;
+        solve[it] = elastic && real && !screened;
+        ent[it].site = site;
+        ent[it].qr = (uint32_t)q_new | ((uint32_t)r << 16);
+        ent[it].gb = gb;
+        ent[it].r1 = r1;
+        n_solve += solve[it] ? 1u : 0u;
+        n_real += real ? 1u : 0u;
+        n_other += (elastic ? screened : accepted) ? 1u : 0u;
     }
-    // block-collective tail, reached by every thread (replica uniform per block)
-    const bool solve = elastic && real && !screened;
-    const uint32_t slot = block_append_and_count(a.list_count, solve, a.stats, kStatReal, real,
-                                                 elastic ? kStatScreened : kStatAccepted,
-                                                 elastic ? screened : accepted);
-    if (solve) {
-        TrialEntry e;
-        e.site = site;
-        e.qr = (uint32_t)q_new | ((uint32_t)r << 16);
-        e.gb = gb;
-        e.r1 = r1;
-        a.list[slot] = e;
+    // block-collective tail, reached by every thread
+    uint32_t total = 0;
+    uint32_t off = block_exclusive_scan(n_solve, total);
+    __shared__ uint32_t s_base;
+    if (threadIdx.x == 0) s_base = total ? atomicAdd(a.list_count, total) : 0u;
+    block_sum2(n_real, n_other);   // (its barrier also publishes s_base)
+    if (threadIdx.x == 0) {
+        unsigned long long* st = a.stats + stat_copy(blockIdx.x);
+        if (n_real) atomicAdd(&st[kStatReal], (unsigned long long)n_real);
+        if (n_other) atomicAdd(&st[elastic ? kStatScreened : kStatAccepted], (unsigned long long)n_other);
     }
+    off += s_base;
+#pragma unroll
+    for (int it = 0; it < SPT; ++it)
+        if (solve[it]) a.list[off++] = ent[it];
 }
 
 // Deferred update of an elastic pass: every accepted entry writes its new state.
@@ -359,7 +389,7 @@ hipError_t launch_potts_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
     a.plane = c->total_sites;
     a.colour = colour;
     a.screen = (c->p.zone_screen != 0 && c->d.sigma != nullptr) ? 1 : 0;
-    const dim3 grid((unsigned)c->pass_blocks), block(kSiteBlock);
+    const dim3 grid((unsigned)c->pass_blocks), block(256);
     const int tok = prof_begin(c, kProfPotts);
     if (c->p.neighbors == 26) hipLaunchKernelGGL(k_potts_pass<26>, grid, block, 0, c->stream, a);
     else hipLaunchKernelGGL(k_potts_pass<6>, grid, block, 0, c->stream, a);

@@ -271,8 +271,8 @@ __global__ __launch_bounds__(64) void k_zone(ZoneArgs a)
                 a.rec[tc.site_off + ent.site].dPi = (float)dPi;
                 a.rec[tc.site_off + ent.site].flags = 1 | 4 | (accept ? 2 : 0);
             }
-            atomicAdd(&a.stats[kStatSolves], 1ull);
-            if (accept) atomicAdd(&a.stats[kStatAccepted], 1ull);
+            atomicAdd(&a.stats[stat_copy(blockIdx.x) + kStatSolves], 1ull);
+            if (accept) atomicAdd(&a.stats[stat_copy(blockIdx.x) + kStatAccepted], 1ull);
         }
         __syncthreads();   // LDS is reused by the next trial
     }
@@ -537,8 +537,8 @@ __global__ __launch_bounds__(256, 2) void k_zone_col(ZoneArgs a)
                 a.rec[tc.site_off + ent.site].dPi = (float)dPi;
                 a.rec[tc.site_off + ent.site].flags = 1 | 4 | (accept ? 2 : 0);
             }
-            atomicAdd(&a.stats[kStatSolves], 1ull);
-            if (accept) atomicAdd(&a.stats[kStatAccepted], 1ull);
+            atomicAdd(&a.stats[stat_copy(blockIdx.x) + kStatSolves], 1ull);
+            if (accept) atomicAdd(&a.stats[stat_copy(blockIdx.x) + kStatAccepted], 1ull);
         }
         __syncthreads();   // LDS is reused by the next group of trials
     }
@@ -865,8 +865,8 @@ __global__ __launch_bounds__(64, 2) void k_zone_lane(ZoneArgs a)
         n_accepted += __shfl_xor(n_accepted, off);
     }
     if (t == 0 && n_solved) {
-        atomicAdd(&a.stats[kStatSolves], (unsigned long long)n_solved);
-        if (n_accepted) atomicAdd(&a.stats[kStatAccepted], (unsigned long long)n_accepted);
+        atomicAdd(&a.stats[stat_copy(blockIdx.x) + kStatSolves], (unsigned long long)n_solved);
+        if (n_accepted) atomicAdd(&a.stats[stat_copy(blockIdx.x) + kStatAccepted], (unsigned long long)n_accepted);
     }
 }
 

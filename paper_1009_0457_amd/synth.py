@@ -92,6 +92,19 @@ def voronoi_polycrystal(K: int, n_grains: int, seed: int,
     return Microstructure(K=K, spins=spins, euler=euler)
 
 
+def refined_polycrystal(K: int, factor: int, n_grains: int, seed: int) -> Microstructure:
+    """A Voronoi polycrystal built on a (K/factor)^3 lattice with each site replicated into a
+    factor^3 block: the same periodic grain structure at K^3 without a K^3 nearest-seed
+    search (for bandwidth measurements on lattices larger than the caches)."""
+    if K % factor:
+        raise ValueError("K must be a multiple of factor")
+    m = voronoi_polycrystal(K // factor, n_grains, seed)
+    k = K // factor
+    s = m.spins.reshape(k, k, k)                       # (z, y, x), x fastest
+    s = np.repeat(np.repeat(np.repeat(s, factor, axis=0), factor, axis=1), factor, axis=2)
+    return Microstructure(K=K, spins=np.ascontiguousarray(s).reshape(-1).astype(np.int32), euler=m.euler)
+
+
 def random_spins(K: int, Q: int, seed: int) -> np.ndarray:
     """Independent uniform spins in [0, Q): a maximally disordered test lattice."""
     rng = np.random.default_rng(seed)
