@@ -157,14 +157,19 @@ __device__ __forceinline__ void block_sum2(uint32_t& a, uint32_t& b)
 }
 
 // One block covers kPassSites = 4 x 256 active sites of one replica (the replica is uniform
-// per block); each thread takes four of them, 256 apart.  A colour pass has tens of thousands
-// of blocks on large lattices, so the block appends its elastic trials with one atomic on the
-// list counter and adds its statistics to one of the spread counter copies.
+// per block); each thread takes four of them, 256 apart.  Phase 1 draws every trial and
+// keeps only the real flips (q_new != q_old), which a wavefront then compacts through LDS
+// so that phase 2 -- the 26 neighbour reads, the decision or the screen -- runs once per 64
+// real flips instead of once per site slot (inside grains most proposals are no-ops, and a
+// single real flip would otherwise hold the whole wavefront).  A colour pass has tens of
+// thousands of blocks on large lattices, so the block appends its elastic trials with one
+// atomic on the list counter and adds its statistics to one of the spread counter copies.
 static_assert(kPassSites == 4 * 256, "four sites per thread of a 256-thread block");
 template <int M>
 __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
 {
     constexpr int SPT = kPassSites / 256;
+    __shared__ uint32_t s_item[4][SPT * 64][3];      // per wavefront: coords, q_old | q_new << 16, r1
     const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);   // neighbouring rows share an L2
     const int r = a.pass_rep[lb];
     const RepDev R = a.reps[r];
@@ -172,26 +177,23 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
     const uint32_t n_active = (uint32_t)(R.n3 / (M == 26 ? 8 : 2));
     const bool elastic = R.elastic != 0;
     int16_t* spins = a.spins + R.site_off;
-    const int K = R.K;
+    const int K = R.K, KK = K * K;
     const uint32_t sweep = (uint32_t)(*a.sweep);
-    TrialEntry ent[SPT];
-    bool solve[SPT];
-    uint32_t n_solve = 0, n_real = 0, n_other = 0;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const unsigned long long below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    uint32_t n_real = 0, n_other = 0, n_wave = 0;
+
+    // ---- phase 1: draws, proposals; real flips to the wavefront's list ----
 #pragma unroll
     for (int it = 0; it < SPT; ++it) {
         const uint32_t t = first + (uint32_t)it * 256u;
-        bool real = false, accepted = false, screened = false;
-        uint32_t site = 0, r1 = 0;
-        int q_new = 0, gb = 0;
+        bool real = false;
+        uint32_t packed = 0, qq = 0, r1 = 0, site = 0;
+        int q_new = 0;
         if (t < n_active) {
             int x, y, z;
             active_site32<M>(K, (uint32_t)R.Kh, a.colour, t, x, y, z);
-            site = (uint32_t)(x + K * (y + K * z));
-            // wrapped coordinates of the -1, 0, +1 neighbours, rows and planes as offsets
-            const int xs[3] = {wrapi(x - 1, K), x, wrapi(x + 1, K)};
-            const int ys[3] = {wrapi(y - 1, K) * K, y * K, wrapi(y + 1, K) * K};
-            const int KK = K * K;
-            const int zs[3] = {wrapi(z - 1, K) * KK, z * KK, wrapi(z + 1, K) * KK};
+            site = (uint32_t)(x + K * y + KK * z);
             const Philox4 rn = philox4x32_10(site, sweep, 0u, 0u, R.key0, R.key1);
             r1 = rn.v[1];
             const int q_old = spins[site];
@@ -199,42 +201,83 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
                 const int k = (int)__umulhi(rn.v[0], (uint32_t)M);
                 int dx, dy, dz;
                 slot_offset<M>(k, dx, dy, dz);
-                q_new = spins[xs[dx + 1] + ys[dy + 1] + zs[dz + 1]];
+                q_new = spins[wrapi(x + dx, K) + K * wrapi(y + dy, K) + KK * wrapi(z + dz, K)];
             } else {
                 const uint32_t step = __umulhi(rn.v[0], (uint32_t)(R.Q - 1));
                 q_new = (int)(((uint32_t)q_old + 1u + step) % (uint32_t)R.Q);
             }
             real = (q_new != q_old);
-            if (real) {
+            packed = (uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20);
+            qq = (uint32_t)q_old | ((uint32_t)q_new << 16);
+            if (!real && a.rec) {
+                hmc_trial_record rc;
+                rc.q_new = q_new;
+                rc.gb = 0;
+                rc.dPi = 0.0f;
+                rc.r1 = r1;
+                rc.flags = 0;
+                rc.reserved = 0;
+                a.rec[R.site_off + site] = rc;
+            }
+        }
+        const unsigned long long m = __ballot(real);
+        if (real) {
+            const uint32_t j = n_wave + (uint32_t)__popcll(m & below);
+            s_item[wid][j][0] = packed;
+            s_item[wid][j][1] = qq;
+            s_item[wid][j][2] = r1;
+        }
+        n_wave += (uint32_t)__popcll(m);
+        n_real += real ? 1u : 0u;
+    }
+    __syncthreads();
+
+    // ---- phase 2: the wavefront's real flips, 64 at a time ----
+    TrialEntry ent[SPT];
+    bool solve[SPT];
+    uint32_t n_solve = 0;
 #pragma unroll
-                for (int k = 0; k < M; ++k) {
-                    int dx, dy, dz;
-                    slot_offset<M>(k, dx, dy, dz);
-                    const int qn = spins[xs[dx + 1] + ys[dy + 1] + zs[dz + 1]];
-                    gb += (qn == q_old) - (qn == q_new);
-                }
-                if (!elastic) {
-                    accepted = (uint64_t)r1 < a.thr[(int64_t)r * 64 + gb + M];
-                } else if (a.screen && r1 != 0u) {
-                    // reject without a solve when even the lowest possible zone energy loses:
-                    // dE >= J gb + lambda dPi_0 > max(0, E*(r1)) + margin
-                    float sp[6];
+    for (int it = 0; it < SPT; ++it) {
+        const uint32_t j = (uint32_t)(it * 64 + lane);
+        solve[it] = false;
+        if (j < n_wave) {
+            const uint32_t packed = s_item[wid][j][0], qq = s_item[wid][j][1], r1 = s_item[wid][j][2];
+            const int x = (int)(packed & 1023u), y = (int)((packed >> 10) & 1023u), z = (int)(packed >> 20);
+            const int q_old = (int)(qq & 0xffffu), q_new = (int)(qq >> 16);
+            const uint32_t site = (uint32_t)(x + K * y + KK * z);
+            const int xs[3] = {wrapi(x - 1, K), x, wrapi(x + 1, K)};
+            const int ys[3] = {wrapi(y - 1, K) * K, y * K, wrapi(y + 1, K) * K};
+            const int zs[3] = {wrapi(z - 1, K) * KK, z * KK, wrapi(z + 1, K) * KK};
+            int gb = 0;
 #pragma unroll
-                    for (int I = 0; I < 6; ++I) sp[I] = a.sigma[(int64_t)I * a.plane + R.site_off + site];
-                    const float* So = a.Stab + (R.grain_off + q_old) * kTab;
-                    const float* Sn = a.Stab + (R.grain_off + q_new) * kTab;
-                    const double lo = R.J * (double)gb + R.lambda * point_zone_energy(So, Sn, sp);
-                    const double estar = -R.kT * log((double)r1 * 2.3283064365386963e-10);
-                    double W = 0.0;   // stored-energy scale of the site for the margin
+            for (int k = 0; k < M; ++k) {
+                int dx, dy, dz;
+                slot_offset<M>(k, dx, dy, dz);
+                const int qn = spins[xs[dx + 1] + ys[dy + 1] + zs[dz + 1]];
+                gb += (qn == q_old) - (qn == q_new);
+            }
+            bool accepted = false, screened = false;
+            if (!elastic) {
+                accepted = (uint64_t)r1 < a.thr[(int64_t)r * 64 + gb + M];
+            } else if (a.screen && r1 != 0u) {
+                // reject without a solve when even the lowest possible zone energy loses:
+                // dE >= J gb + lambda dPi_0 > max(0, E*(r1)) + margin
+                float sp[6];
 #pragma unroll
-                    for (int i = 0; i < 6; ++i)
+                for (int I = 0; I < 6; ++I) sp[I] = a.sigma[(int64_t)I * a.plane + R.site_off + site];
+                const float* So = a.Stab + (R.grain_off + q_old) * kTab;
+                const float* Sn = a.Stab + (R.grain_off + q_new) * kTab;
+                const double lo = R.J * (double)gb + R.lambda * point_zone_energy(So, Sn, sp);
+                const double estar = -R.kT * log((double)r1 * 2.3283064365386963e-10);
+                double W = 0.0;   // stored-energy scale of the site for the margin
 #pragma unroll
-                        for (int j = i; j < 6; ++j)
-                            W += (i == j ? 0.5 : 1.0) * (double)sp[i] * (double)sp[j] *
-                                 fabs((double)So[sym_index(i, j)]);
-                    const double margin = 1e-4 * fabs(R.lambda) * W + 1e-9 * (1.0 + fabs(lo));
-                    screened = lo > fmax(0.0, estar) + margin;
-                }
+                for (int i = 0; i < 6; ++i)
+#pragma unroll
+                    for (int jj = i; jj < 6; ++jj)
+                        W += (i == jj ? 0.5 : 1.0) * (double)sp[i] * (double)sp[jj] *
+                             fabs((double)So[sym_index(i, jj)]);
+                const double margin = 1e-4 * fabs(R.lambda) * W + 1e-9 * (1.0 + fabs(lo));
+                screened = lo > fmax(0.0, estar) + margin;
             }
             if (a.rec) {
                 hmc_trial_record rc;
@@ -242,21 +285,20 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
                 rc.gb = gb;
                 rc.dPi = 0.0f;
                 rc.r1 = r1;
-                rc.flags = (real ? 1 : 0) | (accepted ? 2 : 0) | (screened ? 8 : 0);
+                rc.flags = 1 | (accepted ? 2 : 0) | (screened ? 8 : 0);
                 rc.reserved = 0;
                 a.rec[R.site_off + site] = rc;
             }
             // same-colour sites are never neighbours: nothing else in this pass reads `site`
             if (accepted) spins[site] = (int16_t)q_new;
+            solve[it] = elastic && !screened;
+            ent[it].site = site;
+            ent[it].qr = (uint32_t)q_new | ((uint32_t)r << 16);
+            ent[it].gb = gb;
+            ent[it].r1 = r1;
+            n_solve += solve[it] ? 1u : 0u;
+            n_other += (elastic ? screened : accepted) ? 1u : 0u;
         }
-        solve[it] = elastic && real && !screened;
-        ent[it].site = site;
-        ent[it].qr = (uint32_t)q_new | ((uint32_t)r << 16);
-        ent[it].gb = gb;
-        ent[it].r1 = r1;
-        n_solve += solve[it] ? 1u : 0u;
-        n_real += real ? 1u : 0u;
-        n_other += (elastic ? screened : accepted) ? 1u : 0u;
     }
     // block-collective tail, reached by every thread
     uint32_t total = 0;
