@@ -82,6 +82,9 @@ def parse():
     ap.add_argument("--replicas", type=int, default=64)
     ap.add_argument("--zone-variant", type=int, default=0, help="zone-solve kernel (0 = automatic)")
     ap.add_argument("--tile-z", type=int, default=0, help="node layers per block of the explicit step (0 = automatic)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batched: pick the explicit-step tile depth and the zone kernel with the autotuner "
+                         "(tile depth on throw-away batches; zone kernel during the warm-up sweeps)")
     ap.add_argument("--zero-load", action="store_true",
                     help="the same lattice with no load: the elastic term is off and every trial is decided "
                          "by the integer threshold table inside the colour pass")
@@ -168,11 +171,30 @@ def bench_batched(a):
             r.sigma_MPa[i] = float(c.sigma_MPa[i])
         reps.append(r)
     sites = sum(c.K ** 3 for c in cfgs)
+    tuned = None
+    if a.autotune:
+        from paper_1009_0457_amd import autotune as T
+
+        def build(tz):
+            q = H.hmc_params.from_buffer_copy(common)
+            q.refresh_tile_z = tz
+            bb = H.Batch(q, reps)
+            for i, m in enumerate(micros):
+                bb.set_replica(i, m.euler, m.spins)
+            return bb
+
+        tiles = T.tune_tile_depth(build)
+        common.refresh_tile_z = tiles["best"]
+        tuned = {"tile_z": tiles}
+        log(f"[bench] autotune tile depth: {tiles}")
     b = H.Batch(common, reps)
     for i, m in enumerate(micros):
         b.set_replica(i, m.euler, m.spins)
     log(f"[bench] {sites} sites; cold refresh")
     b.stress_refresh(-1, True)
+    if a.autotune:
+        tuned["zone_variant"] = T.tune_zone_variant(b, common.zone_h)
+        log(f"[bench] autotune zone kernel: {tuned['zone_variant']}")
     b.set_graphs(True)
     for _ in range(a.warmup):
         b.sweep(1)
@@ -190,6 +212,7 @@ def bench_batched(a):
     b.synchronize()
     t_scr = time.perf_counter() - t0
     st_scr = b.stats()
+    b_variant = tuned["zone_variant"]["best"] if tuned else common.zone_variant
     b.close()
     log(f"[bench] batch {t_batch:.3f} s ({sites * a.steps / t_batch:.4e} site-trials/s), screened {t_scr:.3f} s")
     # the same replicas one after another, each a single lattice with graph-replayed sweeps
@@ -197,6 +220,8 @@ def bench_batched(a):
     t_plain = 0.0
     for c, m, r in zip(cfgs, micros, reps):
         p = H.hmc_params.from_buffer_copy(common)
+        p.refresh_tile_z = 0           # each lattice alone picks its own tile depth
+        p.zone_variant = b_variant
         p.K, p.kT, p.lambda_el, p.seed = r.K, r.kT, r.lambda_el, r.seed
         p.glob_alpha, p.glob_beta, p.glob_alphaE = r.glob_alpha, r.glob_beta, r.glob_alphaE
         s = torch.cuda.Stream()
@@ -227,6 +252,7 @@ def bench_batched(a):
                                f"{common.refresh_every}", "sites": sites},
         "replicas_alone": {"value": trials / t_plain, "ms_per_step": t_plain / a.steps * 1e3},
         "batched_over_alone": t_plain / t_batch,
+        "autotune": tuned,
         "zone_solve_fraction": st["zone_solves"] / trials,
         "screened": {"value": trials / t_scr, "zone_solve_fraction": st_scr["zone_solves"] / trials},
     }

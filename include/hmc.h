@@ -208,6 +208,11 @@ hmc_status hmc_reset_stats(hmc_ctx ctx);
 /* Turn the lower-bound screen of hmc_params.zone_screen on (1) or off (0) for later sweeps. */
 hmc_status hmc_set_zone_screen(hmc_ctx ctx, int32_t enable);
 
+/* Select the zone-solve kernel (hmc_params.zone_variant) for later sweeps, e.g. from a
+ * launch-shape autotuner.  Variants compute the same solve in a different FP32 rounding
+ * order.  HMC_EINVAL for a variant the context's zone size does not allow. */
+hmc_status hmc_set_zone_variant(hmc_ctx ctx, int32_t variant);
+
 /* Kernel timing.  While profiling is enabled the library records a pair of HIP events on
  * the context's stream around every launch of each kernel class below; hmc_get_kernel_times
  * synchronises, resolves the pairs recorded since the last call (or since enabling) into

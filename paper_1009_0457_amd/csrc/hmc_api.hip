@@ -1085,6 +1085,18 @@ hmc_status hmc_set_zone_screen(hmc_ctx c, int32_t enable)
     return HMC_OK;
 }
 
+hmc_status hmc_set_zone_variant(hmc_ctx c, int32_t variant)
+{
+    if (!c) return HMC_EINVAL;
+    c->err.clear();
+    hmc_params q = c->p;
+    q.zone_variant = variant;
+    if (check_common(&q) != HMC_OK) return state_fail(c, HMC_EINVAL, "zone variant not allowed for this zone size");
+    c->p.zone_variant = variant;
+    drop_graphs(c);
+    return HMC_OK;
+}
+
 hmc_status hmc_set_profiling(hmc_ctx c, int32_t enable)
 {
     if (!c) return HMC_EINVAL;

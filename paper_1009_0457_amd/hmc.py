@@ -93,6 +93,7 @@ _SIGS = [
     ("hmc_get_stats", C.c_int, [C.c_void_p, C.POINTER(hmc_stats)]),
     ("hmc_reset_stats", C.c_int, [C.c_void_p]),
     ("hmc_set_zone_screen", C.c_int, [C.c_void_p, C.c_int32]),
+    ("hmc_set_zone_variant", C.c_int, [C.c_void_p, C.c_int32]),
     ("hmc_set_profiling", C.c_int, [C.c_void_p, C.c_int32]),
     ("hmc_get_kernel_times", C.c_int, [C.c_void_p, C.POINTER(hmc_kernel_times)]),
     ("hmc_set_graphs", C.c_int, [C.c_void_p, C.c_int32]),
@@ -265,6 +266,10 @@ def hmc_reset_stats(ctx):
 
 def hmc_set_zone_screen(ctx, enable):
     _check(lib().hmc_set_zone_screen(ctx, int(bool(enable))), ctx)
+
+
+def hmc_set_zone_variant(ctx, variant):
+    _check(lib().hmc_set_zone_variant(ctx, int(variant)), ctx)
 
 
 def hmc_set_profiling(ctx, enable):
@@ -492,6 +497,9 @@ class Lattice:
 
     def set_zone_screen(self, enable=True):
         hmc_set_zone_screen(self.ctx, enable)
+
+    def set_zone_variant(self, variant):
+        hmc_set_zone_variant(self.ctx, variant)
 
     def set_profiling(self, enable=True):
         hmc_set_profiling(self.ctx, enable)

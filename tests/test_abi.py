@@ -110,6 +110,19 @@ def test_zone_variant_limits():
         assert (L.hmc_workspace_bytes(C.byref(p), 8) > 0) == ok, (h, variant)
 
 
+def test_autotuner_candidates_are_the_variants_the_library_accepts():
+    L = _lib_or_skip()
+    from paper_1009_0457_amd.autotune import zone_variants_for
+    for h in range(4):
+        ok = []
+        for v in range(1, 6):
+            p = H.hmc_default_params(16, 26, h)
+            p.zone_variant = v
+            if L.hmc_workspace_bytes(C.byref(p), 8) > 0:
+                ok.append(v)
+        assert ok == zone_variants_for(h), h
+
+
 def test_shape_limits():
     L = _lib_or_skip()
     p = H.hmc_default_params(4, 26, 2)          # K < 2h+2 with the elastic term on

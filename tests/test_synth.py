@@ -1,0 +1,41 @@
+"""CPU checks of the seeded input generators (they hold no arithmetic of the method)."""
+import numpy as np
+
+from paper_1009_0457_amd.synth import batched_configs, refined_polycrystal, voronoi_polycrystal
+
+
+def test_voronoi_is_seeded_and_uses_every_grain_label_range():
+    a = voronoi_polycrystal(16, 12, 5)
+    b = voronoi_polycrystal(16, 12, 5)
+    assert np.array_equal(a.spins, b.spins) and np.array_equal(a.euler, b.euler)
+    assert a.spins.min() >= 0 and a.spins.max() < a.Q == 12
+    assert a.spins.dtype == np.int32 and a.spins.size == 16 ** 3
+
+
+def test_refined_polycrystal_replicates_each_coarse_site_into_a_block():
+    f = 3
+    fine = refined_polycrystal(18, f, 10, 2)
+    coarse = voronoi_polycrystal(6, 10, 2)
+    s = fine.spins.reshape(18, 18, 18)          # (z, y, x)
+    c = coarse.spins.reshape(6, 6, 6)
+    for dz in range(f):
+        for dy in range(f):
+            for dx in range(f):
+                assert np.array_equal(s[dz::f, dy::f, dx::f], c)
+    assert np.array_equal(fine.euler, coarse.euler)
+
+
+def test_batched_configs_follow_the_ensemble_recipe():
+    cfgs = batched_configs(64)
+    assert len(cfgs) == 64
+    assert {c.K for c in cfgs} <= {32, 48, 64, 96}
+    for c in cfgs:
+        assert c.n_grains == 8 * (c.K // 16) ** 3
+        assert 0.3 <= c.kT <= 1.0
+        load = c.extra["load_MPa"]
+        assert 0.0 <= load <= 300.0
+        # uniaxial along a unit axis: the Voigt stress is load * n n^T
+        n = c.extra["axis"]
+        assert abs(np.linalg.norm(n) - 1.0) < 1e-12
+        assert np.allclose(c.sigma_MPa[:3], load * n ** 2)
+    assert [c.philox_seed for c in cfgs] == list(range(1, 65))
