@@ -430,6 +430,16 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in "
                                    "DESIGN.md but not built", "n_gpus": a.gpus}))
         sys.exit(2)
+    if a.copy_probe_mib:
+        import torch
+
+        src = torch.ones(a.copy_probe_mib * 2 ** 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {a.copy_probe_mib} MiB read + {a.copy_probe_mib} MiB written")
+        del src, dst
     if a.workload == "batched":
         return bench_batched(a)
     if a.workload == "adjoint":
@@ -444,14 +454,6 @@ def main():
     from paper_1009_0457_amd import hmc as H
     from paper_1009_0457_amd.synth import large_config, voronoi_polycrystal
 
-    if a.copy_probe_mib:
-        src = torch.ones(a.copy_probe_mib * 2 ** 18, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] copy probe: {a.copy_probe_mib} MiB read + {a.copy_probe_mib} MiB written")
-        del src, dst
     cfg = large_config()
     if a.zero_load:
         cfg = cfg.zero_load()

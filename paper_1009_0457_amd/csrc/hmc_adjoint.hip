@@ -195,10 +195,10 @@ __global__ __launch_bounds__(256) void k_adj_step(AdjStepArgs a)
     double acc[6] = {0, 0, 0, 0, 0, 0};
 
     auto load_nodes = [&](int slot, int z) {
-        const int64_t zoff = (int64_t)K * K * wrapk(z, K);
+        const int64_t zoff = (int64_t)K * K * wrap_tile(z, K);
         for (int i = t; i < NX * NY; i += 256) {
             const int ix = i % NX, iy = i / NX;
-            const int64_t n = wrapk(x0 - 1 + ix, K) + (int64_t)K * wrapk(y0 - 1 + iy, K) + zoff;
+            const int64_t n = wrap_tile(x0 - 1 + ix, K) + (int64_t)K * wrap_tile(y0 - 1 + iy, K) + zoff;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 sa[slot][j][iy][ix] = alpha * (a.wb_in[j * n3 + n] + a.ub_in[j * n3 + n]);
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(256) void k_adj_step(AdjStepArgs a)
         }
     };
     auto voxel_layer = [&](int vs, int lo, int hi, int z, bool owned_layer) {
-        const int64_t zoff = (int64_t)K * K * wrapk(z, K);
+        const int64_t zoff = (int64_t)K * K * wrap_tile(z, K);
         for (int i = t; i < VX * VY; i += 256) {
             const int ix = i % VX, iy = i / VX;
             float g[3][3];
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void k_adj_step(AdjStepArgs a)
             eta[4] = b3[4] + g[0][2] + g[2][0];
             eta[5] = b3[5] + g[0][1] + g[1][0];
             const int gx = x0 - 1 + ix, gy = y0 - 1 + iy;
-            const int64_t v = wrapk(gx, K) + (int64_t)K * wrapk(gy, K) + zoff;
+            const int64_t v = wrap_tile(gx, K) + (int64_t)K * wrap_tile(gy, K) + zoff;
             const int q = a.spins[v];
             symv21(a.Ctab + (int64_t)q * kTab, eta, tau);
 #pragma unroll

@@ -7,6 +7,16 @@ namespace hmc {
 
 __device__ __forceinline__ int wrapk(int a, int K) { return a < 0 ? a + K : (a >= K ? a - K : a); }
 
+// Periodic wrap of any a >= -K: a compare and an add for a < 2K (every coordinate of a
+// large lattice), an exact remainder beyond (tile halos on lattices narrower than a tile).
+__device__ __forceinline__ int wrap_tile(int a, int K)
+{
+    if (a < 0) return a + K;
+    if (a < K) return a;
+    a -= K;
+    return a < K ? a : a % K;
+}
+
 __device__ __forceinline__ void symv21(const float* __restrict__ c, const float e[6], float s[6])
 {
     s[0] = c[0] * e[0] + c[1] * e[1] + c[2] * e[2] + c[3] * e[3] + c[4] * e[4] + c[5] * e[5];

@@ -31,11 +31,6 @@ struct GlobArgs {
     int64_t plane;
 };
 
-__device__ __forceinline__ int wrapm(int a, int K)
-{
-    a %= K;
-    return a < 0 ? a + K : a;
-}
 
 // Tiled explicit step.  A block owns a 32 x 8 tile of nodes in x, y and marches through
 // tile_z node layers in z.  Node layers (with a one-node halo) and voxel stress layers (with the
@@ -76,20 +71,56 @@ __global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
     const bool own = nx < K && ny < K;
     double acc[6] = {0, 0, 0, 0, 0, 0};
 
-    auto load_nodes = [&](int slot, int z) {
-        const int64_t zoff = (int64_t)K * K * wrapm(z, K);
-        for (int i = t; i < NX * NY; i += 256) {
-            const int ix = i % NX, iy = i / NX;
-            const int64_t n = wrapm(x0 - 1 + ix, K) + (int64_t)K * wrapm(y0 - 1 + iy, K) + zoff;
-            su[slot][0][iy][ix] = uin[n];
-            su[slot][1][iy][ix] = uin[P + n];
-            su[slot][2][iy][ix] = uin[2 * P + n];
+    // Node layers are fetched one layer ahead into registers (NP per thread) and stored to
+    // LDS after the barrier, so the global loads of layer z+2 are in flight while layer z is
+    // computed; the voxel layer's spins and the own nodes' w are fetched the same way.
+    constexpr int NP = (NX * NY + 255) / 256, VP = (VX * VY + 255) / 256;
+    float pf[NP][3];
+    int sp[VP];
+    auto fetch_nodes = [&](int z) {
+        const int64_t zoff = (int64_t)K * K * wrap_tile(z, K);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int i = t + 256 * k;
+            if (i < NX * NY) {
+                const int ix = i % NX, iy = i / NX;
+                const int64_t n = wrap_tile(x0 - 1 + ix, K) + (int64_t)K * wrap_tile(y0 - 1 + iy, K) + zoff;
+                pf[k][0] = uin[n];
+                pf[k][1] = uin[P + n];
+                pf[k][2] = uin[2 * P + n];
+            }
         }
     };
-    // voxel layer z from node layers z (slot lo) and z + 1 (slot hi)
-    auto voxel_layer = [&](int vs, int lo, int hi, int z, bool owned_layer) {
-        const int64_t zoff = (int64_t)K * K * wrapm(z, K);
-        for (int i = t; i < VX * VY; i += 256) {
+    auto store_nodes = [&](int slot) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int i = t + 256 * k;
+            if (i < NX * NY) {
+                const int ix = i % NX, iy = i / NX;
+                su[slot][0][iy][ix] = pf[k][0];
+                su[slot][1][iy][ix] = pf[k][1];
+                su[slot][2][iy][ix] = pf[k][2];
+            }
+        }
+    };
+    auto fetch_spins = [&](int z) {
+        const int64_t zoff = (int64_t)K * K * wrap_tile(z, K);
+#pragma unroll
+        for (int k = 0; k < VP; ++k) {
+            const int i = t + 256 * k;
+            sp[k] = 0;
+            if (i < VX * VY) {
+                const int ix = i % VX, iy = i / VX;
+                sp[k] = spins[wrap_tile(x0 - 1 + ix, K) + (int64_t)K * wrap_tile(y0 - 1 + iy, K) + zoff];
+            }
+        }
+    };
+    // voxel layer z from node layers z (slot lo) and z + 1 (slot hi); grains in sp
+    auto voxel_layer = [&](int vs, int lo, int hi, bool owned_layer) {
+#pragma unroll
+        for (int k = 0; k < VP; ++k) {
+            const int i = t + 256 * k;
+            if (i >= VX * VY) continue;
             const int ix = i % VX, iy = i / VX;
             float g[3][3];
 #pragma unroll
@@ -109,11 +140,10 @@ __global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
             e[3] = E[3] + g[1][2] + g[2][1];
             e[4] = E[4] + g[0][2] + g[2][0];
             e[5] = E[5] + g[0][1] + g[1][0];
-            const int gx = x0 - 1 + ix, gy = y0 - 1 + iy;
-            const int q = spins[wrapm(gx, K) + (int64_t)K * wrapm(gy, K) + zoff];
-            symv21(Ctab + (int64_t)q * kTab, e, s6);
+            symv21(Ctab + (int64_t)sp[k] * kTab, e, s6);
 #pragma unroll
             for (int I = 0; I < 6; ++I) ss[vs][I][iy][ix] = s6[I];
+            const int gx = x0 - 1 + ix, gy = y0 - 1 + iy;
             if (owned_layer && ix >= 1 && iy >= 1 && gx < K && gy < K) {
 #pragma unroll
                 for (int I = 0; I < 6; ++I) acc[I] += (double)s6[I];
@@ -121,17 +151,45 @@ __global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
         }
     };
 
-    load_nodes(0, z0 - 1);
-    load_nodes(1, z0);
+    fetch_nodes(z0 - 1);
+    store_nodes(0);
+    fetch_nodes(z0);
+    store_nodes(1);
+    fetch_spins(z0 - 1);
     __syncthreads();
-    voxel_layer(0, 0, 1, z0 - 1, false);
+    voxel_layer(0, 0, 1, false);
+    fetch_nodes(z0 + 1);
+    fetch_spins(z0);
     int nlo = 1, vprev = 0;
     for (int z = z0; z < z1; ++z) {
         const int nhi = 1 - nlo, vcur = 1 - vprev;
         __syncthreads();                       // node layer z-1 and voxel layer z-2 are free
-        load_nodes(nhi, z + 1);
+        store_nodes(nhi);                      // node layer z+1
+        int sp_cur[VP];
+#pragma unroll
+        for (int k = 0; k < VP; ++k) sp_cur[k] = sp[k];
+        if (z + 1 < z1) {
+            fetch_nodes(z + 2);                // in flight during this layer
+            fetch_spins(z + 1);
+        }
+        float wz[3] = {0.f, 0.f, 0.f};
+        const int64_t n = nx + (int64_t)K * (ny + (int64_t)K * z);
+        if (own) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) wz[j] = w[(int64_t)j * P + n];
+        }
         __syncthreads();
-        voxel_layer(vcur, nlo, nhi, z, true);
+        {
+            int sp_next[VP];
+#pragma unroll
+            for (int k = 0; k < VP; ++k) {
+                sp_next[k] = sp[k];
+                sp[k] = sp_cur[k];
+            }
+            voxel_layer(vcur, nlo, nhi, true);
+#pragma unroll
+            for (int k = 0; k < VP; ++k) sp[k] = sp_next[k];
+        }
         __syncthreads();
         if (own) {
             float f[3] = {0.f, 0.f, 0.f};
@@ -146,11 +204,10 @@ __global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
                 f[1] += sx * s5 + sy * s1 + sz * s3;
                 f[2] += sx * s4 + sy * s3 + sz * s2;
             }
-            const int64_t n = nx + (int64_t)K * (ny + (int64_t)K * z);
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const int64_t idx = (int64_t)j * P + n;
-                const float wn = beta * w[idx] - alpha * f[j];
+                const float wn = beta * wz[j] - alpha * f[j];
                 w[idx] = wn;
                 uout[idx] = su[nlo][j][ly + 1][lx + 1] + wn;
             }
