@@ -100,21 +100,59 @@ __device__ __forceinline__ void slot_offset(int k, int& dx, int& dy, int& dz)
     }
 }
 
-// Site of active index t (32-bit: K <= 1024) within colour `colour` of a K^3 lattice.
+// Active index t of a colour class, kept as (i, j, k): i counts the class's sites along x
+// (K/2 of them), j along y (K/2 for 26 neighbours, K for 6), k along z.  One division pair
+// places a thread's first site; its later sites, 256 indices apart, are reached by adding the
+// per-block constants 256 / (K/2) and 256 % (K/2) with carries, so the per-site cost is a
+// few adds instead of two integer divisions.
+struct ActiveWalk {
+    uint32_t i, j, k;
+};
+
+__device__ __forceinline__ ActiveWalk walk_start(uint32_t t, uint32_t Kh, uint32_t NJ)
+{
+    ActiveWalk w;
+    const uint32_t row = t / Kh;
+    w.i = t - row * Kh;
+    w.k = row / NJ;
+    w.j = row - w.k * NJ;
+    return w;
+}
+
+__device__ __forceinline__ void walk_advance(ActiveWalk& w, uint32_t Kh, uint32_t NJ, uint32_t di, uint32_t dr)
+{
+    w.i += di;
+    uint32_t rows = dr;
+    if (w.i >= Kh) {
+        w.i -= Kh;
+        rows += 1;
+    }
+    w.j += rows;
+    if (w.j >= NJ) {
+        const uint32_t c = w.j / NJ;
+        w.k += c;
+        w.j -= c * NJ;
+    }
+}
+
 template <int M>
-__device__ __forceinline__ void active_site32(int K, uint32_t Kh, int colour, uint32_t t, int& x, int& y, int& z)
+__device__ __forceinline__ void walk_site(const ActiveWalk& w, int colour, int& x, int& y, int& z)
 {
     if (M == 26) {
-        const uint32_t row = t / Kh, plane = row / Kh;
-        x = 2 * (int)(t - row * Kh) + (colour & 1);
-        y = 2 * (int)(row - plane * Kh) + ((colour >> 1) & 1);
-        z = 2 * (int)plane + ((colour >> 2) & 1);
+        x = 2 * (int)w.i + (colour & 1);
+        y = 2 * (int)w.j + ((colour >> 1) & 1);
+        z = 2 * (int)w.k + ((colour >> 2) & 1);
     } else {
-        const uint32_t row = t / Kh, plane = row / (uint32_t)K;
-        y = (int)(row - plane * (uint32_t)K);
-        z = (int)plane;
-        x = 2 * (int)(t - row * Kh) + ((y + z + colour) & 1);
+        y = (int)w.j;
+        z = (int)w.k;
+        x = 2 * (int)w.i + ((y + z + colour) & 1);
     }
+}
+
+// Linear site index; every factor fits 24 bits for K <= 1024, so full-rate 24-bit multiplies.
+__device__ __forceinline__ uint32_t site_of(int x, int y, int z, int K, int KK)
+{
+    return (uint32_t)x + __umul24((uint32_t)K, (uint32_t)y) + __umul24((uint32_t)KK, (uint32_t)z);
 }
 
 // Block-wide exclusive prefix sum of v (256 threads), with the block total.
@@ -182,6 +220,9 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const unsigned long long below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
     uint32_t n_real = 0, n_other = 0, n_wave = 0;
+    const uint32_t Kh = (uint32_t)R.Kh, NJ = (M == 26) ? Kh : (uint32_t)K;
+    const uint32_t di = 256u % Kh, dr = 256u / Kh;
+    ActiveWalk walk = walk_start(first, Kh, NJ);
 
     // ---- phase 1: draws, proposals; real flips to the wavefront's list ----
 #pragma unroll
@@ -190,10 +231,11 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
         bool real = false;
         uint32_t packed = 0, qq = 0, r1 = 0, site = 0;
         int q_new = 0;
+        if (it > 0) walk_advance(walk, Kh, NJ, di, dr);
         if (t < n_active) {
             int x, y, z;
-            active_site32<M>(K, (uint32_t)R.Kh, a.colour, t, x, y, z);
-            site = (uint32_t)(x + K * y + KK * z);
+            walk_site<M>(walk, a.colour, x, y, z);
+            site = site_of(x, y, z, K, KK);
             const Philox4 rn = philox4x32_10(site, sweep, 0u, 0u, R.key0, R.key1);
             r1 = rn.v[1];
             const int q_old = spins[site];
@@ -201,7 +243,7 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
                 const int k = (int)__umulhi(rn.v[0], (uint32_t)M);
                 int dx, dy, dz;
                 slot_offset<M>(k, dx, dy, dz);
-                q_new = spins[wrapi(x + dx, K) + K * wrapi(y + dy, K) + KK * wrapi(z + dz, K)];
+                q_new = spins[site_of(wrapi(x + dx, K), wrapi(y + dy, K), wrapi(z + dz, K), K, KK)];
             } else {
                 const uint32_t step = __umulhi(rn.v[0], (uint32_t)(R.Q - 1));
                 q_new = (int)(((uint32_t)q_old + 1u + step) % (uint32_t)R.Q);
@@ -244,10 +286,13 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
             const uint32_t packed = s_item[wid][j][0], qq = s_item[wid][j][1], r1 = s_item[wid][j][2];
             const int x = (int)(packed & 1023u), y = (int)((packed >> 10) & 1023u), z = (int)(packed >> 20);
             const int q_old = (int)(qq & 0xffffu), q_new = (int)(qq >> 16);
-            const uint32_t site = (uint32_t)(x + K * y + KK * z);
+            const uint32_t site = site_of(x, y, z, K, KK);
             const int xs[3] = {wrapi(x - 1, K), x, wrapi(x + 1, K)};
-            const int ys[3] = {wrapi(y - 1, K) * K, y * K, wrapi(y + 1, K) * K};
-            const int zs[3] = {wrapi(z - 1, K) * KK, z * KK, wrapi(z + 1, K) * KK};
+            const int ys[3] = {(int)__umul24((uint32_t)wrapi(y - 1, K), (uint32_t)K), (int)__umul24((uint32_t)y, (uint32_t)K),
+                               (int)__umul24((uint32_t)wrapi(y + 1, K), (uint32_t)K)};
+            const int zs[3] = {(int)__umul24((uint32_t)wrapi(z - 1, K), (uint32_t)KK),
+                               (int)__umul24((uint32_t)z, (uint32_t)KK),
+                               (int)__umul24((uint32_t)wrapi(z + 1, K), (uint32_t)KK)};
             int gb = 0;
 #pragma unroll
             for (int k = 0; k < M; ++k) {
