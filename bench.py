@@ -8,6 +8,10 @@ steps, refresh every 10 sweeps (200 steps), 10-degree texture histograms on x an
 10 sweeps.
 
 Prints ONE JSON line on stdout (progress goes to stderr).  A step is one sweep.
+
+Other workloads (--workload): batched (the 64-replica ensemble against the same replicas run
+alone), adjoint (64^3 forward + backward of the stored energy), potts and refresh (the colour
+pass and the explicit step on lattices beyond the caches, default 512^3).
 """
 from __future__ import annotations
 

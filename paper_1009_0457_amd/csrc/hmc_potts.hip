@@ -1,12 +1,13 @@
 // hmc_potts.hip -- colour-pass kernels of the Potts sweep (Sec. 3 Eqs. H_1 and metrop_1,
 // Sec. 6 checkerboard with deferred updates) and small utility kernels.
 //
-// One thread per site of the active colour class.  Each thread draws its two Philox
-// words, forms the trial state, counts the change of unlike neighbour bonds and either
-// decides at once (elastic term off: exact integer threshold table) or appends the real
-// flip to a compacted list for the zone-solve kernel (elastic term on).  Because no two
-// sites of one class are neighbours, the decide-at-once path may write spins in place:
-// every read of the pass touches other classes only.
+// Four sites of the active colour class per thread.  Every trial draws its two Philox
+// words and forms the trial state; the real flips (new state differs) are compacted per
+// wavefront, count the change of unlike neighbour bonds and either decide at once (elastic
+// term off: exact integer threshold table) or go to a compacted list for the zone-solve
+// kernel (elastic term on).  Because no two sites of one class are neighbours, the
+// decide-at-once path may write spins in place: every read of the pass touches other
+// classes only.
 #include "hmc_internal.h"
 
 namespace hmc {

@@ -9,15 +9,21 @@
 // centre-point strain of voxel v from its 8 corners; C_v the stiffness of the pass's
 // snapshot spin at v, except C_new at the trial site.
 //
-// Layout: one 64-lane wavefront (one work-group) owns one trial at a time.  Lane l owns
-// voxels l, l+64, ... (their 21 stiffness entries stay in registers) and nodes l, l+64, ...
-// (displacement and velocity in registers).  Each step is two phases exchanged through LDS:
+// Three kernels compute this solve with different layouts (hmc_params.zone_variant):
+// k_zone (a wavefront per trial), k_zone_col (node columns of several trials across a
+// 256-lane work-group) and k_zone_lane (whole trials inside one wavefront, x neighbours by
+// cross-lane moves; the default for h = 1, 2).  State and arithmetic are FP32; the final
+// energy is accumulated in FP64.  The decision uses the same predicate as the integer
+// path: accept iff dE <= 0 or r1 < 2^32 exp(-dE/kT).
+//
+// k_zone layout: one 64-lane wavefront (one work-group) owns one trial at a time.  Lane l
+// owns voxels l, l+64, ... (their 21 stiffness entries stay in registers) and nodes l,
+// l+64, ... (displacement and velocity in registers).  Each step is two phases exchanged
+// through LDS:
 //   A: every owned voxel reads its 8 corner displacements, forms strain and stress, and
 //      publishes the stress;
 //   B: every owned node gathers the forces of its (up to 8) voxels, takes the heavy-ball
 //      step and publishes its new displacement.
-// State and arithmetic are FP32; the final energy is accumulated in FP64.  The decision
-// uses the same predicate as the integer path: accept iff dE <= 0 or r1 < 2^32 exp(-dE/kT).
 #include "hmc_internal.h"
 
 namespace hmc {
