@@ -77,14 +77,25 @@ __global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
     constexpr int NP = (NX * NY + 255) / 256, VP = (VX * VY + 255) / 256;
     float pf[NP][3];
     int sp[VP];
+    // a thread loads the same (x, y) of the tile in every layer: wrap those once
+    int node_xy[NP], vox_xy[VP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int i = t + 256 * k, ix = i % NX, iy = i / NX;
+        node_xy[k] = wrap_tile(x0 - 1 + ix, K) + K * wrap_tile(y0 - 1 + iy, K);
+    }
+#pragma unroll
+    for (int k = 0; k < VP; ++k) {
+        const int i = t + 256 * k, ix = i % VX, iy = i / VX;
+        vox_xy[k] = wrap_tile(x0 - 1 + ix, K) + K * wrap_tile(y0 - 1 + iy, K);
+    }
     auto fetch_nodes = [&](int z) {
         const int64_t zoff = (int64_t)K * K * wrap_tile(z, K);
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             const int i = t + 256 * k;
             if (i < NX * NY) {
-                const int ix = i % NX, iy = i / NX;
-                const int64_t n = wrap_tile(x0 - 1 + ix, K) + (int64_t)K * wrap_tile(y0 - 1 + iy, K) + zoff;
+                const int64_t n = node_xy[k] + zoff;
                 pf[k][0] = uin[n];
                 pf[k][1] = uin[P + n];
                 pf[k][2] = uin[2 * P + n];
@@ -109,10 +120,7 @@ __global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
         for (int k = 0; k < VP; ++k) {
             const int i = t + 256 * k;
             sp[k] = 0;
-            if (i < VX * VY) {
-                const int ix = i % VX, iy = i / VX;
-                sp[k] = spins[wrap_tile(x0 - 1 + ix, K) + (int64_t)K * wrap_tile(y0 - 1 + iy, K) + zoff];
-            }
+            if (i < VX * VY) sp[k] = spins[vox_xy[k] + zoff];
         }
     };
     // voxel layer z from node layers z (slot lo) and z + 1 (slot hi); grains in sp
