@@ -303,28 +303,19 @@ __global__ __launch_bounds__(256) void k_adj_step(AdjStepArgs a)
 __global__ __launch_bounds__(256) void k_adj_E(double* adj, const double* partials, int nblocks, int mode,
                                                double betaE, double alphaE)
 {
-    __shared__ double red[6][256];
     const int t = threadIdx.x;
     double s[6] = {0, 0, 0, 0, 0, 0};
     for (int bk = t; bk < nblocks; bk += 256)
 #pragma unroll
         for (int I = 0; I < 6; ++I) s[I] += partials[(int64_t)bk * 8 + I];
-#pragma unroll
-    for (int I = 0; I < 6; ++I) red[I][t] = s[I];
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (t < h)
-#pragma unroll
-            for (int I = 0; I < 6; ++I) red[I][t] += red[I][t + h];
-        __syncthreads();
-    }
+    const double tot = block_total<6>(s);
     if (t < 6) {
         if (mode == 0) {
-            adj[kEb + t] = red[t][0];
+            adj[kEb + t] = tot;
             adj[kWEb + t] = 0.0;
             adj[kSigb + t] = 0.0;
         } else {
-            adj[kEb + t] -= red[t][0];
+            adj[kEb + t] -= tot;
             adj[kWEb + t] = betaE * adj[kWEt + t];
             adj[kSigb + t] += adj[kB + t];
         }

@@ -17,7 +17,8 @@ __device__ __forceinline__ int wrap_tile(int a, int K)
     return a < K ? a : a % K;
 }
 
-__device__ __forceinline__ void symv21(const float* __restrict__ c, const float e[6], float s[6])
+template <class Tab>
+__device__ __forceinline__ void symv21(Tab c, const float e[6], float s[6])
 {
     s[0] = c[0] * e[0] + c[1] * e[1] + c[2] * e[2] + c[3] * e[3] + c[4] * e[4] + c[5] * e[5];
     s[1] = c[1] * e[0] + c[6] * e[1] + c[7] * e[2] + c[8] * e[3] + c[9] * e[4] + c[10] * e[5];
@@ -25,6 +26,43 @@ __device__ __forceinline__ void symv21(const float* __restrict__ c, const float 
     s[3] = c[3] * e[0] + c[8] * e[1] + c[12] * e[2] + c[15] * e[3] + c[16] * e[4] + c[17] * e[5];
     s[4] = c[4] * e[0] + c[9] * e[1] + c[13] * e[2] + c[16] * e[3] + c[18] * e[4] + c[19] * e[5];
     s[5] = c[5] * e[0] + c[10] * e[1] + c[14] * e[2] + c[17] * e[3] + c[19] * e[4] + c[20] * e[5];
+}
+
+// The 21 entries of grain q's table when q is the same in every active lane (e.g. from
+// readfirstlane), read through the scalar data cache: the constant address space lets the
+// compiler use scalar loads, which leave the vector memory path (and its in-order wait
+// counter) to the field data.  Tables are read-only while any kernel that reads them runs.
+typedef const __attribute__((address_space(4))) float* UniformTab;
+__device__ __forceinline__ void uniform_row(const float* tab, int q, float c[21])
+{
+    const UniformTab u = (UniformTab)(tab + (int64_t)q * kTab);
+#pragma unroll
+    for (int i = 0; i < 21; ++i) c[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(u[i])));
+}
+
+// s = C_q e over a wavefront whose lanes mostly share the grain q (neighbouring voxels of a
+// polycrystal).  One grain in the wavefront: one product with its table from scalar loads.
+// Two grains: a product with each (the second in its lanes only).  More: each lane gathers
+// its own table.  Each lane's result is symv21 with its own table.
+__device__ __forceinline__ void symv21_grains(const float* tab, int q, const float e[6], float s[6])
+{
+    const int q0 = __builtin_amdgcn_readfirstlane(q);
+    const uint64_t other = __builtin_amdgcn_ballot_w64(q != q0);
+    float c[21];
+    if (other == 0) {
+        uniform_row(tab, q0, c);
+        symv21(c, e, s);
+    } else {
+        const int q1 = __builtin_amdgcn_readlane(q, (int)__builtin_ctzll(other));
+        if (__builtin_amdgcn_ballot_w64(q != q0 && q != q1) == 0) {
+            uniform_row(tab, q0, c);
+            symv21(c, e, s);
+            uniform_row(tab, q1, c);
+            if (q == q1) symv21(c, e, s);
+        } else {
+            symv21(tab + (int64_t)q * kTab, e, s);
+        }
+    }
 }
 
 // Strain E + B_v u of voxel (vx,vy,vz) of the periodic grid.
@@ -55,26 +93,37 @@ __device__ __forceinline__ void voxel_strain(const float* __restrict__ u, int64_
     e[5] = E[5] + g[0][1] + g[1][0];
 }
 
-// Deterministic block sum of NV doubles per thread into partials[slot * 8 + k] (slot: the
+// Sum over the 256 threads of a block of v[k], k < NVALS, in a fixed order: a butterfly
+// within each wavefront (both lanes of a pair form the same sum), then the four wavefront
+// sums in order.  Thread k < NVALS receives total k; the other threads receive 0.
+template <int NVALS>
+__device__ __forceinline__ double block_total(const double v[NVALS])
+{
+    __shared__ double red[NVALS][4];
+    double s[NVALS];
+#pragma unroll
+    for (int k = 0; k < NVALS; ++k) s[k] = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < NVALS; ++k) s[k] += __shfl_xor(s[k], o, 64);
+    const int t = threadIdx.x;
+    if ((t & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < NVALS; ++k) red[k][t >> 6] = s[k];
+    __syncthreads();
+    return t < NVALS ? (red[t][0] + red[t][1]) + (red[t][2] + red[t][3]) : 0.0;
+}
+
+// Deterministic block sum of NVALS doubles per thread into partials[slot * 8 + k] (slot: the
 // block's logical index, blockIdx.x by default).
 template <int NVALS>
 __device__ __forceinline__ void block_sum_to(double* __restrict__ partials, const double v[NVALS],
                                              int slot = -1)
 {
-    __shared__ double red[NVALS][256];
-    const int t = threadIdx.x;
+    const double s = block_total<NVALS>(v);
     if (slot < 0) slot = (int)blockIdx.x;
-#pragma unroll
-    for (int k = 0; k < NVALS; ++k) red[k][t] = v[k];
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) {
-#pragma unroll
-            for (int k = 0; k < NVALS; ++k) red[k][t] += red[k][t + s];
-        }
-        __syncthreads();
-    }
-    if (t < NVALS) partials[(int64_t)slot * 8 + t] = red[t][0];
+    if (threadIdx.x < NVALS) partials[(int64_t)slot * 8 + threadIdx.x] = s;
 }
 
 // Node-parallel kernels: block b belongs to replica node_rep[b]; within a replica the

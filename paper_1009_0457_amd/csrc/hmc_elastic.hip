@@ -33,15 +33,49 @@ struct GlobArgs {
 
 
 // Tiled explicit step.  A block owns a 32 x 8 tile of nodes in x, y and marches through
-// tile_z node layers in z.  Node layers (with a one-node halo) and voxel stress layers (with the
-// low halo voxel) live in two-slot LDS rings, so each voxel stress is formed once per tile
-// (1.3x with halos) instead of once per corner node (8x).  The arithmetic per voxel and per
-// node, and the order of the 8 corner contributions, are those of the untiled step.
-__global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
+// tile_z node layers in z, so each voxel stress is formed once per tile (1.3x with the halo
+// voxels) instead of once per corner node (8x).  The trilinear element's sums are factored
+// along z, where the march shares them between neighbouring layers:
+//  * per node of the layer pair (z, z+1) and component: S = u(z+1) + u(z), D = u(z+1) - u(z);
+//    a voxel's gradient is then 1/4 of (S10 - S00) + (S11 - S01) in x, (S01 - S00) + (S11 - S10)
+//    in y and D00 + D10 + D01 + D11 in z over its four node columns;
+//  * per voxel column of the layer pair (z-1, z): the stress sums P = s(z) + s(z-1) and
+//    differences M = s(z) - s(z-1) that the three force components need (P of xx, yy, yz,
+//    xz, xy; M of zz, yz, xz); a node's force is then 1/4 of a signed sum over its four
+//    voxel columns.
+// Each thread loads the same (x, y) positions of every layer, so the previous layer's
+// displacements and stresses stay in its registers.  The own nodes' displacements pass
+// through a three-layer LDS ring, which leaves two barriers per layer.  The interior voxels
+// are formed in 8 x 8 patches, one per wavefront, so that a wavefront's voxels mostly share
+// one grain and its stiffness comes through the scalar cache.
+constexpr int kStepVox = (kTileX + 1) * (kTileY + 1);
+static_assert(kTileX == 32 && kTileY == 8, "voxel patches assume a 32 x 8 tile");
+__device__ __forceinline__ void step_voxel_pos(int i, int& ix, int& iy)
+{
+    if (i < 256) {                         // interior: wavefront w takes x in [8w + 1, 8w + 8]
+        ix = 1 + 8 * (i >> 6) + (i & 7);
+        iy = 1 + ((i & 63) >> 3);
+    } else if (i < 256 + kTileX + 1) {     // halo row y = 0
+        ix = i - 256;
+        iy = 0;
+    } else {                               // halo column x = 0
+        ix = 0;
+        iy = i - (256 + kTileX + 1) + 1;
+    }
+}
+
+// (At most 128 VGPRs, so that four blocks share a CU: the LDS would allow five.)
+__global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
 {
     constexpr int NX = kTileX + 2, NY = kTileY + 2, VX = kTileX + 1, VY = kTileY + 1;
-    __shared__ float su[2][3][NY][NX];
-    __shared__ float ss[2][6][VY][VX];
+    constexpr int NP = (NX * NY + 255) / 256, VP = (kStepVox + 255) / 256;
+    // LDS entries are vectors, so that each holds what one lane writes or reads at a time:
+    // node pair (S0, D0, S1, D1) and (S2, D2); voxel pair (P_xx, P_yy, P_yz, P_xz) and
+    // (P_xy, M_zz, M_yz, M_xz); own node (u0, u1, u2, -)
+    __shared__ float4 sNa[NY][NX];
+    __shared__ float2 sNb[NY][NX];
+    __shared__ float4 sPa[VY][VX], sPb[VY][VX];
+    __shared__ float4 sraw[3][kTileY][kTileX];
 
     const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);   // neighbouring tiles share an L2
     const int r = a.tile_rep[lb];
@@ -65,19 +99,13 @@ __global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
 #pragma unroll
     for (int I = 0; I < 6; ++I) E[I] = (float)st[kE + I];
     if (a.E_record && lb == R.tile_first && threadIdx.x < 6) a.E_record[threadIdx.x] = st[kE + threadIdx.x];
-    const float alpha = R.glob_alpha, beta = R.glob_beta;
+    const float alpha4 = 0.25f * R.glob_alpha, beta = R.glob_beta;
     const int t = threadIdx.x, lx = t % kTileX, ly = t / kTileX;
     const int nx = x0 + lx, ny = y0 + ly;
     const bool own = nx < K && ny < K;
     double acc[6] = {0, 0, 0, 0, 0, 0};
 
-    // Node layers are fetched one layer ahead into registers (NP per thread) and stored to
-    // LDS after the barrier, so the global loads of layer z+2 are in flight while layer z is
-    // computed; the voxel layer's spins and the own nodes' w are fetched the same way.
-    constexpr int NP = (NX * NY + 255) / 256, VP = (VX * VY + 255) / 256;
-    float pf[NP][3];
-    int sp[VP];
-    // a thread loads the same (x, y) of the tile in every layer: wrap those once
+    // tile positions this thread loads (nodes) and forms (voxels), the same in every layer
     int node_xy[NP], vox_xy[VP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
@@ -86,9 +114,14 @@ __global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
     }
 #pragma unroll
     for (int k = 0; k < VP; ++k) {
-        const int i = t + 256 * k, ix = i % VX, iy = i / VX;
+        int ix, iy;
+        step_voxel_pos(t + 256 * k, ix, iy);
         vox_xy[k] = wrap_tile(x0 - 1 + ix, K) + K * wrap_tile(y0 - 1 + iy, K);
     }
+    // Node layer z+2 and voxel layer z+1's grains are fetched into registers while layer z
+    // is computed.
+    float pf[NP][3], prev[NP][3];
+    int sp[VP];
     auto fetch_nodes = [&](int z) {
         const int64_t zoff = (int64_t)K * K * wrap_tile(z, K);
 #pragma unroll
@@ -102,83 +135,97 @@ __global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
             }
         }
     };
-    auto store_nodes = [&](int slot) {
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int i = t + 256 * k;
-            if (i < NX * NY) {
-                const int ix = i % NX, iy = i / NX;
-                su[slot][0][iy][ix] = pf[k][0];
-                su[slot][1][iy][ix] = pf[k][1];
-                su[slot][2][iy][ix] = pf[k][2];
-            }
-        }
-    };
     auto fetch_spins = [&](int z) {
         const int64_t zoff = (int64_t)K * K * wrap_tile(z, K);
 #pragma unroll
         for (int k = 0; k < VP; ++k) {
             const int i = t + 256 * k;
             sp[k] = 0;
-            if (i < VX * VY) sp[k] = spins[vox_xy[k] + zoff];
+            if (i < kStepVox) sp[k] = spins[vox_xy[k] + zoff];
         }
     };
-    // voxel layer z from node layers z (slot lo) and z + 1 (slot hi); grains in sp
-    auto voxel_layer = [&](int vs, int lo, int hi, bool owned_layer) {
+    // pf holds node layer z+1 and prev layer z: write the pair's S and D, and layer z+1's own
+    // nodes into ring slot `raw`
+    auto store_pair = [&](int raw) {
 #pragma unroll
-        for (int k = 0; k < VP; ++k) {
+        for (int k = 0; k < NP; ++k) {
             const int i = t + 256 * k;
-            if (i >= VX * VY) continue;
-            const int ix = i % VX, iy = i / VX;
-            float g[3][3];
+            if (i < NX * NY) {
+                const int ix = i % NX, iy = i / NX;
+                sNa[iy][ix] = make_float4(pf[k][0] + prev[k][0], pf[k][0] - prev[k][0], pf[k][1] + prev[k][1],
+                                          pf[k][1] - prev[k][1]);
+                sNb[iy][ix] = make_float2(pf[k][2] + prev[k][2], pf[k][2] - prev[k][2]);
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const float c0 = su[lo][j][iy][ix], c1 = su[lo][j][iy][ix + 1];
-                const float c2 = su[lo][j][iy + 1][ix], c3 = su[lo][j][iy + 1][ix + 1];
-                const float c4 = su[hi][j][iy][ix], c5 = su[hi][j][iy][ix + 1];
-                const float c6 = su[hi][j][iy + 1][ix], c7 = su[hi][j][iy + 1][ix + 1];
-                g[j][0] = 0.25f * ((c1 - c0) + (c3 - c2) + (c5 - c4) + (c7 - c6));
-                g[j][1] = 0.25f * ((c2 + c3) - (c0 + c1) + (c6 + c7) - (c4 + c5));
-                g[j][2] = 0.25f * ((c4 + c5 + c6 + c7) - (c0 + c1 + c2 + c3));
-            }
-            float e[6], s6[6];
-            e[0] = E[0] + g[0][0];
-            e[1] = E[1] + g[1][1];
-            e[2] = E[2] + g[2][2];
-            e[3] = E[3] + g[1][2] + g[2][1];
-            e[4] = E[4] + g[0][2] + g[2][0];
-            e[5] = E[5] + g[0][1] + g[1][0];
-            symv21(Ctab + (int64_t)sp[k] * kTab, e, s6);
-#pragma unroll
-            for (int I = 0; I < 6; ++I) ss[vs][I][iy][ix] = s6[I];
-            const int gx = x0 - 1 + ix, gy = y0 - 1 + iy;
-            if (owned_layer && ix >= 1 && iy >= 1 && gx < K && gy < K) {
-#pragma unroll
-                for (int I = 0; I < 6; ++I) acc[I] += (double)s6[I];
+                for (int j = 0; j < 3; ++j) prev[k][j] = pf[k][j];
+                if (ix >= 1 && ix <= kTileX && iy >= 1 && iy <= kTileY)
+                    sraw[raw][iy - 1][ix - 1] = make_float4(pf[k][0], pf[k][1], pf[k][2], 0.f);
             }
         }
+    };
+    // stress of voxel position k of the layer whose node pair is in sNa / sNb (grains in q)
+    auto voxel_stress = [&](int k, int q, float s6[6]) {
+        int ix, iy;
+        step_voxel_pos(t + 256 * k, ix, iy);
+        // node columns 00, 10, 01, 11 of the voxel: S and D of each component
+        float S[3][4], D[3][4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float4 na = sNa[iy + (c >> 1)][ix + (c & 1)];
+            const float2 nb = sNb[iy + (c >> 1)][ix + (c & 1)];
+            S[0][c] = na.x;
+            D[0][c] = na.y;
+            S[1][c] = na.z;
+            D[1][c] = na.w;
+            S[2][c] = nb.x;
+            D[2][c] = nb.y;
+        }
+        float G[3][3];   // 4 x du_j / dx_d
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            G[j][0] = (S[j][1] - S[j][0]) + (S[j][3] - S[j][2]);
+            G[j][1] = (S[j][2] - S[j][0]) + (S[j][3] - S[j][1]);
+            G[j][2] = (D[j][0] + D[j][1]) + (D[j][2] + D[j][3]);
+        }
+        float e[6];
+        e[0] = E[0] + 0.25f * G[0][0];
+        e[1] = E[1] + 0.25f * G[1][1];
+        e[2] = E[2] + 0.25f * G[2][2];
+        e[3] = E[3] + 0.25f * (G[1][2] + G[2][1]);
+        e[4] = E[4] + 0.25f * (G[0][2] + G[2][0]);
+        e[5] = E[5] + 0.25f * (G[0][1] + G[1][0]);
+        symv21_grains(Ctab, q, e, s6);
     };
 
+    // prologue: node layers z0-1, z0 -> voxel layer z0-1 (kept in registers)
+    int ring = 0;                                // sraw slot of layer z
     fetch_nodes(z0 - 1);
-    store_nodes(0);
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) prev[k][j] = pf[k][j];
     fetch_nodes(z0);
-    store_nodes(1);
     fetch_spins(z0 - 1);
+    store_pair(ring);
     __syncthreads();
-    voxel_layer(0, 0, 1, false);
+    float sprev[VP][6];
+#pragma unroll
+    for (int k = 0; k < VP; ++k)
+        if (t + 256 * k < kStepVox) voxel_stress(k, sp[k], sprev[k]);
     fetch_nodes(z0 + 1);
     fetch_spins(z0);
-    int nlo = 1, vprev = 0;
+    __syncthreads();                             // the prologue's reads of sNa / sNb are done
+
     for (int z = z0; z < z1; ++z) {
-        const int nhi = 1 - nlo, vcur = 1 - vprev;
-        __syncthreads();                       // node layer z-1 and voxel layer z-2 are free
-        store_nodes(nhi);                      // node layer z+1
+        const int ring_next = ring == 2 ? 0 : ring + 1;
+        store_pair(ring_next);                   // pair (z, z+1); own nodes of layer z+1
+        // This layer's grains arrived during the last layer: take them now, so that no
+        // later wait on them also waits for the loads issued below.  The own nodes' w is
+        // needed first (at the end of this layer), so it is requested before the prefetch.
         int sp_cur[VP];
 #pragma unroll
-        for (int k = 0; k < VP; ++k) sp_cur[k] = sp[k];
-        if (z + 1 < z1) {
-            fetch_nodes(z + 2);                // in flight during this layer
-            fetch_spins(z + 1);
+        for (int k = 0; k < VP; ++k) {
+            sp_cur[k] = sp[k];
+            asm volatile("" ::"v"(sp_cur[k]));
         }
         float wz[3] = {0.f, 0.f, 0.f};
         const int64_t n = nx + (int64_t)K * (ny + (int64_t)K * z);
@@ -186,42 +233,52 @@ __global__ __launch_bounds__(256) void k_global_step_tiled(GlobArgs a)
 #pragma unroll
             for (int j = 0; j < 3; ++j) wz[j] = w[(int64_t)j * P + n];
         }
-        __syncthreads();
-        {
-            int sp_next[VP];
-#pragma unroll
-            for (int k = 0; k < VP; ++k) {
-                sp_next[k] = sp[k];
-                sp[k] = sp_cur[k];
-            }
-            voxel_layer(vcur, nlo, nhi, true);
-#pragma unroll
-            for (int k = 0; k < VP; ++k) sp[k] = sp_next[k];
+        if (z + 1 < z1) {
+            fetch_nodes(z + 2);                  // in flight during this layer
+            fetch_spins(z + 1);
         }
-        __syncthreads();
-        if (own) {
-            float f[3] = {0.f, 0.f, 0.f};
+        __syncthreads();                         // the node pair is complete
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const int ca = c & 1, cb = (c >> 1) & 1, cc = c >> 2;
-                const int vx = lx + 1 - ca, vy = ly + 1 - cb, vsl = cc ? vprev : vcur;
-                const float s0 = ss[vsl][0][vy][vx], s1 = ss[vsl][1][vy][vx], s2 = ss[vsl][2][vy][vx];
-                const float s3 = ss[vsl][3][vy][vx], s4 = ss[vsl][4][vy][vx], s5 = ss[vsl][5][vy][vx];
-                const float sx = ca ? 0.25f : -0.25f, sy = cb ? 0.25f : -0.25f, sz = cc ? 0.25f : -0.25f;
-                f[0] += sx * s0 + sy * s5 + sz * s4;
-                f[1] += sx * s5 + sy * s1 + sz * s3;
-                f[2] += sx * s4 + sy * s3 + sz * s2;
+        for (int k = 0; k < VP; ++k) {
+            const int i = t + 256 * k;
+            if (i >= kStepVox) continue;
+            int ix, iy;
+            step_voxel_pos(i, ix, iy);
+            float s6[6];
+            voxel_stress(k, sp_cur[k], s6);
+            sPa[iy][ix] = make_float4(s6[0] + sprev[k][0], s6[1] + sprev[k][1], s6[3] + sprev[k][3],
+                                      s6[4] + sprev[k][4]);
+            sPb[iy][ix] = make_float4(s6[5] + sprev[k][5], s6[2] - sprev[k][2], s6[3] - sprev[k][3],
+                                      s6[4] - sprev[k][4]);
+#pragma unroll
+            for (int I = 0; I < 6; ++I) sprev[k][I] = s6[I];
+            const int gx = x0 - 1 + ix, gy = y0 - 1 + iy;
+            if (ix >= 1 && iy >= 1 && gx < K && gy < K) {
+#pragma unroll
+                for (int I = 0; I < 6; ++I) acc[I] += (double)s6[I];
             }
+        }
+        __syncthreads();                         // the voxel pair is complete
+        if (own) {
+            // the node's voxel columns: a = (lx, ly) and b = (lx+1, ly) below it in y, c, d
+            // the same at ly + 1; x weight + for a, c; y weight + for a, b; z weight - for all
+            const float4 pa = sPa[ly][lx], pb = sPa[ly][lx + 1], pc = sPa[ly + 1][lx], pd = sPa[ly + 1][lx + 1];
+            const float4 qa = sPb[ly][lx], qb = sPb[ly][lx + 1], qc = sPb[ly + 1][lx], qd = sPb[ly + 1][lx + 1];
+            float F[3];
+            F[0] = ((pa.x - pb.x) + (pc.x - pd.x)) + ((qa.x - qc.x) + (qb.x - qd.x)) - ((qa.w + qb.w) + (qc.w + qd.w));
+            F[1] = ((qa.x - qb.x) + (qc.x - qd.x)) + ((pa.y - pc.y) + (pb.y - pd.y)) - ((qa.z + qb.z) + (qc.z + qd.z));
+            F[2] = ((pa.w - pb.w) + (pc.w - pd.w)) + ((pa.z - pc.z) + (pb.z - pd.z)) - ((qa.y + qb.y) + (qc.y + qd.y));
+            const float4 u = sraw[ring][ly][lx];
+            const float uz[3] = {u.x, u.y, u.z};
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const int64_t idx = (int64_t)j * P + n;
-                const float wn = beta * wz[j] - alpha * f[j];
+                const float wn = beta * wz[j] - alpha4 * F[j];
                 w[idx] = wn;
-                uout[idx] = su[nlo][j][ly + 1][lx + 1] + wn;
+                uout[idx] = uz[j] + wn;
             }
         }
-        nlo = nhi;
-        vprev = vcur;
+        ring = ring_next;
     }
     block_sum_to<6>(a.partials, acc, lb);
 }
@@ -237,7 +294,6 @@ struct EArgs {
 // macroscopic strain.
 __global__ __launch_bounds__(256) void k_global_E(EArgs a)
 {
-    __shared__ double red[6][256];
     const RepDev R = a.reps[blockIdx.x];
     double* st = a.state + (int64_t)blockIdx.x * kStateDoubles;
     const int t = threadIdx.x;
@@ -246,17 +302,9 @@ __global__ __launch_bounds__(256) void k_global_E(EArgs a)
     for (int b = t; b < nblk; b += 256)
 #pragma unroll
         for (int I = 0; I < 6; ++I) s[I] += a.partials[(int64_t)(first + b) * 8 + I];
-#pragma unroll
-    for (int I = 0; I < 6; ++I) red[I][t] = s[I];
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (t < h)
-#pragma unroll
-            for (int I = 0; I < 6; ++I) red[I][t] += red[I][t + h];
-        __syncthreads();
-    }
+    const double tot = block_total<6>(s);
     if (t < 6) {
-        const double rE = R.Sigma[t] - red[t][0] / (double)R.n3;
+        const double rE = R.Sigma[t] - tot / (double)R.n3;
         const double wE = (double)R.glob_beta * st[kWE + t] + R.glob_alphaE * rE;
         st[kWE + t] = wE;
         st[kE + t] += wE;
@@ -307,18 +355,13 @@ __global__ __launch_bounds__(256) void k_global_final(FinalArgs a)
 // One block per replica: stored energy = fixed-order sum of the block partials.
 __global__ __launch_bounds__(256) void k_sum_U(double* state, const double* partials, const RepDev* reps)
 {
-    __shared__ double red[256];
     const RepDev R = reps[blockIdx.x];
     const int t = threadIdx.x;
     double s = 0.0;
     for (int b = t; b < R.node_blocks; b += 256) s += partials[(int64_t)(R.node_first + b) * 8];
-    red[t] = s;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (t < h) red[t] += red[t + h];
-        __syncthreads();
-    }
-    if (t == 0) state[(int64_t)blockIdx.x * kStateDoubles + kU] = red[0];
+    const double v[1] = {s};
+    const double tot = block_total<1>(v);
+    if (t == 0) state[(int64_t)blockIdx.x * kStateDoubles + kU] = tot;
 }
 
 struct ReussArgs {
@@ -352,25 +395,16 @@ __global__ __launch_bounds__(256) void k_reuss(ReussArgs a)
 // One block per replica: E = mean(S_q) Sigma, wE = 0.
 __global__ __launch_bounds__(256) void k_reuss_E(double* state, const double* partials, const RepDev* reps)
 {
-    __shared__ double red[6][256];
     const RepDev R = reps[blockIdx.x];
     const int t = threadIdx.x;
     double s[6] = {0, 0, 0, 0, 0, 0};
     for (int b = t; b < R.node_blocks; b += 256)
 #pragma unroll
         for (int I = 0; I < 6; ++I) s[I] += partials[(int64_t)(R.node_first + b) * 8 + I];
-#pragma unroll
-    for (int I = 0; I < 6; ++I) red[I][t] = s[I];
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (t < h)
-#pragma unroll
-            for (int I = 0; I < 6; ++I) red[I][t] += red[I][t + h];
-        __syncthreads();
-    }
+    const double tot = block_total<6>(s);
     if (t < 6) {
         double* st = state + (int64_t)blockIdx.x * kStateDoubles;
-        st[kE + t] = red[t][0] / (double)R.n3;
+        st[kE + t] = tot / (double)R.n3;
         st[kWE + t] = 0.0;
     }
 }
