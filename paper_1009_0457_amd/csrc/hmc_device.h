@@ -65,6 +65,94 @@ __device__ __forceinline__ void symv21_grains(const float* tab, int q, const flo
     }
 }
 
+// Voxel positions of a 32 x 8 node tile's layer (33 x 9 voxels, tile-relative; voxel (ix, iy)
+// has the tile's nodes ix, ix+1 and iy, iy+1 as corners, node 0 being the low halo) in the
+// order the 256 threads of a tiled step take them: first the 32 x 8 voxels whose high corner
+// is an own node, as four 8 x 8 patches, one per wavefront (neighbouring voxels mostly share
+// a grain), then the low halo row and column.
+constexpr int kStepVox = (kTileX + 1) * (kTileY + 1);
+static_assert(kTileX == 32 && kTileY == 8, "voxel patches assume a 32 x 8 tile");
+__device__ __forceinline__ void step_voxel_pos(int i, int& ix, int& iy)
+{
+    if (i < 256) {                         // interior: wavefront w takes x in [8w + 1, 8w + 8]
+        ix = 1 + 8 * (i >> 6) + (i & 7);
+        iy = 1 + ((i & 63) >> 3);
+    } else if (i < 256 + kTileX + 1) {     // halo row y = 0
+        ix = i - 256;
+        iy = 0;
+    } else {                               // halo column x = 0
+        ix = 0;
+        iy = i - (256 + kTileX + 1) + 1;
+    }
+}
+
+// Layer-pair sums of the tiled steps.  A node entry holds, for the pair of node layers
+// (z, z+1), S = u(z+1) + u(z) and D = u(z+1) - u(z) of each component as (S0, D0, S1, D1) and
+// (S2, D2); a voxel entry holds, for the pair of voxel layers (z-1, z), sums P = s(z) + s(z-1)
+// and differences M = s(z) - s(z-1) of a symmetric tensor field as (P_xx, P_yy, P_yz, P_xz)
+// and (P_xy, M_zz, M_yz, M_xz).
+__device__ __forceinline__ void pair_node_entry(const float hi[3], const float lo[3], float4& na, float2& nb)
+{
+    na = make_float4(hi[0] + lo[0], hi[0] - lo[0], hi[1] + lo[1], hi[1] - lo[1]);
+    nb = make_float2(hi[2] + lo[2], hi[2] - lo[2]);
+}
+
+__device__ __forceinline__ void pair_voxel_entry(const float s[6], const float sp[6], float4& pa, float4& pb)
+{
+    pa = make_float4(s[0] + sp[0], s[1] + sp[1], s[3] + sp[3], s[4] + sp[4]);
+    pb = make_float4(s[5] + sp[5], s[2] - sp[2], s[3] - sp[3], s[4] - sp[4]);
+}
+
+// base + the symmetric gradient (engineering shears) of the trilinear field at the centre of
+// voxel (ix, iy) between the two node layers: with S, D at the voxel's node columns 00, 10,
+// 01, 11, 4 du/dx = (S10 - S00) + (S11 - S01), 4 du/dy = (S01 - S00) + (S11 - S10) and
+// 4 du/dz = D00 + D10 + D01 + D11.
+template <int NX>
+__device__ __forceinline__ void pair_strain(const float4 (*Na)[NX], const float2 (*Nb)[NX], int ix, int iy,
+                                            const float base[6], float e[6])
+{
+    float S[3][4], D[3][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const float4 na = Na[iy + (c >> 1)][ix + (c & 1)];
+        const float2 nb = Nb[iy + (c >> 1)][ix + (c & 1)];
+        S[0][c] = na.x;
+        D[0][c] = na.y;
+        S[1][c] = na.z;
+        D[1][c] = na.w;
+        S[2][c] = nb.x;
+        D[2][c] = nb.y;
+    }
+    float G[3][3];   // 4 du_j / dx_d
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        G[j][0] = (S[j][1] - S[j][0]) + (S[j][3] - S[j][2]);
+        G[j][1] = (S[j][2] - S[j][0]) + (S[j][3] - S[j][1]);
+        G[j][2] = (D[j][0] + D[j][1]) + (D[j][2] + D[j][3]);
+    }
+    e[0] = base[0] + 0.25f * G[0][0];
+    e[1] = base[1] + 0.25f * G[1][1];
+    e[2] = base[2] + 0.25f * G[2][2];
+    e[3] = base[3] + 0.25f * (G[1][2] + G[2][1]);
+    e[4] = base[4] + 0.25f * (G[0][2] + G[2][0]);
+    e[5] = base[5] + 0.25f * (G[0][1] + G[1][0]);
+}
+
+// 4 x sum over the 8 voxels around tile node (lx+1, ly+1) of B_v(n)^T s_v, from the voxel
+// pair entries: its voxel columns a = (lx, ly), b = (lx+1, ly), c = (lx, ly+1),
+// d = (lx+1, ly+1) carry x weight + for a, c, y weight + for a, b and z weight + for the
+// lower layer, i.e. - on M.
+template <int VX>
+__device__ __forceinline__ void pair_force(const float4 (*Pa)[VX], const float4 (*Pb)[VX], int lx, int ly,
+                                           float F[3])
+{
+    const float4 pa = Pa[ly][lx], pb = Pa[ly][lx + 1], pc = Pa[ly + 1][lx], pd = Pa[ly + 1][lx + 1];
+    const float4 qa = Pb[ly][lx], qb = Pb[ly][lx + 1], qc = Pb[ly + 1][lx], qd = Pb[ly + 1][lx + 1];
+    F[0] = ((pa.x - pb.x) + (pc.x - pd.x)) + ((qa.x - qc.x) + (qb.x - qd.x)) - ((qa.w + qb.w) + (qc.w + qd.w));
+    F[1] = ((qa.x - qb.x) + (qc.x - qd.x)) + ((pa.y - pc.y) + (pb.y - pd.y)) - ((qa.z + qb.z) + (qc.z + qd.z));
+    F[2] = ((pa.w - pb.w) + (pc.w - pd.w)) + ((pa.z - pc.z) + (pb.z - pd.z)) - ((qa.y + qb.y) + (qc.y + qd.y));
+}
+
 // Strain E + B_v u of voxel (vx,vy,vz) of the periodic grid.
 __device__ __forceinline__ void voxel_strain(const float* __restrict__ u, int64_t n3, int K, int vx, int vy,
                                              int vz, const float E[6], float e[6])

@@ -48,22 +48,6 @@ struct GlobArgs {
 // through a three-layer LDS ring, which leaves two barriers per layer.  The interior voxels
 // are formed in 8 x 8 patches, one per wavefront, so that a wavefront's voxels mostly share
 // one grain and its stiffness comes through the scalar cache.
-constexpr int kStepVox = (kTileX + 1) * (kTileY + 1);
-static_assert(kTileX == 32 && kTileY == 8, "voxel patches assume a 32 x 8 tile");
-__device__ __forceinline__ void step_voxel_pos(int i, int& ix, int& iy)
-{
-    if (i < 256) {                         // interior: wavefront w takes x in [8w + 1, 8w + 8]
-        ix = 1 + 8 * (i >> 6) + (i & 7);
-        iy = 1 + ((i & 63) >> 3);
-    } else if (i < 256 + kTileX + 1) {     // halo row y = 0
-        ix = i - 256;
-        iy = 0;
-    } else {                               // halo column x = 0
-        ix = 0;
-        iy = i - (256 + kTileX + 1) + 1;
-    }
-}
-
 // (At most 128 VGPRs, so that four blocks share a CU: the LDS would allow five.)
 __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
 {
@@ -152,9 +136,7 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
             const int i = t + 256 * k;
             if (i < NX * NY) {
                 const int ix = i % NX, iy = i / NX;
-                sNa[iy][ix] = make_float4(pf[k][0] + prev[k][0], pf[k][0] - prev[k][0], pf[k][1] + prev[k][1],
-                                          pf[k][1] - prev[k][1]);
-                sNb[iy][ix] = make_float2(pf[k][2] + prev[k][2], pf[k][2] - prev[k][2]);
+                pair_node_entry(pf[k], prev[k], sNa[iy][ix], sNb[iy][ix]);
 #pragma unroll
                 for (int j = 0; j < 3; ++j) prev[k][j] = pf[k][j];
                 if (ix >= 1 && ix <= kTileX && iy >= 1 && iy <= kTileY)
@@ -166,33 +148,8 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
     auto voxel_stress = [&](int k, int q, float s6[6]) {
         int ix, iy;
         step_voxel_pos(t + 256 * k, ix, iy);
-        // node columns 00, 10, 01, 11 of the voxel: S and D of each component
-        float S[3][4], D[3][4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const float4 na = sNa[iy + (c >> 1)][ix + (c & 1)];
-            const float2 nb = sNb[iy + (c >> 1)][ix + (c & 1)];
-            S[0][c] = na.x;
-            D[0][c] = na.y;
-            S[1][c] = na.z;
-            D[1][c] = na.w;
-            S[2][c] = nb.x;
-            D[2][c] = nb.y;
-        }
-        float G[3][3];   // 4 x du_j / dx_d
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            G[j][0] = (S[j][1] - S[j][0]) + (S[j][3] - S[j][2]);
-            G[j][1] = (S[j][2] - S[j][0]) + (S[j][3] - S[j][1]);
-            G[j][2] = (D[j][0] + D[j][1]) + (D[j][2] + D[j][3]);
-        }
         float e[6];
-        e[0] = E[0] + 0.25f * G[0][0];
-        e[1] = E[1] + 0.25f * G[1][1];
-        e[2] = E[2] + 0.25f * G[2][2];
-        e[3] = E[3] + 0.25f * (G[1][2] + G[2][1]);
-        e[4] = E[4] + 0.25f * (G[0][2] + G[2][0]);
-        e[5] = E[5] + 0.25f * (G[0][1] + G[1][0]);
+        pair_strain<NX>(sNa, sNb, ix, iy, E, e);
         symv21_grains(Ctab, q, e, s6);
     };
 
@@ -246,10 +203,7 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
             step_voxel_pos(i, ix, iy);
             float s6[6];
             voxel_stress(k, sp_cur[k], s6);
-            sPa[iy][ix] = make_float4(s6[0] + sprev[k][0], s6[1] + sprev[k][1], s6[3] + sprev[k][3],
-                                      s6[4] + sprev[k][4]);
-            sPb[iy][ix] = make_float4(s6[5] + sprev[k][5], s6[2] - sprev[k][2], s6[3] - sprev[k][3],
-                                      s6[4] - sprev[k][4]);
+            pair_voxel_entry(s6, sprev[k], sPa[iy][ix], sPb[iy][ix]);
 #pragma unroll
             for (int I = 0; I < 6; ++I) sprev[k][I] = s6[I];
             const int gx = x0 - 1 + ix, gy = y0 - 1 + iy;
@@ -260,14 +214,8 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
         }
         __syncthreads();                         // the voxel pair is complete
         if (own) {
-            // the node's voxel columns: a = (lx, ly) and b = (lx+1, ly) below it in y, c, d
-            // the same at ly + 1; x weight + for a, c; y weight + for a, b; z weight - for all
-            const float4 pa = sPa[ly][lx], pb = sPa[ly][lx + 1], pc = sPa[ly + 1][lx], pd = sPa[ly + 1][lx + 1];
-            const float4 qa = sPb[ly][lx], qb = sPb[ly][lx + 1], qc = sPb[ly + 1][lx], qd = sPb[ly + 1][lx + 1];
             float F[3];
-            F[0] = ((pa.x - pb.x) + (pc.x - pd.x)) + ((qa.x - qc.x) + (qb.x - qd.x)) - ((qa.w + qb.w) + (qc.w + qd.w));
-            F[1] = ((qa.x - qb.x) + (qc.x - qd.x)) + ((pa.y - pc.y) + (pb.y - pd.y)) - ((qa.z + qb.z) + (qc.z + qd.z));
-            F[2] = ((pa.w - pb.w) + (pc.w - pd.w)) + ((pa.z - pc.z) + (pb.z - pd.z)) - ((qa.y + qb.y) + (qc.y + qd.y));
+            pair_force<VX>(sPa, sPb, lx, ly, F);
             const float4 u = sraw[ring][ly][lx];
             const float uz[3] = {u.x, u.y, u.z};
 #pragma unroll
