@@ -17,8 +17,8 @@ import pytest
 
 import oracle as O
 from paper_1009_0457_amd import hmc as H
-from paper_1009_0457_amd.synth import (full_config, large_config, random_spins, tiny_config,
-                                       voronoi_polycrystal)
+from paper_1009_0457_amd.synth import (Microstructure, full_config, haar_euler, large_config, random_spins,
+                                       tiny_config, voronoi_polycrystal)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -147,6 +147,68 @@ def test_refresh_matches_oracle(K, ng, steps, tile_z):
     s_gpu2 = lat.get_stress().cpu().numpy().astype(np.float64)
     assert np.linalg.norm(s_gpu2 - s2) / np.linalg.norm(s2) <= 1e-4
     lat.close()
+
+
+def _patch_grain_counts(K, spins):
+    """Distinct grains in each 8 x 8 (x, y) patch of each layer, the patches the explicit step
+    hands to one wavefront (aligned to multiples of 8, wrapped at the lattice edge)."""
+    q = spins.reshape(K, K, K)   # z, y, x
+    counts = []
+    for z in range(K):
+        for y0 in range(0, K, 8):
+            for x0 in range(0, K, 8):
+                ys = [(y0 + j) % K for j in range(8)]
+                xs = [(x0 + i) % K for i in range(8)]
+                counts.append(len(np.unique(q[z][np.ix_(ys, xs)])))
+    return np.array(counts)
+
+
+@pytest.mark.parametrize("kind", ["bicrystal", "random"])
+def test_refresh_grain_paths(kind):
+    """The explicit step reads a voxel's stiffness by scalar loads when the voxels of its
+    wavefront belong to one or two grains and by a per-lane gather otherwise.  An oblique
+    bicrystal gives wavefronts of one and of two grains; per-voxel random grains give
+    wavefronts of many.  Both match the oracle, and relabelling the grains (which changes
+    which grain a wavefront meets first) leaves the GPU result bit-identical."""
+    K, steps = 34, 120
+    rng = np.random.default_rng(21)
+    if kind == "bicrystal":
+        x = np.arange(K)
+        zz, yy, xx = np.meshgrid(x, x, x, indexing="ij")
+        spins = ((xx + 2 * yy + 3 * zz) >= 3 * K).astype(np.int32).ravel()
+        euler = haar_euler(rng, 2)
+    else:
+        spins = random_spins(K, 40, 17)
+        euler = haar_euler(rng, 40)
+    counts = _patch_grain_counts(K, spins)
+    if kind == "bicrystal":
+        assert counts.max() == 2 and (counts == 1).any() and (counts == 2).any()
+    else:
+        assert (counts >= 3).all()
+    say(f"[refresh grain paths] {kind}: patches with 1 / 2 / 3+ grains: {(counts == 1).sum()} / "
+        f"{(counts == 2).sum()} / {(counts >= 3).sum()}")
+    micro = Microstructure(K, spins, euler)
+    sig = np.array([120.0, -40.0, 80.0, 30.0, -20.0, 10.0])
+    p, lat = make_lattice(K, 26, 1, micro)
+    lat.set_load(sig)
+    lat.stress_refresh(steps, True)
+    s_gpu = lat.get_stress().cpu().numpy()
+    lat.close()
+    Ct, St, _ = O.tables(euler, p.C11, p.C12, p.C44)
+    _, E, s_ora, _ = O.global_solve(K, spins, Ct, St, sig * 1e-3, steps, True, p.glob_alpha, p.glob_beta,
+                                    p.glob_alphaE)
+    rel = np.linalg.norm(s_gpu.astype(np.float64) - s_ora) / np.linalg.norm(s_ora)
+    say(f"    rel |dsigma| = {rel:.3e}")
+    assert rel <= 1e-4
+    perm = rng.permutation(micro.Q).astype(np.int32)
+    euler2 = np.empty_like(euler)
+    euler2[perm] = euler
+    micro2 = Microstructure(K, perm[spins], euler2)
+    _, lat2 = make_lattice(K, 26, 1, micro2)
+    lat2.set_load(sig)
+    lat2.stress_refresh(steps, True)
+    assert np.array_equal(lat2.get_stress().cpu().numpy(), s_gpu)
+    lat2.close()
 
 
 def test_refresh_single_crystal_closed_form():
