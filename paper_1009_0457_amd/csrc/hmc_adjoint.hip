@@ -158,17 +158,46 @@ struct AdjStepArgs {
     float alpha, beta;
 };
 
-// One adjoint step, tiled as the forward step: a block owns a 32 x 8 x tile_z node tile;
-// the nodal field a = alpha (w~) and the forward displacement u_t pass through two-slot LDS
-// rings of node layers (one-node halo), the adjoint stresses tau through a ring of voxel
-// layers.  Each voxel's tau is formed once per tile; the voxels the block owns also add
-// their angle contractions to G and their tau to the block's partial sums.
+// tau = C_q eta and, where `owned`, gq_k = eta . (dC_{q,k} eps) for the three angles k,
+// with the tables of a wavefront's first two grains from scalar loads (as symv21_grains);
+// wavefronts with more grains gather per lane.
+__device__ __forceinline__ void adjoint_voxel(const float* Ctab, const float* dC, int q, bool owned,
+                                              const float eta[6], const float eps[6], float tau[6], double gq[3])
+{
+    auto with_rows = [&](int g) {   // g is the same in every active lane
+        float c[21];
+        uniform_row(Ctab, g, c);
+        symv21(c, eta, tau);
+        if (owned) angle_contractions(dC, g, eta, eps, gq);
+    };
+    const int q0 = __builtin_amdgcn_readfirstlane(q);
+    const uint64_t other = __builtin_amdgcn_ballot_w64(q != q0);
+    if (other == 0) {
+        with_rows(q0);
+    } else {
+        const int q1 = __builtin_amdgcn_readlane(q, (int)__builtin_ctzll(other));
+        if (__builtin_amdgcn_ballot_w64(q != q0 && q != q1) == 0) {
+            with_rows(q0);
+            if (q == q1) with_rows(q1);
+        } else {
+            symv21(Ctab + (int64_t)q * kTab, eta, tau);
+            if (owned) angle_contractions(dC, q, eta, eps, gq);
+        }
+    }
+}
+
+// One adjoint step, tiled as the forward step (32 x 8 x tile_z nodes per block, layer-pair
+// sums of the nodal fields and of the voxel stresses in LDS, previous layer in registers):
+// the nodal field a = alpha (w^ + u^) and the forward displacement u_t give each voxel its
+// adjoint strain eta and forward strain eps; tau = C eta is formed once per tile, and the
+// voxels the block owns also add their angle contractions to G and tau to the block's sums.
 __global__ __launch_bounds__(256) void k_adj_step(AdjStepArgs a)
 {
     constexpr int NX = kTileX + 2, NY = kTileY + 2, VX = kTileX + 1, VY = kTileY + 1;
-    __shared__ float sa[2][3][NY][NX];
-    __shared__ float sf[2][3][NY][NX];
-    __shared__ float ss[2][6][VY][VX];
+    constexpr int NP = (NX * NY + 255) / 256, VP = (kStepVox + 255) / 256;
+    __shared__ float4 sAa[NY][NX], sUa[NY][NX];
+    __shared__ float2 sAb[NY][NX], sUb[NY][NX];
+    __shared__ float4 sPa[VY][VX], sPb[VY][VX];
 
     const RepDev R = a.reps[0];
     const int K = R.K;
@@ -194,105 +223,162 @@ __global__ __launch_bounds__(256) void k_adj_step(AdjStepArgs a)
     const bool own = nx < K && ny < K;
     double acc[6] = {0, 0, 0, 0, 0, 0};
 
-    auto load_nodes = [&](int slot, int z) {
+    int node_xy[NP], vox_xy[VP];
+    bool vox_own[VP];   // only interior positions (k = 0) can be owned
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int i = t + 256 * k, ix = i % NX, iy = i / NX;
+        node_xy[k] = wrap_tile(x0 - 1 + ix, K) + K * wrap_tile(y0 - 1 + iy, K);
+    }
+#pragma unroll
+    for (int k = 0; k < VP; ++k) {
+        int ix, iy;
+        step_voxel_pos(t + 256 * k, ix, iy);
+        vox_xy[k] = wrap_tile(x0 - 1 + ix, K) + K * wrap_tile(y0 - 1 + iy, K);
+        vox_own[k] = t + 256 * k < kStepVox && ix >= 1 && iy >= 1 && x0 - 1 + ix < K && y0 - 1 + iy < K;
+    }
+    // the fetched node layer (w^, u^ for a, and u_t) at the thread's positions; the previous
+    // layer's a and u_t stay in registers for the pair sums
+    float fw[NP][3], fb[NP][3], fu[NP][3], prevA[NP][3], prevU[NP][3];
+    int sp[VP];
+    auto fetch_nodes = [&](int z) {
         const int64_t zoff = (int64_t)K * K * wrap_tile(z, K);
-        for (int i = t; i < NX * NY; i += 256) {
-            const int ix = i % NX, iy = i / NX;
-            const int64_t n = wrap_tile(x0 - 1 + ix, K) + (int64_t)K * wrap_tile(y0 - 1 + iy, K) + zoff;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            if (t + 256 * k < NX * NY) {
+                const int64_t n = node_xy[k] + zoff;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    fw[k][j] = a.wb_in[j * n3 + n];
+                    fb[k][j] = a.ub_in[j * n3 + n];
+                    fu[k][j] = a.u_t[j * n3 + n];
+                }
+            }
+        }
+    };
+    auto fetch_spins = [&](int z) {
+        const int64_t zoff = (int64_t)K * K * wrap_tile(z, K);
+#pragma unroll
+        for (int k = 0; k < VP; ++k) {
+            sp[k] = 0;
+            if (t + 256 * k < kStepVox) sp[k] = a.spins[vox_xy[k] + zoff];
+        }
+    };
+    // the fetched layer is z+1, prev* hold layer z: write the pair's entries
+    auto store_pair = [&]() {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int i = t + 256 * k;
+            if (i < NX * NY) {
+                const int ix = i % NX, iy = i / NX;
+                float an[3];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) an[j] = alpha * (fw[k][j] + fb[k][j]);
+                pair_node_entry(an, prevA[k], sAa[iy][ix], sAb[iy][ix]);
+                pair_node_entry(fu[k], prevU[k], sUa[iy][ix], sUb[iy][ix]);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    prevA[k][j] = an[j];
+                    prevU[k][j] = fu[k][j];
+                }
+            }
+        }
+    };
+    auto take_prev = [&]() {
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                sa[slot][j][iy][ix] = alpha * (a.wb_in[j * n3 + n] + a.ub_in[j * n3 + n]);
-                sf[slot][j][iy][ix] = a.u_t[j * n3 + n];
+                prevA[k][j] = alpha * (fw[k][j] + fb[k][j]);
+                prevU[k][j] = fu[k][j];
             }
-        }
     };
-    // centre-point gradient of a node field held in two ring slots
-    auto gradient = [&](float (*f)[3][NY][NX], int lo, int hi, int ix, int iy, float g[3][3]) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const float c0 = f[lo][j][iy][ix], c1 = f[lo][j][iy][ix + 1];
-            const float c2 = f[lo][j][iy + 1][ix], c3 = f[lo][j][iy + 1][ix + 1];
-            const float c4 = f[hi][j][iy][ix], c5 = f[hi][j][iy][ix + 1];
-            const float c6 = f[hi][j][iy + 1][ix], c7 = f[hi][j][iy + 1][ix + 1];
-            g[j][0] = 0.25f * ((c1 - c0) + (c3 - c2) + (c5 - c4) + (c7 - c6));
-            g[j][1] = 0.25f * ((c2 + c3) - (c0 + c1) + (c6 + c7) - (c4 + c5));
-            g[j][2] = 0.25f * ((c4 + c5 + c6 + c7) - (c0 + c1 + c2 + c3));
-        }
-    };
-    auto voxel_layer = [&](int vs, int lo, int hi, int z, bool owned_layer) {
-        const int64_t zoff = (int64_t)K * K * wrap_tile(z, K);
-        for (int i = t; i < VX * VY; i += 256) {
-            const int ix = i % VX, iy = i / VX;
-            float g[3][3];
-            gradient(sa, lo, hi, ix, iy, g);
-            float eta[6], tau[6];
-            eta[0] = b3[0] + g[0][0];
-            eta[1] = b3[1] + g[1][1];
-            eta[2] = b3[2] + g[2][2];
-            eta[3] = b3[3] + g[1][2] + g[2][1];
-            eta[4] = b3[4] + g[0][2] + g[2][0];
-            eta[5] = b3[5] + g[0][1] + g[1][0];
-            const int gx = x0 - 1 + ix, gy = y0 - 1 + iy;
-            const int64_t v = wrap_tile(gx, K) + (int64_t)K * wrap_tile(gy, K) + zoff;
-            const int q = a.spins[v];
-            symv21(a.Ctab + (int64_t)q * kTab, eta, tau);
-#pragma unroll
-            for (int I = 0; I < 6; ++I) ss[vs][I][iy][ix] = tau[I];
-            if (owned_layer && ix >= 1 && iy >= 1 && gx < K && gy < K) {
-#pragma unroll
-                for (int I = 0; I < 6; ++I) acc[I] += (double)tau[I];
-                gradient(sf, lo, hi, ix, iy, g);
-                float eps[6];
-                eps[0] = E[0] + g[0][0];
-                eps[1] = E[1] + g[1][1];
-                eps[2] = E[2] + g[2][2];
-                eps[3] = E[3] + g[1][2] + g[2][1];
-                eps[4] = E[4] + g[0][2] + g[2][0];
-                eps[5] = E[5] + g[0][1] + g[1][0];
-                double gq[3];
-                angle_contractions(a.dC, q, eta, eps, gq);
-#pragma unroll
-                for (int qa = 0; qa < 3; ++qa) a.G[(int64_t)qa * n3 + v] -= gq[qa];
-            }
-        }
+    // adjoint stress of voxel position k (and, if owned, its angle contractions)
+    auto voxel_adj = [&](int k, int q, bool owned, float tau[6], double gq[3]) {
+        int ix, iy;
+        step_voxel_pos(t + 256 * k, ix, iy);
+        float eta[6], eps[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        pair_strain<NX>(sAa, sAb, ix, iy, b3, eta);
+        if (owned) pair_strain<NX>(sUa, sUb, ix, iy, E, eps);
+        adjoint_voxel(a.Ctab, a.dC, q, owned, eta, eps, tau, gq);
     };
 
-    load_nodes(0, z0 - 1);
-    load_nodes(1, z0);
+    // prologue: node layers z0-1, z0 -> voxel layer z0-1 (kept in registers)
+    fetch_nodes(z0 - 1);
+    take_prev();
+    fetch_nodes(z0);
+    fetch_spins(z0 - 1);
+    store_pair();
     __syncthreads();
-    voxel_layer(0, 0, 1, z0 - 1, false);
-    int nlo = 1, vprev = 0;
-    for (int z = z0; z < z1; ++z) {
-        const int nhi = 1 - nlo, vcur = 1 - vprev;
-        __syncthreads();
-        load_nodes(nhi, z + 1);
-        __syncthreads();
-        voxel_layer(vcur, nlo, nhi, z, true);
-        __syncthreads();
-        if (own) {
-            float f[3] = {0.f, 0.f, 0.f};
+    float tprev[VP][6];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const int ca = c & 1, cb = (c >> 1) & 1, cc = c >> 2;
-                const int vx = lx + 1 - ca, vy = ly + 1 - cb, vsl = cc ? vprev : vcur;
-                const float s0 = ss[vsl][0][vy][vx], s1 = ss[vsl][1][vy][vx], s2 = ss[vsl][2][vy][vx];
-                const float s3 = ss[vsl][3][vy][vx], s4 = ss[vsl][4][vy][vx], s5 = ss[vsl][5][vy][vx];
-                const float sx = ca ? 0.25f : -0.25f, sy = cb ? 0.25f : -0.25f, sz = cc ? 0.25f : -0.25f;
-                f[0] += sx * s0 + sy * s5 + sz * s4;
-                f[1] += sx * s5 + sy * s1 + sz * s3;
-                f[2] += sx * s4 + sy * s3 + sz * s2;
+    for (int k = 0; k < VP; ++k)
+        if (t + 256 * k < kStepVox) {
+            double unused[3];
+            voxel_adj(k, sp[k], false, tprev[k], unused);
+        }
+    fetch_spins(z0);
+    __syncthreads();
+
+    for (int z = z0; z < z1; ++z) {
+        fetch_nodes(z + 1);
+        store_pair();                            // pair (z, z+1)
+        int sp_cur[VP];
+#pragma unroll
+        for (int k = 0; k < VP; ++k) {
+            sp_cur[k] = sp[k];
+            asm volatile("" ::"v"(sp_cur[k]));   // take them before the loads below are issued
+        }
+        // requested in the order needed: this layer's G of the owned voxels, the own nodes'
+        // w^ and u^, then the next layer's grains
+        const int64_t zoff = (int64_t)K * K * z;
+        double Gv[3] = {0.0, 0.0, 0.0};
+        if (vox_own[0]) {
+#pragma unroll
+            for (int qa = 0; qa < 3; ++qa) Gv[qa] = a.G[(int64_t)qa * n3 + vox_xy[0] + zoff];
+        }
+        float wn_in[3] = {0.f, 0.f, 0.f}, un_in[3] = {0.f, 0.f, 0.f};
+        const int64_t n = nx + (int64_t)K * ny + zoff;
+        if (own) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                wn_in[j] = a.wb_in[(int64_t)j * n3 + n];
+                un_in[j] = a.ub_in[(int64_t)j * n3 + n];
             }
-            const int64_t n = nx + (int64_t)K * (ny + (int64_t)K * z);
+        }
+        if (z + 1 < z1) fetch_spins(z + 1);
+        __syncthreads();                         // the node pairs are complete
+#pragma unroll
+        for (int k = 0; k < VP; ++k) {
+            const int i = t + 256 * k;
+            if (i >= kStepVox) continue;
+            int ix, iy;
+            step_voxel_pos(i, ix, iy);
+            const bool owned = k == 0 && vox_own[0];   // the halo (k >= 1) is never owned
+            float tau[6];
+            double gq[3] = {0.0, 0.0, 0.0};
+            voxel_adj(k, sp_cur[k], owned, tau, gq);
+            pair_voxel_entry(tau, tprev[k], sPa[iy][ix], sPb[iy][ix]);
+#pragma unroll
+            for (int I = 0; I < 6; ++I) tprev[k][I] = tau[I];
+            if (owned) {
+#pragma unroll
+                for (int I = 0; I < 6; ++I) acc[I] += (double)tau[I];
+#pragma unroll
+                for (int qa = 0; qa < 3; ++qa) a.G[(int64_t)qa * n3 + vox_xy[k] + zoff] = Gv[qa] - gq[qa];
+            }
+        }
+        __syncthreads();                         // the voxel pair is complete
+        if (own) {
+            float F[3];
+            pair_force<VX>(sPa, sPb, lx, ly, F);
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const int64_t idx = (int64_t)j * n3 + n;
-                const float u_in = a.ub_in[idx];
-                a.ub_out[idx] = u_in - f[j];
-                a.wb_out[idx] = beta * (a.wb_in[idx] + u_in);
+                a.ub_out[idx] = un_in[j] - 0.25f * F[j];
+                a.wb_out[idx] = beta * (wn_in[j] + un_in[j]);
             }
         }
-        nlo = nhi;
-        vprev = vcur;
     }
     block_sum_to<6>(a.partials, acc, lb);
 }
