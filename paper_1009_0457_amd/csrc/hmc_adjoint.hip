@@ -538,7 +538,6 @@ hmc_status check_adj(hmc_ctx c, int n_steps, int k, void* ws, size_t bytes, AdjL
 }  // namespace
 
 namespace hmc {
-hipError_t launch_global_step_ptrs(hmc_ctx_s* c, const float* uin, float* uout, double* E_record);
 }
 
 extern "C" {
@@ -565,12 +564,10 @@ hmc_status hmc_elastic_forward(hmc_ctx c, int32_t n_steps, int32_t ckpt_every, v
     ATRY(launch_fill_f32(c->d.w, 0.f, 3 * c->total_sites, c->stream), "forward");
     c->cur_u = 0;
     ATRY(launch_reuss(c), "forward");
-    for (int t = 0; t < n_steps; ++t) {
-        if (t % ckpt_every == 0) {
-            st = save_ckpt(c, base, L, t / ckpt_every);
-            if (st != HMC_OK) return st;
-        }
-        ATRY(launch_global_steps(c, 1), "forward");
+    for (int t = 0; t < n_steps; t += ckpt_every) {
+        st = save_ckpt(c, base, L, t / ckpt_every);
+        if (st != HMC_OK) return st;
+        ATRY(launch_global_steps(c, (t + ckpt_every < n_steps) ? ckpt_every : n_steps - t), "forward");
     }
     st = save_ckpt(c, base, L, L.n_ck - 1);   // final state
     if (st != HMC_OK) return st;
@@ -650,15 +647,17 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
         // recompute the segment's forward states u_t, E_t for t in [t0, t1)
         st = load_ckpt(c, base, L, j, seg_u);
         if (st != HMC_OK) return st;
-        for (int t = t0; t < t1; ++t) {
-            float* ut = seg_u + (size_t)(t - t0) * 3 * n3;
-            double* Et = seg_E + (size_t)(t - t0) * 8;
-            if (t + 1 < t1)
-                ATRY(launch_global_step_ptrs(c, ut, ut + 3 * n3, Et), "backward: recompute");   // records E_t
-            else
-                ATRY(hipMemcpyAsync(Et, c->d.state + kE, 6 * sizeof(double), hipMemcpyDeviceToDevice, c->stream),
-                     "backward: recompute");
+        if (t1 - 1 > t0) {
+            ATRY(seq_begin(c), "backward: recompute");
+            for (int t = t0; t + 1 < t1; ++t) {
+                float* ut = seg_u + (size_t)(t - t0) * 3 * n3;
+                ATRY(seq_step(c, t - t0, ut, ut + 3 * n3, seg_E + (size_t)(t - t0) * 8), "backward: recompute");   // records E_t
+            }
+            ATRY(seq_end(c, t1 - 1 - t0), "backward: recompute");
         }
+        ATRY(hipMemcpyAsync(seg_E + (size_t)(t1 - 1 - t0) * 8, c->d.state + kE, 6 * sizeof(double),
+                            hipMemcpyDeviceToDevice, c->stream),
+             "backward: recompute");
         // adjoint steps t1-1 .. t0
         for (int t = t1 - 1; t >= t0; --t) {
             AdjStepArgs a;

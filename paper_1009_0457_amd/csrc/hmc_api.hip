@@ -78,7 +78,8 @@ hmc_replica replica_of_params(const hmc_params* p, int32_t Q)
 // workspace layout
 // ------------------------------------------------------------------------------------
 struct Layout {
-    size_t spins, Ctab, Stab, sigma, u0, u1, w, list, accept, state, partials, counters, stats, thr, tex, hist,
+    size_t spins, Ctab, Stab, sigma, u0, u1, w, list, accept, state, partials, sums, seq_state, counters, stats,
+        thr, tex, hist,
         bonds, reps, pass_rep, node_rep, tile_rep, sweep, total;
     int64_t sites, grains, max_list;
     int pass_blocks, node_blocks, tile_blocks, tile_z;
@@ -136,6 +137,8 @@ Layout layout_of(const hmc_params* p, int n, const hmc_replica* r)
     L.state = take((size_t)n * kStateDoubles * sizeof(double));
     const int pblocks = L.node_blocks > L.tile_blocks ? L.node_blocks : L.tile_blocks;
     L.partials = take((size_t)pblocks * 8 * sizeof(double));
+    L.sums = take((size_t)3 * n * kSumSlots * sizeof(unsigned long long));
+    L.seq_state = take((size_t)2 * n * kSeqState * sizeof(double));
     L.counters = take(kCounters * sizeof(uint32_t));
     L.stats = take(kStats * kStatCopies * sizeof(unsigned long long));
     L.thr = take((size_t)n * 64 * sizeof(uint64_t));
@@ -458,6 +461,8 @@ hmc_status build_context(const hmc_params* p, int n, const hmc_replica* r, void*
     }
     c->d.state = (double*)(b + L.state);
     c->d.partials = (double*)(b + L.partials);
+    c->d.sums = (unsigned long long*)(b + L.sums);
+    c->d.seq_state = (double*)(b + L.seq_state);
     c->d.counters = (uint32_t*)(b + L.counters);
     c->d.stats = (unsigned long long*)(b + L.stats);
     c->d.thr = (uint64_t*)(b + L.thr);

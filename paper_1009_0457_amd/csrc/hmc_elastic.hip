@@ -9,9 +9,10 @@
 //     r_n = -sum_{v at n} B_v(n)^T sigma_v,   w <- beta w + alpha r,   u <- u + w
 //     r_E = Sigma - mean_v sigma_v,          wE <- beta wE + alphaE r_E,  E <- E + wE
 // k_global_step_tiled does the node part for every node (reading u, writing the other u
-// buffer, so no node sees a half-updated neighbour) and writes per-block sums of the
-// stresses it formed; k_global_E folds those sums in a fixed order (deterministic) and
-// advances E.  k_global_final writes the stress field the zone solves read.
+// buffer, so no node sees a half-updated neighbour) and adds its blocks' stress sums into
+// fixed-point accumulators; the next step's blocks first advance E from them, and
+// k_seq_fold does so after a sequence's last step.  k_global_final writes the stress field
+// the zone solves read.
 #include "hmc_device.h"
 
 namespace hmc {
@@ -22,14 +23,37 @@ struct GlobArgs {
     const float* uin;
     float* uout;
     float* w;
-    double* partials;
-    const double* state;
-    double* E_record;        // optional: receives the step's input E (single lattice)
+    const unsigned long long* sums_in;   // the previous step's stress sums (null: first step)
+    unsigned long long* sums_out;        // this step's
+    unsigned long long* sums_clear;      // the next step's, cleared here
+    const double* st_in;     // (E, wE) the previous step started from, or the context's state
+    int st_in_stride;        // doubles per replica in st_in
+    double* st_out;          // (E, wE) of this step (kSeqState per replica)
+    double* E_record;        // optional: receives the step's E (single lattice)
     const RepDev* reps;
-    const int32_t* node_rep;
     const int32_t* tile_rep;
     int64_t plane;
 };
+
+// (E, wE) of the step after the one that started from st_in and whose stress sums are in
+// sums (Sec. 5's average-stress control: r_E = Sigma - <sigma>, wE <- beta wE + alphaE r_E,
+// E <- E + wE), component I; sums == null: st_in unchanged.
+__device__ __forceinline__ void advance_E(const RepDev* reps, int r, const double* st_in, int stride,
+                                          const unsigned long long* sums, int I, double& E_I, double& wE_I)
+{
+    const RepDev& R = reps[r];
+    E_I = st_in[(int64_t)r * stride + I];
+    wE_I = st_in[(int64_t)r * stride + 6 + I];
+    if (sums) {
+        const unsigned long long* sm = sums + (int64_t)r * kSumSlots + I;
+        long long tot = 0;
+#pragma unroll
+        for (int c = 0; c < kSumCopies; ++c) tot += (long long)sm[c * 8];
+        const double rE = R.Sigma[I] - (double)tot / (kSumScale * (double)R.n3);
+        wE_I = (double)R.glob_beta * wE_I + R.glob_alphaE * rE;
+        E_I += wE_I;
+    }
+}
 
 
 // Tiled explicit step.  A block owns a 32 x 8 tile of nodes in x, y and marches through
@@ -78,11 +102,21 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
     float* uout = a.uout + R.site_off;
     float* w = a.w + R.site_off;
     const int64_t P = a.plane;
-    const double* st = a.state + (int64_t)r * kStateDoubles;
+    // this step's E (read after the prologue's first barrier); the replica's first block
+    // records it and clears the accumulators of the step after
+    __shared__ double sE[6];
+    if (threadIdx.x < 6) {
+        double E_I, wE_I;
+        advance_E(a.reps, r, a.st_in, a.st_in_stride, a.sums_in, threadIdx.x, E_I, wE_I);
+        sE[threadIdx.x] = E_I;
+        if (lb == R.tile_first) {
+            a.st_out[(int64_t)r * kSeqState + threadIdx.x] = E_I;
+            a.st_out[(int64_t)r * kSeqState + 6 + threadIdx.x] = wE_I;
+            if (a.E_record) a.E_record[threadIdx.x] = E_I;
+        }
+    }
+    if (lb == R.tile_first && threadIdx.x < kSumSlots) a.sums_clear[(int64_t)r * kSumSlots + threadIdx.x] = 0ull;
     float E[6];
-#pragma unroll
-    for (int I = 0; I < 6; ++I) E[I] = (float)st[kE + I];
-    if (a.E_record && lb == R.tile_first && threadIdx.x < 6) a.E_record[threadIdx.x] = st[kE + threadIdx.x];
     const float alpha4 = 0.25f * R.glob_alpha, beta = R.glob_beta;
     const int t = threadIdx.x, lx = t % kTileX, ly = t / kTileX;
     const int nx = x0 + lx, ny = y0 + ly;
@@ -164,6 +198,8 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
     fetch_spins(z0 - 1);
     store_pair(ring);
     __syncthreads();
+#pragma unroll
+    for (int I = 0; I < 6; ++I) E[I] = (float)sE[I];
     float sprev[VP][6];
 #pragma unroll
     for (int k = 0; k < VP; ++k)
@@ -228,35 +264,24 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
         }
         ring = ring_next;
     }
-    block_sum_to<6>(a.partials, acc, lb);
+    const double tot = block_total<6>(acc);
+    if (threadIdx.x < 6) {
+        const unsigned copy = (unsigned)(lb - R.tile_first) & (kSumCopies - 1);
+        atomicAdd(a.sums_out + (int64_t)r * kSumSlots + copy * 8 + threadIdx.x,
+                  (unsigned long long)llrint(tot * kSumScale));
+    }
 }
 
-struct EArgs {
-    double* state;
-    const double* partials;
-    const RepDev* reps;
-    int tiled;            // partial sums come from the tiled step's blocks
-};
-
-// One block per replica: folds its per-block stress sums (fixed order) and advances the
-// macroscopic strain.
-__global__ __launch_bounds__(256) void k_global_E(EArgs a)
+// After a sequence's last step: the context's (E, wE), one block per replica.
+__global__ void k_seq_fold(double* state, const double* st_last, const unsigned long long* sums_last,
+                           const RepDev* reps)
 {
-    const RepDev R = a.reps[blockIdx.x];
-    double* st = a.state + (int64_t)blockIdx.x * kStateDoubles;
-    const int t = threadIdx.x;
-    double s[6] = {0, 0, 0, 0, 0, 0};
-    const int first = a.tiled ? R.tile_first : R.node_first, nblk = a.tiled ? R.tile_blocks : R.node_blocks;
-    for (int b = t; b < nblk; b += 256)
-#pragma unroll
-        for (int I = 0; I < 6; ++I) s[I] += a.partials[(int64_t)(first + b) * 8 + I];
-    const double tot = block_total<6>(s);
-    if (t < 6) {
-        const double rE = R.Sigma[t] - tot / (double)R.n3;
-        const double wE = (double)R.glob_beta * st[kWE + t] + R.glob_alphaE * rE;
-        st[kWE + t] = wE;
-        st[kE + t] += wE;
-    }
+    const int r = blockIdx.x, I = threadIdx.x;
+    if (I >= 6) return;
+    double E_I, wE_I;
+    advance_E(reps, r, st_last, kSeqState, sums_last, I, E_I, wE_I);
+    state[(int64_t)r * kStateDoubles + kE + I] = E_I;
+    state[(int64_t)r * kStateDoubles + kWE + I] = wE_I;
 }
 
 struct FinalArgs {
@@ -421,63 +446,63 @@ hipError_t launch_reuss(hmc_ctx_s* c)
     return hipGetLastError();
 }
 
-hipError_t launch_global_steps(hmc_ctx_s* c, int n_steps)
+hipError_t seq_begin(hmc_ctx_s* c)
 {
-    GlobArgs a;
-    a.spins = c->d.spins;
-    a.Ctab = c->d.Ctab;
-    a.w = c->d.w;
-    a.partials = c->d.partials;
-    a.state = c->d.state;
-    a.E_record = nullptr;
-    a.reps = c->d.reps;
-    a.node_rep = c->d.node_rep;
-    a.tile_rep = c->d.tile_rep;
-    a.plane = c->total_sites;
-    EArgs ea;
-    ea.state = c->d.state;
-    ea.partials = c->d.partials;
-    ea.reps = c->d.reps;
-    ea.tiled = 1;
-    for (int s = 0; s < n_steps; ++s) {
-        a.uin = c->d.u[c->cur_u];
-        a.uout = c->d.u[1 - c->cur_u];
-        int tok = prof_begin(c, kProfRefreshStep);
-        hipLaunchKernelGGL(k_global_step_tiled, dim3(c->tile_blocks), dim3(256), 0, c->stream, a);
-        prof_end(c, tok);
-        tok = prof_begin(c, kProfRefreshOther);
-        hipLaunchKernelGGL(k_global_E, dim3(c->n_rep), dim3(256), 0, c->stream, ea);
-        prof_end(c, tok);
-        c->cur_u = 1 - c->cur_u;
-    }
-    return hipGetLastError();
+    // the first step adds into buffer 0, which starts cleared; each step clears the next
+    const int tok = prof_begin(c, kProfRefreshOther);
+    // (buffers 0 and 1: 2 x kSumSlots 64-bit words per replica, 2 uint32 each)
+    const hipError_t e = launch_fill_u32((uint32_t*)c->d.sums, 0u, 4 * (int64_t)c->n_rep * kSumSlots, c->stream);
+    prof_end(c, tok);
+    return e;
 }
 
-// One explicit step from `uin` to `uout`, recording its input E into E_record (single-lattice
-// contexts; used by the adjoint's segment recomputation).
-hipError_t launch_global_step_ptrs(hmc_ctx_s* c, const float* uin, float* uout, double* E_record)
+hipError_t seq_step(hmc_ctx_s* c, int i, const float* uin, float* uout, double* E_record)
 {
+    const int64_t per = (int64_t)c->n_rep * kSumSlots;
     GlobArgs a;
     a.spins = c->d.spins;
     a.Ctab = c->d.Ctab;
     a.uin = uin;
     a.uout = uout;
     a.w = c->d.w;
-    a.partials = c->d.partials;
-    a.state = c->d.state;
+    a.sums_in = i > 0 ? c->d.sums + ((i - 1) % 3) * per : nullptr;
+    a.sums_out = c->d.sums + (i % 3) * per;
+    a.sums_clear = c->d.sums + ((i + 1) % 3) * per;
+    a.st_in = i > 0 ? c->d.seq_state + (int64_t)((i - 1) & 1) * c->n_rep * kSeqState : c->d.state + kE;
+    a.st_in_stride = i > 0 ? kSeqState : kStateDoubles;
+    a.st_out = c->d.seq_state + (int64_t)(i & 1) * c->n_rep * kSeqState;
     a.E_record = E_record;
     a.reps = c->d.reps;
-    a.node_rep = c->d.node_rep;
     a.tile_rep = c->d.tile_rep;
     a.plane = c->total_sites;
-    EArgs ea;
-    ea.state = c->d.state;
-    ea.partials = c->d.partials;
-    ea.reps = c->d.reps;
-    ea.tiled = 1;
+    const int tok = prof_begin(c, kProfRefreshStep);
     hipLaunchKernelGGL(k_global_step_tiled, dim3(c->tile_blocks), dim3(256), 0, c->stream, a);
-    hipLaunchKernelGGL(k_global_E, dim3(c->n_rep), dim3(256), 0, c->stream, ea);
+    prof_end(c, tok);
     return hipGetLastError();
+}
+
+hipError_t seq_end(hmc_ctx_s* c, int n)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t per = (int64_t)c->n_rep * kSumSlots;
+    const int tok = prof_begin(c, kProfRefreshOther);
+    hipLaunchKernelGGL(k_seq_fold, dim3(c->n_rep), dim3(64), 0, c->stream, c->d.state,
+                       c->d.seq_state + (int64_t)((n - 1) & 1) * c->n_rep * kSeqState,
+                       c->d.sums + ((n - 1) % 3) * per, c->d.reps);
+    prof_end(c, tok);
+    return hipGetLastError();
+}
+
+hipError_t launch_global_steps(hmc_ctx_s* c, int n_steps)
+{
+    if (n_steps <= 0) return hipSuccess;
+    hipError_t e = seq_begin(c);
+    for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
+        e = seq_step(c, s, c->d.u[c->cur_u], c->d.u[1 - c->cur_u], nullptr);
+        c->cur_u = 1 - c->cur_u;
+    }
+    if (e == hipSuccess) e = seq_end(c, n_steps);
+    return e;
 }
 
 hipError_t launch_global_final(hmc_ctx_s* c, bool write_sigma)

@@ -81,6 +81,17 @@ enum StateSlot {
     kStateDoubles = 16
 };
 
+// Stress sums of a sequence of explicit steps.  Each step adds its blocks' six sums, as
+// 64-bit fixed-point integers (2^-26 GPa per voxel; integer adds commute, so the totals do not
+// depend on the order the blocks finish in), into one of kSumCopies copies picked by block;
+// the next step's blocks fold them into E themselves.  Three rotating buffers: the one being
+// added to, the one being read, and the one being cleared for the step after.
+constexpr int kSumCopies = 8;
+constexpr int kSumSlots = kSumCopies * 8;      // per replica and buffer (8 int64 per copy)
+constexpr double kSumScale = 67108864.0;       // 2^26
+// (E, wE) of the step a sequence is at, per replica and parity: 16 doubles (E at 0, wE at 6).
+constexpr int kSeqState = 16;
+
 // Counters (uint32): list counts per colour, error flag.
 enum CounterSlot { kListCount = 0, kErrFlag = 8, kCounters = 16 };
 
@@ -101,6 +112,8 @@ struct DeviceState {
     uint8_t* accept = nullptr;       // max_list
     double* state = nullptr;         // n_rep x kStateDoubles
     double* partials = nullptr;      // total node blocks x 8
+    unsigned long long* sums = nullptr;  // 3 x n_rep x kSumSlots (explicit-step stress sums)
+    double* seq_state = nullptr;     // 2 x n_rep x kSeqState
     uint32_t* counters = nullptr;    // kCounters
     unsigned long long* stats = nullptr;  // kStats x kStatCopies
     uint64_t* thr = nullptr;         // n_rep x 64 integer Metropolis thresholds
@@ -182,6 +195,12 @@ hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec);
 hipError_t launch_apply_pass(hmc_ctx_s* c, int colour);
 hipError_t launch_reuss(hmc_ctx_s* c);
 hipError_t launch_global_steps(hmc_ctx_s* c, int n_steps);
+// A sequence of explicit steps from the context's state (E, wE): seq_begin, then seq_step for
+// i = 0, 1, ... (each from uin to uout; E_record, if set, receives the step's E), then
+// seq_end(n) with the number of steps taken, which leaves the context's state after them.
+hipError_t seq_begin(hmc_ctx_s* c);
+hipError_t seq_step(hmc_ctx_s* c, int i, const float* uin, float* uout, double* E_record);
+hipError_t seq_end(hmc_ctx_s* c, int n);
 hipError_t launch_global_final(hmc_ctx_s* c, bool write_sigma);
 hipError_t launch_zero_wE(hmc_ctx_s* c);
 hipError_t launch_unlike_bonds(hmc_ctx_s* c, int rep);
