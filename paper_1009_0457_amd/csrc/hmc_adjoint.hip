@@ -30,9 +30,13 @@
 namespace hmc {
 
 constexpr double kFixScale = 1099511627776.0;   // 2^40
+// Doubles per copy of the part of the adjoint state the adjoint steps advance (the slots
+// kEb .. kWEt below), kept per step like the forward sequence's (E, wE); the tau sums between
+// steps use the forward's fixed-point accumulators.
+constexpr int kAdjSeq = 32;
 
 struct AdjLayout {
-    size_t ckpt, seg_u, seg_E, ub0, ub1, wb0, wb1, G, dC, dS, adj, grad, total;
+    size_t ckpt, seg_u, seg_E, ub0, ub1, wb0, wb1, G, dC, dS, adj, asums, aseq, grad, total;
     int n_ck;          // checkpoints of segment starts
     size_t ck_bytes;   // bytes per checkpoint: u, w planes then 12 doubles
 };
@@ -63,6 +67,8 @@ static AdjLayout adj_layout(const hmc_ctx_s* c, int n_steps, int k)
     L.dC = take(Q * 3 * kTab * sizeof(float));
     L.dS = take(Q * 3 * kTab * sizeof(float));
     L.adj = take(64 * sizeof(double));
+    L.asums = take(3 * kSumSlots * sizeof(unsigned long long));
+    L.aseq = take(2 * kAdjSeq * sizeof(double));
     L.grad = take(Q * 3 * sizeof(unsigned long long));
     L.total = o;
     return L;
@@ -70,6 +76,38 @@ static AdjLayout adj_layout(const hmc_ctx_s* c, int n_steps, int k)
 
 // Slots of the adjoint's small state block.
 enum AdjSlot { kEb = 0, kWEb = 6, kB = 12, kSigb = 18, kWEt = 24, kE0 = 30, kAdjDoubles = 64 };
+
+// Component I of the adjoint state after one more adjoint step whose tau sums are in `sums`
+// (null: unchanged): E^ -= sum tau, wE^ = beta wE~, Sigma^ += b, wE~ = wE^ + E^, b = alphaE wE~.
+__device__ __forceinline__ void adj_advance(const double* in, const unsigned long long* sums, int I, double betaE,
+                                            double alphaE, double out[5])
+{
+    double Eb = in[kEb + I], wEb = in[kWEb + I], b = in[kB + I], Sb = in[kSigb + I], wt = in[kWEt + I];
+    if (sums) {
+        long long tot = 0;
+#pragma unroll
+        for (int c = 0; c < kSumCopies; ++c) tot += (long long)sums[c * 8 + I];
+        Eb -= (double)tot / kSumScale;
+        wEb = betaE * wt;
+        Sb += b;
+        wt = wEb + Eb;
+        b = alphaE * wt;
+    }
+    out[0] = Eb;
+    out[1] = wEb;
+    out[2] = b;
+    out[3] = Sb;
+    out[4] = wt;
+}
+
+__device__ __forceinline__ void adj_store(double* dst, int I, const double v[5])
+{
+    dst[kEb + I] = v[0];
+    dst[kWEb + I] = v[1];
+    dst[kB + I] = v[2];
+    dst[kSigb + I] = v[3];
+    dst[kWEt + I] = v[4];
+}
 
 // eta . (dC_q eps) for the three angles q of grain g
 __device__ __forceinline__ void angle_contractions(const float* __restrict__ dC, int g, const float eta[6],
@@ -151,11 +189,15 @@ struct AdjStepArgs {
     float* wb_out;
     const float* u_t;        // forward displacement of step t
     const double* E_t;       // forward macroscopic strain of step t (6)
-    const double* adj;       // b
+    const double* st_in;     // adjoint state the previous step started from (or the initial one)
+    double* st_out;          // this step's (written by block 0)
+    const unsigned long long* sums_in;   // the previous step's tau sums (null: first step)
+    unsigned long long* sums_out;        // this step's
+    unsigned long long* sums_clear;      // the next step's, cleared by block 0
     double* G;               // 3 planes
-    double* partials;
     const RepDev* reps;
     float alpha, beta;
+    double betaE, alphaE;
 };
 
 // tau = C_q eta and, where `owned`, gq_k = eta . (dC_{q,k} eps) for the three angles k,
@@ -191,7 +233,7 @@ __device__ __forceinline__ void adjoint_voxel(const float* Ctab, const float* dC
 // the nodal field a = alpha (w^ + u^) and the forward displacement u_t give each voxel its
 // adjoint strain eta and forward strain eps; tau = C eta is formed once per tile, and the
 // voxels the block owns also add their angle contractions to G and tau to the block's sums.
-__global__ __launch_bounds__(256) void k_adj_step(AdjStepArgs a)
+__global__ __launch_bounds__(256, 3) void k_adj_step(AdjStepArgs a)
 {
     constexpr int NX = kTileX + 2, NY = kTileY + 2, VX = kTileX + 1, VY = kTileY + 1;
     constexpr int NP = (NX * NY + 255) / 256, VP = (kStepVox + 255) / 256;
@@ -210,13 +252,20 @@ __global__ __launch_bounds__(256) void k_adj_step(AdjStepArgs a)
     const int by = b % nty, bz = b / nty;
     const int x0 = bx * kTileX, y0 = by * kTileY, z0 = bz * tz;
     const int z1 = (z0 + tz < K) ? z0 + tz : K;
+    // this step's adjoint state from the previous one and its tau sums (read after the
+    // prologue's first barrier); block 0 records it and clears the sums of the step after
+    __shared__ double sb[6];
+    if (threadIdx.x < 6) {
+        double v[5];
+        adj_advance(a.st_in, a.sums_in, threadIdx.x, a.betaE, a.alphaE, v);
+        sb[threadIdx.x] = v[2];
+        if (lb == 0) adj_store(a.st_out, threadIdx.x, v);
+    }
+    if (lb == 0 && threadIdx.x < kSumSlots) a.sums_clear[threadIdx.x] = 0ull;
     float b3[6], E[6];
     const double inv_n3 = 1.0 / (double)n3;
 #pragma unroll
-    for (int I = 0; I < 6; ++I) {
-        b3[I] = (float)(a.adj[kB + I] * inv_n3);
-        E[I] = (float)a.E_t[I];
-    }
+    for (int I = 0; I < 6; ++I) E[I] = (float)a.E_t[I];
     const float alpha = a.alpha, beta = a.beta;
     const int t = threadIdx.x, lx = t % kTileX, ly = t / kTileX;
     const int nx = x0 + lx, ny = y0 + ly;
@@ -310,6 +359,8 @@ __global__ __launch_bounds__(256) void k_adj_step(AdjStepArgs a)
     fetch_spins(z0 - 1);
     store_pair();
     __syncthreads();
+#pragma unroll
+    for (int I = 0; I < 6; ++I) b3[I] = (float)(sb[I] * inv_n3);
     float tprev[VP][6];
 #pragma unroll
     for (int k = 0; k < VP; ++k)
@@ -380,7 +431,20 @@ __global__ __launch_bounds__(256) void k_adj_step(AdjStepArgs a)
             }
         }
     }
-    block_sum_to<6>(a.partials, acc, lb);
+    const double tot = block_total<6>(acc);
+    if (threadIdx.x < 6)
+        atomicAdd(a.sums_out + (lb & (kSumCopies - 1)) * 8 + threadIdx.x, (unsigned long long)llrint(tot * kSumScale));
+}
+
+// After the last adjoint step: the adjoint state block.
+__global__ void k_adj_seq_fold(double* adj, const double* st_last, const unsigned long long* sums_last, double betaE,
+                               double alphaE)
+{
+    const int I = threadIdx.x;
+    if (I >= 6) return;
+    double v[5];
+    adj_advance(st_last, sums_last, I, betaE, alphaE, v);
+    adj_store(adj, I, v);
 }
 
 // Folds the per-block sums (fixed order).  mode 0 (start): E^ = sum sigma, wE^ = 0,
@@ -606,6 +670,8 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
     float* dC = (float*)(base + L.dC);
     float* dS = (float*)(base + L.dS);
     double* adj = (double*)(base + L.adj);
+    unsigned long long* asums = (unsigned long long*)(base + L.asums);
+    double* aseq = (double*)(base + L.aseq);
     unsigned long long* grad = (unsigned long long*)(base + L.grad);
     const int nb = adj_blocks(n3);
 
@@ -640,7 +706,9 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
                            R.glob_alphaE);
         ATRY(hipGetLastError(), "backward: start");
     }
-    int cur_b = 0;
+    int cur_b = 0, i_adj = 0;   // i_adj: adjoint steps taken
+    // the first adjoint step adds into tau-sum buffer 0 (2 uint32 per 64-bit word)
+    ATRY(launch_fill_u32((uint32_t*)asums, 0u, 2 * kSumSlots, c->stream), "backward: start");
     const int n_seg = (n + k - 1) / k;
     for (int j = n_seg - 1; j >= 0; --j) {
         const int t0 = j * k, t1 = (t0 + k < n) ? t0 + k : n;
@@ -670,21 +738,28 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
             a.wb_out = wb[1 - cur_b];
             a.u_t = seg_u + (size_t)(t - t0) * 3 * n3;
             a.E_t = seg_E + (size_t)(t - t0) * 8;
-            a.adj = adj;
+            a.st_in = i_adj > 0 ? aseq + ((i_adj - 1) & 1) * kAdjSeq : adj;
+            a.st_out = aseq + (i_adj & 1) * kAdjSeq;
+            a.sums_in = i_adj > 0 ? asums + ((i_adj - 1) % 3) * kSumSlots : nullptr;
+            a.sums_out = asums + (i_adj % 3) * kSumSlots;
+            a.sums_clear = asums + ((i_adj + 1) % 3) * kSumSlots;
             a.G = G;
-            a.partials = c->d.partials;
             a.reps = c->d.reps;
             a.alpha = R.glob_alpha;
             a.beta = R.glob_beta;
+            a.betaE = (double)R.glob_beta;
+            a.alphaE = R.glob_alphaE;
             const int tok = prof_begin(c, kProfRefreshStep);
             hipLaunchKernelGGL(k_adj_step, dim3(c->tile_blocks), dim3(256), 0, c->stream, a);
             prof_end(c, tok);
-            hipLaunchKernelGGL(k_adj_E, dim3(1), dim3(256), 0, c->stream, adj, c->d.partials, c->tile_blocks, 1,
-                               (double)R.glob_beta, R.glob_alphaE);
             ATRY(hipGetLastError(), "backward: step");
             cur_b = 1 - cur_b;
+            ++i_adj;
         }
     }
+    hipLaunchKernelGGL(k_adj_seq_fold, dim3(1), dim3(64), 0, c->stream, adj, aseq + ((i_adj - 1) & 1) * kAdjSeq,
+                       asums + ((i_adj - 1) % 3) * kSumSlots, (double)R.glob_beta, R.glob_alphaE);
+    ATRY(hipGetLastError(), "backward: step");
     // contractions and the start-strain terms
     {
         AdjGradArgs a;
