@@ -153,7 +153,8 @@ hmc_status hmc_get_spins(hmc_ctx ctx, int32_t* spins_dev);
 
 /* Applied macroscopic stress Sigma (Voigt, MPa, host array of 6): the average stress the
  * global solve holds (periodic lattice, Sec. 5).  All-zero load turns the elastic term off
- * (decisions then use exact integer thresholds). */
+ * (decisions then use exact integer thresholds).  HMC_ENUMERIC for non-finite components,
+ * HMC_EINVAL for any beyond 5e4 MPa (the range the solve's fixed-point stress sums hold). */
 hmc_status hmc_set_load(hmc_ctx ctx, const double sigma_MPa[6]);
 
 /* Global explicit relaxation (Sec. 5), n_steps steps (cold_start with n_steps < 0 uses
@@ -254,7 +255,7 @@ typedef struct {
     double kT;
     double lambda_el;       /* 0: elastic term off for this replica */
     double glob_alpha, glob_beta, glob_alphaE;
-    double sigma_MPa[6];    /* applied average stress (Voigt, MPa) */
+    double sigma_MPa[6];    /* applied average stress (Voigt, MPa; |each| <= 5e4) */
     uint64_t seed;          /* Philox key */
 } hmc_replica;
 

@@ -46,6 +46,17 @@ hmc_status check_common(const hmc_params* p)
     return HMC_OK;
 }
 
+// The explicit step's fixed-point stress sums (2^-26 GPa per voxel, 64-bit) hold the whole
+// lattice's sum for mean stresses up to 128 GPa at K = 1024; loads are held to 50 GPa, which
+// leaves room for the relaxation's overshoot.
+constexpr double kMaxLoadMPa = 5.0e4;
+bool load_in_range(const double s[6])
+{
+    for (int I = 0; I < 6; ++I)
+        if (!(std::fabs(s[I]) <= kMaxLoadMPa)) return false;
+    return true;
+}
+
 hmc_status check_replica(const hmc_params* p, const hmc_replica* r)
 {
     if (r->K < 2 || r->K > 1024 || (r->K & 1)) return HMC_ESHAPE;
@@ -56,6 +67,7 @@ hmc_status check_replica(const hmc_params* p, const hmc_replica* r)
     for (double v : vals)
         if (!std::isfinite(v)) return HMC_ENUMERIC;
     if (!(r->kT > 0)) return HMC_EINVAL;
+    if (!load_in_range(r->sigma_MPa)) return HMC_EINVAL;
     if (r->lambda_el != 0.0 && r->K < 2 * p->zone_h + 2) return HMC_ESHAPE;
     return HMC_OK;
 }
@@ -897,6 +909,7 @@ hmc_status hmc_set_load(hmc_ctx c, const double sigma_MPa[6])
     if (!sigma_MPa) return state_fail(c, HMC_EINVAL, "null load");
     for (int I = 0; I < 6; ++I)
         if (!std::isfinite(sigma_MPa[I])) return state_fail(c, HMC_ENUMERIC, "non-finite load");
+    if (!load_in_range(sigma_MPa)) return state_fail(c, HMC_EINVAL, "load component beyond 5e4 MPa");
     for (auto& R : c->reps) {
         bool nz = false;
         for (int I = 0; I < 6; ++I) {

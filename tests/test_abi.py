@@ -142,6 +142,20 @@ def test_shape_limits():
     assert st == H.HMC_ESHAPE
 
 
+def test_load_range():
+    """Loads beyond 5e4 MPa per component are refused: the explicit step's fixed-point stress
+    sums are sized for that range."""
+    L = _lib_or_skip()
+    p = H.hmc_default_params(16, 26, 2)
+    reps = (H.hmc_replica * 2)()
+    for i in range(2):
+        reps[i] = H.hmc_default_replica(p, 16, 8)
+    reps[1].sigma_MPa[2] = 4.9e4
+    assert L.hmc_batch_workspace_bytes(C.byref(p), 2, reps) > 0
+    reps[1].sigma_MPa[2] = -5.1e4
+    assert L.hmc_batch_workspace_bytes(C.byref(p), 2, reps) == 0
+
+
 def test_null_context_calls_are_rejected():
     L = _lib_or_skip()
     assert L.hmc_sweep(None, 1) == H.HMC_EINVAL

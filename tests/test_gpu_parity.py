@@ -462,6 +462,9 @@ def test_error_paths():
         lat.set_load([0, 0, float("inf"), 0, 0, 0])
     assert e.value.status == H.HMC_ENUMERIC
     with pytest.raises(H.HmcError) as e:
+        lat.set_load([0, 0, 6.0e4, 0, 0, 0])   # beyond the fixed-point stress sums' range
+    assert e.value.status == H.HMC_EINVAL
+    with pytest.raises(H.HmcError) as e:
         lat.texture_histogram([0, 0, 0])
     assert e.value.status == H.HMC_EINVAL
     with pytest.raises(H.HmcError) as e:
