@@ -204,7 +204,10 @@ __device__ __forceinline__ void block_sum2(uint32_t& a, uint32_t& b)
 // thousands of blocks on large lattices, so the block appends its elastic trials with one
 // atomic on the list counter and adds its statistics to one of the spread counter copies.
 static_assert(kPassSites == 4 * 256, "four sites per thread of a 256-thread block");
-template <int M>
+// SCREEN: the lower-bound screen's FP64 path is compiled in only where it is used, since it
+// more than doubles the kernel's registers (126 against 48 VGPRs: 4 against 8 wavefronts per
+// SIMD, which hide the chain of dependent reads of every site).
+template <int M, bool SCREEN>
 __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
 {
     constexpr int SPT = kPassSites / 256;
@@ -305,7 +308,7 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
             bool accepted = false, screened = false;
             if (!elastic) {
                 accepted = (uint64_t)r1 < a.thr[(int64_t)r * 64 + gb + M];
-            } else if (a.screen && r1 != 0u) {
+            } else if (SCREEN && r1 != 0u) {
                 // reject without a solve when even the lowest possible zone energy loses:
                 // dE >= J gb + lambda dPi_0 > max(0, E*(r1)) + margin
                 float sp[6];
@@ -479,8 +482,13 @@ hipError_t launch_potts_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
     a.screen = (c->p.zone_screen != 0 && c->d.sigma != nullptr) ? 1 : 0;
     const dim3 grid((unsigned)c->pass_blocks), block(256);
     const int tok = prof_begin(c, kProfPotts);
-    if (c->p.neighbors == 26) hipLaunchKernelGGL(k_potts_pass<26>, grid, block, 0, c->stream, a);
-    else hipLaunchKernelGGL(k_potts_pass<6>, grid, block, 0, c->stream, a);
+    if (c->p.neighbors == 26) {
+        if (a.screen) hipLaunchKernelGGL((k_potts_pass<26, true>), grid, block, 0, c->stream, a);
+        else hipLaunchKernelGGL((k_potts_pass<26, false>), grid, block, 0, c->stream, a);
+    } else {
+        if (a.screen) hipLaunchKernelGGL((k_potts_pass<6, true>), grid, block, 0, c->stream, a);
+        else hipLaunchKernelGGL((k_potts_pass<6, false>), grid, block, 0, c->stream, a);
+    }
     prof_end(c, tok);
     return hipGetLastError();
 }
