@@ -447,11 +447,10 @@ __global__ void k_adj_seq_fold(double* adj, const double* st_last, const unsigne
     adj_store(adj, I, v);
 }
 
-// Folds the per-block sums (fixed order).  mode 0 (start): E^ = sum sigma, wE^ = 0,
-// Sigma^ = 0.  mode 1 (after a step): E^ -= sum tau, wE^ = beta wE~, Sigma^ += b.  Both then
-// prepare the next step: wE~ = wE^ + E^, b = alphaE wE~.
-__global__ __launch_bounds__(256) void k_adj_E(double* adj, const double* partials, int nblocks, int mode,
-                                               double betaE, double alphaE)
+// Starts the adjoint state from the per-block sums of the final stresses (fixed order):
+// E^ = sum sigma, wE^ = 0, Sigma^ = 0, then wE~ = wE^ + E^ and b = alphaE wE~ for the first
+// adjoint step (later steps advance the state themselves, adj_advance).
+__global__ __launch_bounds__(256) void k_adj_E(double* adj, const double* partials, int nblocks, double alphaE)
 {
     const int t = threadIdx.x;
     double s[6] = {0, 0, 0, 0, 0, 0};
@@ -460,18 +459,11 @@ __global__ __launch_bounds__(256) void k_adj_E(double* adj, const double* partia
         for (int I = 0; I < 6; ++I) s[I] += partials[(int64_t)bk * 8 + I];
     const double tot = block_total<6>(s);
     if (t < 6) {
-        if (mode == 0) {
-            adj[kEb + t] = tot;
-            adj[kWEb + t] = 0.0;
-            adj[kSigb + t] = 0.0;
-        } else {
-            adj[kEb + t] -= tot;
-            adj[kWEb + t] = betaE * adj[kWEt + t];
-            adj[kSigb + t] += adj[kB + t];
-        }
-        const double wt = adj[kWEb + t] + adj[kEb + t];
-        adj[kWEt + t] = wt;
-        adj[kB + t] = alphaE * wt;
+        adj[kEb + t] = tot;
+        adj[kWEb + t] = 0.0;
+        adj[kSigb + t] = 0.0;
+        adj[kWEt + t] = tot;
+        adj[kB + t] = alphaE * tot;
     }
 }
 
@@ -702,8 +694,7 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
     {
         AdjInitArgs a{c->d.spins, c->d.Ctab, dC, c->d.u[0], ub[0], wb[0], G, c->d.partials, c->d.state, R.K, n3};
         hipLaunchKernelGGL(k_adj_init, dim3(nb), dim3(256), 0, c->stream, a);
-        hipLaunchKernelGGL(k_adj_E, dim3(1), dim3(256), 0, c->stream, adj, c->d.partials, nb, 0, (double)R.glob_beta,
-                           R.glob_alphaE);
+        hipLaunchKernelGGL(k_adj_E, dim3(1), dim3(256), 0, c->stream, adj, c->d.partials, nb, R.glob_alphaE);
         ATRY(hipGetLastError(), "backward: start");
     }
     int cur_b = 0, i_adj = 0;   // i_adj: adjoint steps taken
