@@ -134,3 +134,29 @@ def test_autograd_function_matches_direct_adjoint():
     assert np.array_equal(eu.grad.numpy(), ge)
     assert np.array_equal(st.grad.numpy(), gs)
     lat.close()
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    """The explicit steps carry (E, wE) from one step to the next inside a sequence and through
+    the context's state between sequences (one per checkpoint segment, and per recomputed
+    segment); both routes use the same arithmetic, so the gradient is bit-identical for any
+    checkpoint interval, including one step per segment."""
+    K, n = 12, 40
+    m = voronoi_polycrystal(K, 10, 8)
+    sig = np.array([90.0, -30.0, 60.0, 20.0, -10.0, 40.0])
+    out = []
+    for every in (1, 7, 40):
+        p = H.hmc_default_params(K, 26, 1)
+        lat = H.Lattice(p, m.Q)
+        lat.set_orientations(m.euler)
+        lat.set_spins(m.spins)
+        lat.set_load(sig)
+        U = lat.elastic_forward(n, every)
+        ge, gs = lat.elastic_backward(1.0)
+        out.append((U, ge, gs))
+        lat.close()
+    for U, ge, gs in out[1:]:
+        assert U == out[0][0]
+        assert np.array_equal(ge, out[0][1])
+        assert np.array_equal(gs, out[0][2])
+

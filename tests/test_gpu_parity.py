@@ -211,6 +211,27 @@ def test_refresh_grain_paths(kind):
     lat2.close()
 
 
+@pytest.mark.parametrize("steps", [1, 2, 3, 4])
+def test_refresh_short_sequences(steps):
+    """Refreshes of 1-4 steps: the strain state passes between steps through three rotating
+    sum buffers and two state copies, and to the context after the last step; every length
+    up to a full turn of both matches the oracle."""
+    K = 16
+    micro = voronoi_polycrystal(K, 9, 4)
+    sig = np.array([50.0, 80.0, -60.0, 0.0, 25.0, -15.0])
+    p, lat = make_lattice(K, 26, 1, micro)
+    lat.set_load(sig)
+    lat.stress_refresh(steps, True)
+    s_gpu = lat.get_stress().cpu().numpy().astype(np.float64)
+    E_gpu = lat.macro_strain()
+    lat.close()
+    Ct, St, _ = O.tables(micro.euler, p.C11, p.C12, p.C44)
+    _, E, s_ora, _ = O.global_solve(K, micro.spins, Ct, St, sig * 1e-3, steps, True, p.glob_alpha, p.glob_beta,
+                                    p.glob_alphaE)
+    assert np.linalg.norm(s_gpu - s_ora) / np.linalg.norm(s_ora) <= 1e-5
+    assert np.linalg.norm(E_gpu - E) <= 1e-6 * np.linalg.norm(E)
+
+
 def test_refresh_single_crystal_closed_form():
     K = 12
     micro = voronoi_polycrystal(K, 1, 2)
