@@ -36,7 +36,7 @@ constexpr double kFixScale = 1099511627776.0;   // 2^40
 constexpr int kAdjSeq = 32;
 
 struct AdjLayout {
-    size_t ckpt, seg_u, seg_E, ub0, ub1, wb0, wb1, G, dC, dS, adj, asums, aseq, grad, total;
+    size_t ckpt, seg_u[2], seg_E[2], ub0, ub1, wb0, wb1, G, dC, dS, adj, asums, aseq, grad, total;
     int n_ck;          // checkpoints of segment starts
     size_t ck_bytes;   // bytes per checkpoint: u, w planes then 12 doubles
 };
@@ -57,8 +57,12 @@ static AdjLayout adj_layout(const hmc_ctx_s* c, int n_steps, int k)
         return at;
     };
     L.ckpt = take((size_t)L.n_ck * L.ck_bytes);
-    L.seg_u = take((size_t)(k + 1) * 3 * n3 * sizeof(float));
-    L.seg_E = take((size_t)(k + 1) * 8 * sizeof(double));
+    // two segment buffers: one segment's adjoint steps read one while the next segment is
+    // recomputed into the other
+    for (int b = 0; b < 2; ++b) {
+        L.seg_u[b] = take((size_t)(k + 1) * 3 * n3 * sizeof(float));
+        L.seg_E[b] = take((size_t)(k + 1) * 8 * sizeof(double));
+    }
     L.ub0 = take(3 * n3 * sizeof(float));
     L.ub1 = take(3 * n3 * sizeof(float));
     L.wb0 = take(3 * n3 * sizeof(float));
@@ -565,17 +569,16 @@ hmc_status save_ckpt(hmc_ctx c, char* base, const AdjLayout& L, int j)
     return HMC_OK;
 }
 
-// restores checkpoint j with u into `u_dst`
-hmc_status load_ckpt(hmc_ctx c, char* base, const AdjLayout& L, int j, float* u_dst)
+// restores checkpoint j with u into `u_dst`, on stream s
+hmc_status load_ckpt(hmc_ctx c, char* base, const AdjLayout& L, int j, float* u_dst, hipStream_t s)
 {
     const size_t n3 = (size_t)c->reps[0].n3;
     char* ck = base + L.ckpt + (size_t)j * L.ck_bytes;
-    ATRY(hipMemcpyAsync(u_dst, ck, 3 * n3 * sizeof(float), hipMemcpyDeviceToDevice, c->stream), "restore");
-    ATRY(hipMemcpyAsync(c->d.w, ck + 3 * n3 * sizeof(float), 3 * n3 * sizeof(float), hipMemcpyDeviceToDevice,
-                        c->stream),
+    ATRY(hipMemcpyAsync(u_dst, ck, 3 * n3 * sizeof(float), hipMemcpyDeviceToDevice, s), "restore");
+    ATRY(hipMemcpyAsync(c->d.w, ck + 3 * n3 * sizeof(float), 3 * n3 * sizeof(float), hipMemcpyDeviceToDevice, s),
          "restore");
     ATRY(hipMemcpyAsync(c->d.state + kE, ck + al256(6 * n3 * sizeof(float)), 12 * sizeof(double),
-                        hipMemcpyDeviceToDevice, c->stream),
+                        hipMemcpyDeviceToDevice, s),
          "restore");
     return HMC_OK;
 }
@@ -654,8 +657,8 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
     const int64_t n3 = R.n3;
     const int Q = R.Q;
     char* base = (char*)ws;
-    float* seg_u = (float*)(base + L.seg_u);
-    double* seg_E = (double*)(base + L.seg_E);
+    float* seg_u[2] = {(float*)(base + L.seg_u[0]), (float*)(base + L.seg_u[1])};
+    double* seg_E[2] = {(double*)(base + L.seg_E[0]), (double*)(base + L.seg_E[1])};
     float* ub[2] = {(float*)(base + L.ub0), (float*)(base + L.ub1)};
     float* wb[2] = {(float*)(base + L.wb0), (float*)(base + L.wb1)};
     double* G = (double*)(base + L.G);
@@ -688,7 +691,7 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
     }
 
     // final state -> initial adjoint
-    st = load_ckpt(c, base, L, L.n_ck - 1, c->d.u[0]);
+    st = load_ckpt(c, base, L, L.n_ck - 1, c->d.u[0], c->stream);
     if (st != HMC_OK) return st;
     c->cur_u = 0;
     {
@@ -701,22 +704,56 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
     // the first adjoint step adds into tau-sum buffer 0 (2 uint32 per 64-bit word)
     ATRY(launch_fill_u32((uint32_t*)asums, 0u, 2 * kSumSlots, c->stream), "backward: start");
     const int n_seg = (n + k - 1) / k;
-    for (int j = n_seg - 1; j >= 0; --j) {
-        const int t0 = j * k, t1 = (t0 + k < n) ? t0 + k : n;
-        // recompute the segment's forward states u_t, E_t for t in [t0, t1)
-        st = load_ckpt(c, base, L, j, seg_u);
-        if (st != HMC_OK) return st;
-        if (t1 - 1 > t0) {
-            ATRY(seq_begin(c), "backward: recompute");
-            for (int t = t0; t + 1 < t1; ++t) {
-                float* ut = seg_u + (size_t)(t - t0) * 3 * n3;
-                ATRY(seq_step(c, t - t0, ut, ut + 3 * n3, seg_E + (size_t)(t - t0) * 8), "backward: recompute");   // records E_t
-            }
-            ATRY(seq_end(c, t1 - 1 - t0), "backward: recompute");
+    // Segment j's forward states are recomputed from its checkpoint into buffer j & 1.  With
+    // the auxiliary stream the recomputation of segment j-1 runs while the context's stream
+    // takes segment j's adjoint steps (both are latency-bound at this size); events order
+    // them: ev[0..1] "buffer b free", ev[2..3] "buffer b recomputed", ev[4] start.  With
+    // profiling on, everything stays on the context's stream.
+    const bool overlap = !c->profiling;
+    hipStream_t rs = c->stream;
+    if (overlap) {
+        if (!c->aux_stream) {
+            ATRY(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking), "backward: stream");
+            for (auto& e : c->aux_ev) ATRY(hipEventCreateWithFlags(&e, hipEventDisableTiming), "backward: events");
         }
-        ATRY(hipMemcpyAsync(seg_E + (size_t)(t1 - 1 - t0) * 8, c->d.state + kE, 6 * sizeof(double),
-                            hipMemcpyDeviceToDevice, c->stream),
+        rs = c->aux_stream;
+        // the recomputation overwrites the context's w and (E, wE), which the start above read
+        ATRY(hipEventRecord(c->aux_ev[4], c->stream), "backward: events");
+        ATRY(hipStreamWaitEvent(rs, c->aux_ev[4], 0), "backward: events");
+        ATRY(hipEventRecord(c->aux_ev[0], c->stream), "backward: events");
+        ATRY(hipEventRecord(c->aux_ev[1], c->stream), "backward: events");
+    }
+    auto recompute = [&](int j) -> hmc_status {
+        const int b = j & 1;
+        const int t0 = j * k, t1 = (t0 + k < n) ? t0 + k : n;
+        if (overlap) ATRY(hipStreamWaitEvent(rs, c->aux_ev[b], 0), "backward: events");
+        hmc_status s2 = load_ckpt(c, base, L, j, seg_u[b], rs);
+        if (s2 != HMC_OK) return s2;
+        if (t1 - 1 > t0) {
+            ATRY(seq_begin(c, rs), "backward: recompute");
+            for (int t = t0; t + 1 < t1; ++t) {
+                float* ut = seg_u[b] + (size_t)(t - t0) * 3 * n3;
+                ATRY(seq_step(c, rs, t - t0, ut, ut + 3 * n3, seg_E[b] + (size_t)(t - t0) * 8),
+                     "backward: recompute");   // records E_t
+            }
+            ATRY(seq_end(c, rs, t1 - 1 - t0), "backward: recompute");
+        }
+        ATRY(hipMemcpyAsync(seg_E[b] + (size_t)(t1 - 1 - t0) * 8, c->d.state + kE, 6 * sizeof(double),
+                            hipMemcpyDeviceToDevice, rs),
              "backward: recompute");
+        if (overlap) ATRY(hipEventRecord(c->aux_ev[2 + b], rs), "backward: events");
+        return HMC_OK;
+    };
+    st = recompute(n_seg - 1);
+    if (st != HMC_OK) return st;
+    for (int j = n_seg - 1; j >= 0; --j) {
+        const int b = j & 1;
+        const int t0 = j * k, t1 = (t0 + k < n) ? t0 + k : n;
+        if (j > 0) {
+            st = recompute(j - 1);
+            if (st != HMC_OK) return st;
+        }
+        if (overlap) ATRY(hipStreamWaitEvent(c->stream, c->aux_ev[2 + b], 0), "backward: events");
         // adjoint steps t1-1 .. t0
         for (int t = t1 - 1; t >= t0; --t) {
             AdjStepArgs a;
@@ -727,8 +764,8 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
             a.ub_out = ub[1 - cur_b];
             a.wb_in = wb[cur_b];
             a.wb_out = wb[1 - cur_b];
-            a.u_t = seg_u + (size_t)(t - t0) * 3 * n3;
-            a.E_t = seg_E + (size_t)(t - t0) * 8;
+            a.u_t = seg_u[b] + (size_t)(t - t0) * 3 * n3;
+            a.E_t = seg_E[b] + (size_t)(t - t0) * 8;
             a.st_in = i_adj > 0 ? aseq + ((i_adj - 1) & 1) * kAdjSeq : adj;
             a.st_out = aseq + (i_adj & 1) * kAdjSeq;
             a.sums_in = i_adj > 0 ? asums + ((i_adj - 1) % 3) * kSumSlots : nullptr;
@@ -747,6 +784,7 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
             cur_b = 1 - cur_b;
             ++i_adj;
         }
+        if (overlap) ATRY(hipEventRecord(c->aux_ev[b], c->stream), "backward: events");
     }
     hipLaunchKernelGGL(k_adj_seq_fold, dim3(1), dim3(64), 0, c->stream, adj, aseq + ((i_adj - 1) & 1) * kAdjSeq,
                        asums + ((i_adj - 1) % 3) * kSumSlots, (double)R.glob_beta, R.glob_alphaE);
@@ -783,7 +821,7 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
         grad_sigma_MPa[I] = dU * (ad[kSigb + I] + s / (double)n3) * 1e-3;
     }
     // leave the context at the final forward state
-    st = load_ckpt(c, base, L, L.n_ck - 1, c->d.u[0]);
+    st = load_ckpt(c, base, L, L.n_ck - 1, c->d.u[0], c->stream);
     if (st != HMC_OK) return st;
     c->cur_u = 0;
     ATRY(launch_global_final(c, true), "backward: restore");

@@ -843,6 +843,9 @@ void hmc_destroy(hmc_ctx c)
         (void)hipEventDestroy(pp.b);
     }
     for (auto e : c->prof_free) (void)hipEventDestroy(e);
+    for (auto e : c->aux_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->aux_stream) (void)hipStreamDestroy(c->aux_stream);
     delete c;
 }
 

@@ -446,17 +446,17 @@ hipError_t launch_reuss(hmc_ctx_s* c)
     return hipGetLastError();
 }
 
-hipError_t seq_begin(hmc_ctx_s* c)
+hipError_t seq_begin(hmc_ctx_s* c, hipStream_t s)
 {
     // the first step adds into buffer 0, which starts cleared; each step clears the next
-    const int tok = prof_begin(c, kProfRefreshOther);
+    const int tok = s == c->stream ? prof_begin(c, kProfRefreshOther) : -1;
     // (buffers 0 and 1: 2 x kSumSlots 64-bit words per replica, 2 uint32 each)
-    const hipError_t e = launch_fill_u32((uint32_t*)c->d.sums, 0u, 4 * (int64_t)c->n_rep * kSumSlots, c->stream);
+    const hipError_t e = launch_fill_u32((uint32_t*)c->d.sums, 0u, 4 * (int64_t)c->n_rep * kSumSlots, s);
     prof_end(c, tok);
     return e;
 }
 
-hipError_t seq_step(hmc_ctx_s* c, int i, const float* uin, float* uout, double* E_record)
+hipError_t seq_step(hmc_ctx_s* c, hipStream_t s, int i, const float* uin, float* uout, double* E_record)
 {
     const int64_t per = (int64_t)c->n_rep * kSumSlots;
     GlobArgs a;
@@ -475,18 +475,18 @@ hipError_t seq_step(hmc_ctx_s* c, int i, const float* uin, float* uout, double* 
     a.reps = c->d.reps;
     a.tile_rep = c->d.tile_rep;
     a.plane = c->total_sites;
-    const int tok = prof_begin(c, kProfRefreshStep);
-    hipLaunchKernelGGL(k_global_step_tiled, dim3(c->tile_blocks), dim3(256), 0, c->stream, a);
+    const int tok = s == c->stream ? prof_begin(c, kProfRefreshStep) : -1;
+    hipLaunchKernelGGL(k_global_step_tiled, dim3(c->tile_blocks), dim3(256), 0, s, a);
     prof_end(c, tok);
     return hipGetLastError();
 }
 
-hipError_t seq_end(hmc_ctx_s* c, int n)
+hipError_t seq_end(hmc_ctx_s* c, hipStream_t s, int n)
 {
     if (n <= 0) return hipSuccess;
     const int64_t per = (int64_t)c->n_rep * kSumSlots;
-    const int tok = prof_begin(c, kProfRefreshOther);
-    hipLaunchKernelGGL(k_seq_fold, dim3(c->n_rep), dim3(64), 0, c->stream, c->d.state,
+    const int tok = s == c->stream ? prof_begin(c, kProfRefreshOther) : -1;
+    hipLaunchKernelGGL(k_seq_fold, dim3(c->n_rep), dim3(64), 0, s, c->d.state,
                        c->d.seq_state + (int64_t)((n - 1) & 1) * c->n_rep * kSeqState,
                        c->d.sums + ((n - 1) % 3) * per, c->d.reps);
     prof_end(c, tok);
@@ -496,12 +496,12 @@ hipError_t seq_end(hmc_ctx_s* c, int n)
 hipError_t launch_global_steps(hmc_ctx_s* c, int n_steps)
 {
     if (n_steps <= 0) return hipSuccess;
-    hipError_t e = seq_begin(c);
+    hipError_t e = seq_begin(c, c->stream);
     for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
-        e = seq_step(c, s, c->d.u[c->cur_u], c->d.u[1 - c->cur_u], nullptr);
+        e = seq_step(c, c->stream, s, c->d.u[c->cur_u], c->d.u[1 - c->cur_u], nullptr);
         c->cur_u = 1 - c->cur_u;
     }
-    if (e == hipSuccess) e = seq_end(c, n_steps);
+    if (e == hipSuccess) e = seq_end(c, c->stream, n_steps);
     return e;
 }
 

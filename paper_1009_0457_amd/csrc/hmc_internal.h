@@ -165,6 +165,10 @@ struct hmc_ctx_s {
     int graph_u[2] = {-1, -1};
     bool use_graphs = false;
     int adj_steps = 0, adj_every = 0;   // last hmc_elastic_forward
+    // second stream (default priority) on which the adjoint's backward pass recomputes forward
+    // segments while the context's stream runs adjoint steps; created on first use
+    hipStream_t aux_stream = nullptr;
+    hipEvent_t aux_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     hmc::DeviceState d;
     std::string err;
 
@@ -195,12 +199,13 @@ hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec);
 hipError_t launch_apply_pass(hmc_ctx_s* c, int colour);
 hipError_t launch_reuss(hmc_ctx_s* c);
 hipError_t launch_global_steps(hmc_ctx_s* c, int n_steps);
-// A sequence of explicit steps from the context's state (E, wE): seq_begin, then seq_step for
-// i = 0, 1, ... (each from uin to uout; E_record, if set, receives the step's E), then
-// seq_end(n) with the number of steps taken, which leaves the context's state after them.
-hipError_t seq_begin(hmc_ctx_s* c);
-hipError_t seq_step(hmc_ctx_s* c, int i, const float* uin, float* uout, double* E_record);
-hipError_t seq_end(hmc_ctx_s* c, int n);
+// A sequence of explicit steps from the context's state (E, wE), enqueued on stream s:
+// seq_begin, then seq_step for i = 0, 1, ... (each from uin to uout; E_record, if set,
+// receives the step's E), then seq_end(n) with the number of steps taken, which leaves the
+// context's state after them.  Profiling events are taken only on the context's stream.
+hipError_t seq_begin(hmc_ctx_s* c, hipStream_t s);
+hipError_t seq_step(hmc_ctx_s* c, hipStream_t s, int i, const float* uin, float* uout, double* E_record);
+hipError_t seq_end(hmc_ctx_s* c, hipStream_t s, int n);
 hipError_t launch_global_final(hmc_ctx_s* c, bool write_sigma);
 hipError_t launch_zero_wE(hmc_ctx_s* c);
 hipError_t launch_unlike_bonds(hmc_ctx_s* c, int rep);
