@@ -294,7 +294,10 @@ hmc_status hmc_batch_texture_histogram(hmc_ctx ctx, int32_t r, const double axis
  * dU * dU/dtheta (host, Q x 3, per radian) and dU * dU/dSigma (host, 6, per MPa).  The
  * backward call leaves the context at the forward's final state.  The adjoint workspace must
  * not change between the two calls.  HMC_ESTATE on batches, without a forward, or with the
- * elastic term disabled. */
+ * elastic term disabled.  The backward call recomputes segments on a second stream of the
+ * library's own (default priority, created on first use, released by hmc_destroy) while the
+ * context's stream runs adjoint steps; events order the two, and the call returns only after
+ * both are done (it returns host results), so the caller sees ordinary stream order. */
 size_t hmc_adjoint_workspace_bytes(hmc_ctx ctx, int32_t n_steps, int32_t ckpt_every);
 hmc_status hmc_elastic_forward(hmc_ctx ctx, int32_t n_steps, int32_t ckpt_every, void* dev_adjoint_ws,
                                size_t adjoint_ws_bytes, double* U_host);
