@@ -91,8 +91,7 @@ hmc_replica replica_of_params(const hmc_params* p, int32_t Q)
 // ------------------------------------------------------------------------------------
 struct Layout {
     size_t spins, Ctab, Stab, sigma, u0, u1, w, list, accept, state, partials, sums, seq_state, counters, stats,
-        thr, tex, hist,
-        bonds, reps, pass_rep, node_rep, tile_rep, sweep, total;
+        thr, tex, hist, bonds, reps, pass_rep, node_rep, tile_rep, sweep, total;
     int64_t sites, grains, max_list;
     int pass_blocks, node_blocks, tile_blocks, tile_z;
     bool elastic;
