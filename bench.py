@@ -292,6 +292,30 @@ def bench_adjoint(a):
         t2 = time.perf_counter()
         tf.append(t1 - t0)
         tb.append(t2 - t1)
+    # The plain method on the same GPU: central differences of the forward for the probe
+    # grains' angles (h = 1e-2 rad: the FP32 forward's rounding makes smaller steps noisy).
+    h = 1e-2
+    fd_abs = []
+    n_fwd = 0
+    t_fd0 = time.perf_counter()
+    for g in probe:
+        for k in range(3):
+            u_pm = []
+            for sgn in (1.0, -1.0):
+                e = micro.euler.copy()
+                e[g, k] += sgn * h
+                lat.set_orientations(e)
+                u_pm.append(lat.elastic_forward(2000, 50))
+                n_fwd += 1
+            fd_abs.append(abs((u_pm[0] - u_pm[1]) / (2 * h) - ge[g, k]))
+    t_fd = (time.perf_counter() - t_fd0) / n_fwd
+    lat.set_orientations(micro.euler)
+    n_params = 3 * micro.Q + 6
+    plain = {"method": "central differences of the GPU forward", "h_rad": h, "angles_checked": len(fd_abs),
+             "max_abs_diff_over_max_grad": float(max(fd_abs) / np.abs(ge).max()),
+             "seconds_per_forward": t_fd, "full_gradient_s": 2 * n_params * t_fd,
+             "adjoint_speedup": 2 * n_params * t_fd * (1.0 / (float(np.median(tf)) + float(np.median(tb))))}
+    log(f"[bench] plain FD: {plain}")
     lat.set_profiling(True)
     lat.kernel_times()
     lat.elastic_forward(2000, 50)
@@ -314,6 +338,7 @@ def bench_adjoint(a):
         "forward_step_GBs": step_bytes * fs["launches"] / (fs["total_ms"] * 1e-3) / 1e9 if fs["launches"] else None,
         "adjoint_step_ms": kb["refresh_step"]["total_ms"] / max(1, kb["refresh_step"]["launches"]),
         "forward_step_ms": fs["total_ms"] / max(1, fs["launches"]),
+        "plain_method": plain,
     }
     print(json.dumps(out), flush=True)
 
