@@ -76,7 +76,7 @@ typedef struct {
                                Decisions are those of the full solve; the trial's record then
                                carries flag 8 and no dPi.  0: solve every real flip. */
     int32_t refresh_tile_z; /* node layers per work-group of the explicit global step and of its
-                               adjoint: 1, 2, 4, 8 or 16, or 0 to pick the deepest tile that
+                               adjoint: 1, 2, 4, 8, 16 or 32, or 0 to pick the deepest tile that
                                still gives at least 1024 work-groups (2 rather than 1; 1 if none
                                does): shallower tiles recompute more halo voxels but fill the GPU
                                on small lattices.  Other values: HMC_EINVAL. */

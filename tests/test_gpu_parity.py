@@ -121,7 +121,7 @@ def test_zero_load_energy_and_resume():
 # --------------------------------------------------------------------------------------
 @pytest.mark.parametrize("K,ng,steps,tile_z", [(8, 5, 300, 0), (16, 8, 500, 0), (20, 30, 200, 0), (20, 30, 200, 2),
                                                (20, 30, 200, 8), (18, 20, 150, 4), (18, 20, 150, 8),
-                                               (34, 40, 120, 16)])
+                                               (34, 40, 120, 16), (34, 40, 120, 32)])
 def test_refresh_matches_oracle(K, ng, steps, tile_z):
     """Every tile depth of the explicit step, including tiles cut short by the lattice edge."""
     say(f"[refresh] K={K} grains={ng} steps={steps} tile_z={tile_z}")
