@@ -97,6 +97,7 @@ def lib():
         L.ora_trials.restype = C.c_int64
         L.ora_sweeps.argtypes = [C.POINTER(Params), _i32p, _f64p, _f64p, _f64p, _f64p, _f64p,
                                  C.c_uint32, C.c_int]
+        L.ora_gs_sweeps.argtypes = [C.POINTER(Params), _i32p, C.c_uint32, C.c_int]
         _lib = L
     return _lib
 
@@ -325,6 +326,13 @@ def trials(P: Params, snap, Ct, St, sigma, sweep, sites):
     lib().ora_trials(C.byref(P), np.ascontiguousarray(snap, np.int32), np.ascontiguousarray(Ct).ravel(),
                      np.ascontiguousarray(St).ravel(), sp, sweep, sites, sites.shape[0], _vp(recs))
     return recs
+
+
+def gs_sweeps(P: Params, q, s0, n):
+    """n Gauss-Seidel sweeps (Sec. 6's comparison scheme) in place on q, zero load only."""
+    if P.elastic:
+        raise ValueError("Gauss-Seidel sweeps are for zero load")
+    lib().ora_gs_sweeps(C.byref(P), q, s0, n)
 
 
 def sweeps(P: Params, q, Ct, St, u, E, sigma, s0, n):

@@ -13,7 +13,8 @@
  *     (metrop_1).  H_gb = J * (number of unlike neighbour bonds), each bond once; for a
  *     trial flip of site i only the bonds of i change.
  *   - Red/black (here: 2- or 8-colour) checkerboard with updates deferred to the end of
- *     each half step: Sec. 6.
+ *     each half step: Sec. 6.  The Gauss-Seidel scheme Sec. 6 compares it with (every site
+ *     in turn, each accepted change written at once) is here too, at zero load.
  *   - Local elastic energy change from a zone Omega_1 under constant boundary traction,
  *     "stored energy minus boundary work": Sec. 3, Eq. (H_1, second form) and Fig. 1;
  *     the point-zone limit is Eq. (eladriv).
@@ -775,5 +776,21 @@ void ora_sweeps(const ora_params* P, int32_t* q, const double* Ctab, const doubl
             ora_global(P->K, q, Ctab, Stab, P->Sigma, P->n_warm, 0, P->glob_alpha, P->glob_beta,
                        P->glob_alphaE, u, E, sigma, NULL);
         for (int c = 0; c < C; ++c) ora_pass(P, q, Ctab, Stab, P->elastic ? sigma : NULL, s, c, NULL);
+    }
+}
+
+/* Gauss-Seidel sweeps at zero load (Sec. 6, the scheme the checkerboard is compared with):
+ * every site in turn, x fastest, tried against the current state and updated at once.  The
+ * trial of site i in sweep s uses the same draws as in the colour passes.                */
+void ora_gs_sweeps(const ora_params* P, int32_t* q, uint32_t s0, int n)
+{
+    int64_t n3 = (int64_t)P->K * P->K * P->K;
+    for (int a = 0; a < n; ++a) {
+        uint32_t s = s0 + (uint32_t)a;
+        for (int64_t i = 0; i < n3; ++i) {
+            ora_record rec;
+            ora_trial(P, q, NULL, NULL, NULL, i, s, &rec);
+            if (rec.flags & 2) q[i] = rec.q_new;
+        }
     }
 }

@@ -186,3 +186,76 @@ def test_philox_chain_matches_boltzmann(M):
     chi2 = ((hist - expct) ** 2 / expct).sum()
     p = stats.chi2.sf(chi2, df=255)
     assert p > 1e-3, (chi2, p, thin)
+
+
+# --------------------------------------------------------------------------------------
+# Gauss-Seidel sweeps (Sec. 6's comparison scheme): the same pins as the checkerboard
+# --------------------------------------------------------------------------------------
+def _gs_sweep_matrix(M, kT, J=1.0):
+    """One sweep visiting sites 0..7 in turn, each a single-site Metropolis step on the
+    current state: the product of eight one-site transition matrices."""
+    K = 2
+    S = _states(8)
+    idx = {tuple(s): a for a, s in enumerate(S)}
+    P = np.eye(256)
+    for i in range(8):
+        Pi = np.zeros((256, 256))
+        for a, s in enumerate(S):
+            dE = J * O.gb_count(K, M, s, i, int(1 - s[i]))
+            pf = 1.0 if dE <= 0 else np.exp(-dE / kT)
+            t = s.copy()
+            t[i] = 1 - t[i]
+            Pi[a, idx[tuple(t)]] += pf
+            Pi[a, a] += 1 - pf
+        P = P @ Pi
+    return S, P
+
+
+@pytest.mark.parametrize("M", [6, 26])
+def test_gs_sweep_stationary_by_enumeration(M):
+    kT = 1.3
+    S, P = _gs_sweep_matrix(M, kT)
+    H = np.array([unlike_slots_numpy(2, M, s) / 2 for s in S])
+    pi = np.exp(-(H - H.min()) / kT)
+    pi /= pi.sum()
+    assert np.abs(pi @ P - pi).max() < 1e-12
+    # with 2 colours the sequential sweep is a different chain from the checkerboard's; at
+    # K=2 each of the 8 colours holds one site, visited in site order, so there they agree
+    _, Prb = _sweep_matrix(M, kT)
+    if M == 6:
+        assert np.abs(P - Prb).max() > 1e-3
+    else:
+        assert np.abs(P - Prb).max() < 1e-12
+
+
+@pytest.mark.parametrize("M", [6, 26])
+def test_gs_chain_matches_gs_matrix(M):
+    """The oracle's Gauss-Seidel sweep (Philox draws) started from one fixed state: the
+    empirical distribution after one sweep matches that row of the enumerated one-sweep
+    matrix (chi-square over many seeds), so order and immediate writes are as stated."""
+    from scipy import stats
+    kT = 2.0
+    S, P = _gs_sweep_matrix(M, kT)
+    start = np.array([0, 1, 1, 0, 1, 0, 0, 1], np.int32)
+    a0 = int(start @ (1 << np.arange(8)))
+    row = P[a0]
+    n = 20000
+    hist = np.zeros(256, np.int64)
+    for seed in range(n):
+        prm = O.make_params(2, M, 2, proposal=1, elastic=False, J=1.0, kT=kT, seed=seed)
+        q = start.copy()
+        O.gs_sweeps(prm, q, 0, 1)
+        hist[int(q @ (1 << np.arange(8)))] += 1
+    keep = row * n >= 5
+    expct = row[keep] * n
+    obs = hist[keep]
+    chi2 = ((obs - expct) ** 2 / expct).sum() + (hist[~keep].sum() - row[~keep].sum() * n) ** 2 / max(row[~keep].sum() * n, 1e-9)
+    p = stats.chi2.sf(chi2, df=int(keep.sum()))
+    assert p > 1e-3, (chi2, p)
+    if M != 6:
+        return
+    # the 2-colour checkerboard's one-sweep row is rejected by the same statistic
+    _, Prb = _sweep_matrix(M, kT)
+    rb = Prb[a0]
+    chi2_rb = ((obs - rb[keep] * n) ** 2 / np.maximum(rb[keep] * n, 1e-9)).sum()
+    assert stats.chi2.sf(chi2_rb, df=int(keep.sum())) < 1e-6
