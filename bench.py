@@ -11,7 +11,8 @@ Prints ONE JSON line on stdout (progress goes to stderr).  A step is one sweep.
 
 Other workloads (--workload): batched (the 64-replica ensemble against the same replicas run
 alone), adjoint (64^3 forward + backward of the stored energy), potts and refresh (the colour
-pass and the explicit step on lattices beyond the caches, default 512^3).
+pass and the explicit step on lattices beyond the caches, default 512^3), growth (the ten
+60^3 zero-load grain-growth runs of Sec. 6 as one fused batch).
 """
 from __future__ import annotations
 
@@ -77,12 +78,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--K", type=int, default=0, help="override the lattice edge (diagnostics only)")
-    ap.add_argument("--workload", choices=["large", "batched", "adjoint", "potts", "refresh"], default="large",
+    ap.add_argument("--workload", choices=["large", "batched", "adjoint", "potts", "refresh", "growth"], default="large",
                     help="large: the headline 128^3 workload; batched: the 64-replica ensemble in fused "
                          "graph-captured launches vs the same replicas run one by one; adjoint: 64^3 "
                          "forward 2000 steps + backward with checkpoints every 50; potts: zero-load colour "
                          "passes on a lattice larger than the caches (default 512^3); refresh: explicit global "
-                         "steps on such a lattice")
+                         "steps on such a lattice; growth: ten 60^3 zero-load grain-growth runs as one batch")
+    ap.add_argument("--neighbors", type=int, choices=[6, 26], default=None,
+                    help="growth: 6 neighbours / 2 colours or 26 / 8 (default 26)")
     ap.add_argument("--replicas", type=int, default=64)
     ap.add_argument("--zone-variant", type=int, default=0, help="zone-solve kernel (0 = automatic)")
     ap.add_argument("--tile-z", type=int, default=0, help="node layers per block of the explicit step (0 = automatic)")
@@ -409,6 +412,122 @@ def bench_potts(a):
     print(json.dumps(out), flush=True)
 
 
+def bench_growth(a):
+    """Sec. 6's grain-growth study: ten independent 60^3 runs, 99 orientations, random spins,
+    kT/J = 1.0, zero load, as one fused batch with graph-replayed sweeps; against the same
+    runs one after another as single lattices, and the oracle's sweeps on one run."""
+    import numpy as np
+    import torch
+
+    from paper_1009_0457_amd import hmc as H
+    from paper_1009_0457_amd.synth import haar_euler, random_spins
+
+    K, Q, runs = 60, 99, 10
+    M = 26 if a.neighbors is None else a.neighbors
+    colours = 8 if M == 26 else 2
+    common = H.hmc_default_params(K, M, 1)
+    common.proposal = 0 if a.proposal == "neighbor" else 1
+    reps, init = [], []
+    for r in range(runs):
+        rep = H.hmc_default_replica(common, K, Q)
+        rep.kT, rep.lambda_el, rep.seed = 1.0, 0.0, 9000 + r
+        reps.append(rep)
+        init.append((haar_euler(np.random.default_rng(8000 + r), Q), random_spins(K, Q, 7000 + r)))
+    log(f"[bench] growth: {runs} x {K}^3, Q={Q}, {M} neighbours, kT/J=1.0, zero load")
+
+    def fresh_batch():
+        b = H.Batch(common, reps)
+        for r, (eu, q0) in enumerate(init):
+            b.set_replica(r, eu, q0)
+        return b
+
+    # kernel duration of the colour pass (profiling bypasses the graphs), from the initial state
+    b = fresh_batch()
+    for _ in range(a.warmup):
+        b.sweep(1)
+    b.synchronize()
+    b.kernel_times()
+    b.set_profiling(True)
+    b.sweep(a.steps)
+    b.synchronize()
+    b.set_profiling(False)
+    kt = b.kernel_times()["potts"]
+    b.close()
+    # timed: graph-replayed sweeps of the whole batch
+    b = fresh_batch()
+    b.set_graphs(True)
+    for _ in range(a.warmup):
+        b.sweep(1)
+    b.synchronize()
+    b.reset_stats()
+    t0 = time.perf_counter()
+    b.sweep(a.steps)
+    b.synchronize()
+    t_batch = time.perf_counter() - t0
+    st = b.stats()
+    b.close()
+    # the same runs one after another
+    t_plain = 0.0
+    for r, (eu, q0) in enumerate(init):
+        p = H.hmc_params.from_buffer_copy(common)
+        p.kT, p.lambda_el, p.seed = 1.0, 0.0, reps[r].seed
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            lat = H.Lattice(p, Q, stream=s)
+            lat.set_orientations(eu)
+            lat.set_spins(q0)
+            lat.set_graphs(True)
+            for _ in range(a.warmup):
+                lat.sweep(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lat.sweep(a.steps)
+            s.synchronize()
+            t_plain += time.perf_counter() - t0
+            lat.close()
+    sites = runs * K ** 3
+    trials = sites * a.steps
+    ms = kt["total_ms"] / max(1, kt["launches"])
+    bytes_pass = (2 * colours + 2) * sites / colours
+    ach = bytes_pass / (ms * 1e-3) / 1e9
+    log(f"[bench] batch {t_batch:.3f} s, runs alone {t_plain:.3f} s, colour pass {ms * 1e3:.1f} us")
+    out = {"metric": "site-trials/sec at zero load (grain growth, fused batch of runs)",
+           "value": trials / t_batch, "unit": "site-trials/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": t_batch / a.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "int16", "data": "synthetic",
+           "config": {"workload": f"growth: {runs} runs of {K}^3, {Q} orientations, random spins, {M} neighbours / "
+                                  f"{colours} colours, kT/J 1.0, zero load, proposal {a.proposal}", "sites": sites},
+           "roofline": {"kernel": "colour pass", "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+                        "avg_launch_ms": round(ms, 4),
+                        "note": f"(2C+2) bytes of spins per site-trial over all {runs} runs; "
+                                f"{2 * sites / 2 ** 20:.1f} MiB of spins, cache-resident"},
+           "runs_alone": {"value": trials / t_plain, "ms_per_step": t_plain / a.steps * 1e3},
+           "batched_over_alone": t_plain / t_batch,
+           "real_flip_fraction": st["real_flips"] / max(1, st["site_trials"]),
+           "acceptance": st["accepted"] / max(1, st["real_flips"])}
+    if not a.no_cpu_baseline:
+        import oracle as O
+
+        eu, q = init[0]
+        q = q.copy()
+        prm = O.make_params(K, M, Q, proposal=common.proposal, elastic=False, J=common.J, kT=1.0,
+                            seed=reps[0].seed)
+        d = np.zeros(1)
+        Ct = np.zeros(36 * Q)
+        n, t_cpu, s0 = 0, 0.0, 0
+        while t_cpu < 10.0 and n < 400:
+            t0 = time.perf_counter()
+            O.sweeps(prm, q, Ct, Ct, d, np.zeros(6), d, s0, 1)
+            t_cpu += time.perf_counter() - t0
+            s0 += 1
+            n += 1
+        out["cpu_baseline"] = {"value": n * K ** 3 / t_cpu, "unit": "site-trials/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the oracle's checkerboard sweeps 0..{n - 1} of run 0 ({t_cpu:.1f} s); "
+                                         f"serial C, -O2"}
+    print(json.dumps(out), flush=True)
+
+
 def bench_refresh(a):
     """Explicit global steps (Sec. 5 relaxation) on a lattice whose 54 B/site working set
     exceeds the 256 MB Infinity Cache."""
@@ -477,6 +596,8 @@ def main():
         return bench_potts(a)
     if a.workload == "refresh":
         return bench_refresh(a)
+    if a.workload == "growth":
+        return bench_growth(a)
     import numpy as np
     import torch
 
