@@ -1,0 +1,105 @@
+"""Texture measures of Sec. 7 for runs whose orientations are rotations about one axis.
+
+Host-side post-processing of spin fields read back from the library (no lattice work).
+With orientations phi = 0, 1, ..., 90 degrees about z and the load along x, cubic symmetry
+makes E(phi) = E(90 - phi): 0 and 90 degrees are the softest orientations along x, 45 the
+stiffest (Sec. 7, Fig. 2).  A texture is described by the signed deviation of each
+orientation from the nearest soft one, in [-45, 45] degrees.
+
+* ``gaussian_density``: the orientation density of Eq. (text_evl), a Gaussian of variance
+  parameter g(t) on [-45, 45] normalised by the error function;
+* ``fit_g``: g of one texture snapshot by least squares of the measured orientation fractions
+  against the density at each orientation's deviation (normalised over the orientations
+  present, the discrete form of the Erf normalisation);
+* ``fit_variance_law``: tau and beta of g(t) = beta sigma^2 exp(-t / tau), the solution of
+  Eq. (varn_eqn), by least squares on log g;
+* ``young_x`` / ``young_phi``: the Gaussian fit of x = E / C11 of Eq. (young_gau) and its
+  inverse, Eq. (inv_young), which maps orientation densities to Young's-modulus densities.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = ["signed_deviation", "orientation_fractions", "gaussian_density", "fit_g", "fit_variance_law",
+           "young_x", "young_phi", "soft_fraction", "mean_abs_deviation"]
+
+
+def signed_deviation(phi_deg):
+    """Deviation from the nearest soft orientation (0 or 90 degrees), in [-45, 45]."""
+    phi = np.asarray(phi_deg, float)
+    return np.where(phi <= 45.0, phi, phi - 90.0)
+
+
+def orientation_fractions(spins, Q):
+    """Volume fraction of each of the Q orientations (one count per site)."""
+    c = np.bincount(np.asarray(spins).ravel(), minlength=Q).astype(float)
+    return c / c.sum()
+
+
+def gaussian_density(phi_deg, g):
+    """Eq. (text_evl): exp(-phi^2 / 2g^2) / (g sqrt(2 pi) Erf(45 / (sqrt(2) g)))."""
+    phi = np.asarray(phi_deg, float)
+    return np.exp(-phi ** 2 / (2.0 * g * g)) / (g * math.sqrt(2.0 * math.pi) * math.erf(45.0 / (math.sqrt(2.0) * g)))
+
+
+def _model_fractions(dev, g):
+    f = gaussian_density(dev, g)
+    return f / f.sum()
+
+
+def fit_g(phi_deg, fractions, g_max=1.0e4):
+    """Least-squares g of Eq. (text_evl) for one snapshot; returns g_max for a texture that
+    is flat (or leans towards the stiff orientations) within the data."""
+    from scipy.optimize import minimize_scalar
+
+    dev = signed_deviation(phi_deg)
+    F = np.asarray(fractions, float)
+    F = F / F.sum()
+
+    def cost(lg):
+        return float(((F - _model_fractions(dev, math.exp(lg))) ** 2).sum())
+
+    lo, hi = math.log(0.5), math.log(g_max)
+    grid = np.linspace(lo, hi, 200)
+    k = int(np.argmin([cost(x) for x in grid]))
+    a, b = grid[max(k - 1, 0)], grid[min(k + 1, grid.size - 1)]
+    if a == b:
+        return math.exp(a)
+    r = minimize_scalar(cost, bounds=(a, b), method="bounded", options={"xatol": 1e-10})
+    return math.exp(r.x)
+
+
+def fit_variance_law(t, g, sigma_MPa):
+    """tau and beta of g(t) = beta sigma^2 exp(-t/tau) (Eq. varn_eqn's solution) by least
+    squares of log g on t.  tau is in the units of t; tau = inf when g does not fall."""
+    t = np.asarray(t, float)
+    lg = np.log(np.asarray(g, float))
+    slope, icpt = np.polyfit(t, lg, 1)
+    tau = -1.0 / slope if slope < -1e-12 else math.inf
+    return tau, math.exp(icpt) / sigma_MPa ** 2
+
+
+def young_x(phi_deg, a=0.388, b=16.40, c=0.541):
+    """Eq. (young_gau): x = E / C11 = a exp(-(phi - 45)^2 / 2b^2) + c (Sec. 7's constants)."""
+    phi = np.asarray(phi_deg, float)
+    return a * np.exp(-(phi - 45.0) ** 2 / (2.0 * b * b)) + c
+
+
+def young_phi(x, a=0.388, b=16.40, c=0.541):
+    """Eq. (inv_young): the orientation in [0, 45] degrees with modulus ratio x."""
+    x = np.asarray(x, float)
+    return 45.0 - np.sqrt(-2.0 * b * b * np.log((x - c) / a))
+
+
+def soft_fraction(phi_deg, fractions, within_deg=10.0):
+    """Volume fraction within within_deg of a soft orientation."""
+    return float(np.asarray(fractions)[np.abs(signed_deviation(phi_deg)) <= within_deg].sum())
+
+
+def mean_abs_deviation(phi_deg, fractions):
+    """Volume-weighted mean |deviation| from the nearest soft orientation (22.75 degrees for
+    a flat texture over 0..90 in 1-degree steps)."""
+    F = np.asarray(fractions, float)
+    return float((np.abs(signed_deviation(phi_deg)) * F).sum() / F.sum())

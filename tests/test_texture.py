@@ -1,0 +1,69 @@
+"""Pins of the Sec. 7 texture measures: normalisation of Eq. (text_evl), recovery of g and of
+(tau, beta) from exact model data, the Young's-modulus fit of Eq. (young_gau) against the
+paper's printed endpoints and its inverse Eq. (inv_young)."""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+
+from paper_1009_0457_amd import texture as T
+
+PHI = np.arange(91.0)
+
+
+@pytest.mark.parametrize("g", [3.0, 10.0, 25.0, 45.0, 300.0])
+def test_density_normalised_on_pm45(g):
+    v, _ = quad(lambda p: float(T.gaussian_density(p, g)), -45, 45, points=[0.0])
+    assert abs(v - 1.0) < 1e-10
+
+
+def test_deviation_mapping():
+    assert list(T.signed_deviation([0, 1, 45, 46, 89, 90])) == [0, 1, 45, -44, -1, 0]
+    flat = np.full(91, 1 / 91)
+    assert abs(T.mean_abs_deviation(PHI, flat) - 2 * sum(range(46)) / 91 + 45 / 91) < 1e-12
+    assert abs(T.soft_fraction(PHI, flat, 10) - 22 / 91) < 1e-12
+
+
+@pytest.mark.parametrize("g", [4.0, 10.0, 20.0, 40.0])
+def test_fit_g_recovers_model(g):
+    dev = T.signed_deviation(PHI)
+    F = T.gaussian_density(dev, g)
+    F /= F.sum()
+    assert abs(T.fit_g(PHI, F) / g - 1) < 1e-6
+
+
+def test_fit_g_flat_and_inverted():
+    assert T.fit_g(PHI, np.full(91, 1.0)) > 1e3
+    dev = np.abs(T.signed_deviation(PHI))
+    assert T.fit_g(PHI, 1.0 + dev / 45) > 1e3          # leaning to the stiff orientations
+
+
+def test_fit_g_noisy_many_sites():
+    rng = np.random.default_rng(3)
+    dev = T.signed_deviation(PHI)
+    p = T.gaussian_density(dev, 15.0)
+    p /= p.sum()
+    F = rng.multinomial(10 ** 7, p) / 1e7
+    assert abs(T.fit_g(PHI, F) / 15.0 - 1) < 0.01
+
+
+def test_variance_law_recovers_tau_beta(paper):
+    # the paper's constants: tau = 500 min = 50 MC steps of 10 min, beta = 0.05 deg/MPa^2
+    tau_steps = paper["tau_min"] / paper["minutes_per_mc_step"]
+    t = np.arange(0, 76, 5.0)
+    g = paper["beta_deg_per_MPa2"] * paper["load_MPa"] ** 2 * np.exp(-t / tau_steps)
+    tau, beta = T.fit_variance_law(t, g, paper["load_MPa"])
+    assert abs(tau - tau_steps) < 1e-9 and abs(beta - paper["beta_deg_per_MPa2"]) < 1e-12
+    assert abs(g[0] - 45.0) < 1e-12
+    tau, _ = T.fit_variance_law(t, np.full(t.size, 7.0), 30.0)
+    assert tau == math.inf
+
+
+def test_young_fit_endpoints_and_inverse(paper):
+    # Sec. 7 prints the fit's range 0.55 < x < 0.929 (the values at 0 and 45 degrees)
+    kw = dict(a=paper["fit_a"], b=paper["fit_b_deg"], c=paper["fit_c"])
+    assert abs(T.young_x(0.0, **kw) - paper["x_low"]) < 5e-4
+    assert abs(T.young_x(45.0, **kw) - paper["x_high"]) < 5e-4
+    phi = np.linspace(0.0, 44.9, 50)
+    assert np.abs(T.young_phi(T.young_x(phi)) - phi).max() < 1e-9
