@@ -34,6 +34,8 @@ __all__ = [
     "batched_configs",
     "adjoint_config",
     "random_spins",
+    "z_rotation_euler",
+    "texture_run_inputs",
 ]
 
 
@@ -109,6 +111,21 @@ def random_spins(K: int, Q: int, seed: int) -> np.ndarray:
     """Independent uniform spins in [0, Q): a maximally disordered test lattice."""
     rng = np.random.default_rng(seed)
     return rng.integers(0, Q, size=K ** 3, dtype=np.int64).astype(np.int32)
+
+
+def z_rotation_euler(n: int = 91, step_deg: float = 1.0) -> np.ndarray:
+    """Bunge angles of n rotations about z by 0, step, 2 step, ... degrees (Sec. 7's single
+    Euler angle study: the other two angles zero)."""
+    e = np.zeros((n, 3))
+    e[:, 0] = np.radians(step_deg * np.arange(n))
+    return e
+
+
+def texture_run_inputs(K: int = 100, runs: int = 10, Q: int = 91, seed: int = 300):
+    """Sec. 7's texture runs: every site an independent uniform choice among Q rotations
+    about z (0..90 degrees); one (euler, spins) pair per run, run r drawn with seed + r."""
+    e = z_rotation_euler(Q, 90.0 / (Q - 1))
+    return [(e, random_spins(K, Q, seed + r)) for r in range(runs)]
 
 
 @dataclass

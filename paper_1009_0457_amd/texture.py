@@ -103,3 +103,58 @@ def mean_abs_deviation(phi_deg, fractions):
     a flat texture over 0..90 in 1-degree steps)."""
     F = np.asarray(fractions, float)
     return float((np.abs(signed_deviation(phi_deg)) * F).sum() / F.sum())
+
+
+def texture_run(K=100, runs=10, *, Q=91, coarsen_steps=100, kT=2.6, load_MPa=30.0, substeps=75,
+                refresh_steps=200, neighbors=26, zone_h=2, zone_steps=200, lambda_scale=1.0, screen=True,
+                record_every=5, C=(250.8, 150.0, 123.5), seed=300, philox_seed=400, device="cuda:0"):
+    """Sec. 7's texture experiment as one fused batch of ``runs`` replicas on the library.
+
+    Every site starts as an independent random choice among Q rotations about z; the lattice
+    coarsens for ``coarsen_steps`` sweeps without load; then, for sub-load i = 1..substeps,
+    the uniaxial load i/substeps * load_MPa along x is set, the stress field is relaxed to its
+    quasi-static state (a cold start of cold_steps the first time, then warm refreshes of
+    refresh_steps) and one sweep follows.  ``lambda_scale`` multiplies the elastic-to-MC
+    energy scale of every replica; 0 runs the same schedule without any load (the control).
+
+    Returns a dict: t (sweeps since the end of coarsening, every record_every), fractions
+    (len(t), runs, Q) volume fractions per orientation, and the library's counters."""
+    from . import hmc as H
+    from .synth import texture_run_inputs
+
+    common = H.hmc_default_params(K, neighbors, zone_h)
+    common.zone_steps = zone_steps
+    common.refresh_steps = refresh_steps
+    common.refresh_every = 1 << 30          # refreshes are explicit, once per sub-load
+    common.zone_screen = 1 if screen else 0
+    common.C11, common.C12, common.C44 = C
+    reps = []
+    for r in range(runs):
+        rep = H.hmc_default_replica(common, K, Q)
+        rep.kT = kT
+        rep.lambda_el *= lambda_scale
+        rep.seed = philox_seed + r
+        reps.append(rep)
+    b = H.Batch(common, reps, device=device)
+    try:
+        for r, (eu, q0) in enumerate(texture_run_inputs(K, runs, Q, seed)):
+            b.set_replica(r, eu, q0)
+        b.sweep(coarsen_steps)
+
+        def snapshot():
+            return np.stack([orientation_fractions(b.get_spins(r).cpu().numpy(), Q) for r in range(runs)])
+
+        ts, fr = [0], [snapshot()]
+        for i in range(1, substeps + 1):
+            if lambda_scale != 0.0:
+                b.set_load([load_MPa * i / substeps, 0.0, 0.0, 0.0, 0.0, 0.0])
+                b.stress_refresh(-1, i == 1)
+            b.sweep(1)
+            if i % record_every == 0 or i == substeps:
+                ts.append(i)
+                fr.append(snapshot())
+        b.synchronize()
+        st = b.stats()
+    finally:
+        b.close()
+    return {"t": np.array(ts), "fractions": np.array(fr), "stats": st}
