@@ -12,7 +12,8 @@ Prints ONE JSON line on stdout (progress goes to stderr).  A step is one sweep.
 Other workloads (--workload): batched (the 64-replica ensemble against the same replicas run
 alone), adjoint (64^3 forward + backward of the stored energy), potts and refresh (the colour
 pass and the explicit step on lattices beyond the caches, default 512^3), growth (the ten
-60^3 zero-load grain-growth runs of Sec. 6 as one fused batch).
+60^3 zero-load grain-growth runs of Sec. 6 as one fused batch), texture (Sec. 7's ten 100^3
+runs: coarsening, then 75 sub-loads to 30 MPa, each a quasi-static refresh and one sweep).
 """
 from __future__ import annotations
 
@@ -78,12 +79,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--K", type=int, default=0, help="override the lattice edge (diagnostics only)")
-    ap.add_argument("--workload", choices=["large", "batched", "adjoint", "potts", "refresh", "growth"], default="large",
+    ap.add_argument("--workload", choices=["large", "batched", "adjoint", "potts", "refresh", "growth", "texture"], default="large",
                     help="large: the headline 128^3 workload; batched: the 64-replica ensemble in fused "
                          "graph-captured launches vs the same replicas run one by one; adjoint: 64^3 "
                          "forward 2000 steps + backward with checkpoints every 50; potts: zero-load colour "
                          "passes on a lattice larger than the caches (default 512^3); refresh: explicit global "
-                         "steps on such a lattice; growth: ten 60^3 zero-load grain-growth runs as one batch")
+                         "steps on such a lattice; growth: ten 60^3 zero-load grain-growth runs as one batch; "
+                         "texture: the ten 100^3 runs of the loaded texture experiment as one batch")
     ap.add_argument("--neighbors", type=int, choices=[6, 26], default=None,
                     help="growth: 6 neighbours / 2 colours or 26 / 8 (default 26)")
     ap.add_argument("--replicas", type=int, default=64)
@@ -528,6 +530,81 @@ def bench_growth(a):
     print(json.dumps(out), flush=True)
 
 
+def bench_texture(a):
+    """Sec. 7's experiment: ten 100^3 runs of 91 rotations about z as one batch; coarsening
+    (untimed), then the timed loaded phase of 75 sub-loads to 30 MPa along x, each a warm
+    200-step refresh (2000-step cold start at the first) and one sweep with the decision-exact
+    zone screen.  A step is one sub-load."""
+    import numpy as np
+
+    from paper_1009_0457_amd import texture as T
+
+    K, runs, substeps = 100, 10, 75
+    log(f"[bench] texture: {runs} x {K}^3, 91 orientations about z, 30 MPa in {substeps} sub-loads")
+    out_run = T.texture_run(K, runs, substeps=substeps, record_every=substeps, profile=True)
+    wall = out_run["wall_s"]
+    kt = out_run["kernel_times"]
+    st = out_run["stats"]
+    trials = runs * K ** 3 * substeps
+    ks = kt["refresh_step"]
+    ms = ks["total_ms"] / max(1, ks["launches"])
+    node_steps = runs * K ** 3
+    ach = 50.0 * node_steps / (ms * 1e-3) / 1e9
+    PHI = np.arange(91.0)
+    F0, F1 = out_run["fractions"][0].mean(0), out_run["fractions"][-1].mean(0)
+    log(f"[bench] loaded phase {wall:.2f} s; explicit step {ms * 1e3:.1f} us x {ks['launches']}")
+    out = {"metric": "site-trials/sec of the loaded texture run (sub-load refresh + sweep, zone solves screened)",
+           "value": trials / wall, "unit": "site-trials/s", "n_gpus": 1, "steps": substeps, "warmup": 0,
+           "ms_per_step": wall / substeps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"texture: {runs} runs of {K}^3, 91 rotations about z, coarsened 100 sweeps at "
+                                  f"kT/J 2.6, 30 MPa xx in {substeps} sub-loads (refresh 200 steps, cold 2000, then "
+                                  f"one sweep), 26 neighbours, 5^3 zone x 200, screen on", "sites": runs * K ** 3},
+           "roofline": {"kernel": "explicit step", "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
+                        "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+                        "avg_launch_ms": round(ms, 4),
+                        "note": "50 B per node-step (the explicit step's algorithmic bytes) over all runs"},
+           "kernel_ms": {k: round(v["total_ms"], 2) for k, v in kt.items()},
+           "zone_solve_fraction": st["zone_solves"] / trials,
+           "texture": {"soft10_before": T.soft_fraction(PHI, F0), "soft10_after": T.soft_fraction(PHI, F1),
+                       "mean_abs_dev_before": T.mean_abs_deviation(PHI, F0),
+                       "mean_abs_dev_after": T.mean_abs_deviation(PHI, F1)}}
+    if not a.no_cpu_baseline:
+        import oracle as O
+        from paper_1009_0457_amd.synth import texture_run_inputs
+
+        eu, q = texture_run_inputs(K, 1)[0]
+        Ct, St, _ = O.tables(eu, 250.8, 150.0, 123.5)
+        from paper_1009_0457_amd import hmc as H
+
+        p = H.hmc_default_params(K, 26, 2)
+        t0 = time.perf_counter()
+        u, E, sig, _ = O.global_solve(K, q, Ct, St, np.array([30.0, 0, 0, 0, 0, 0]) * 1e-3, 1, True, p.glob_alpha,
+                                      p.glob_beta, p.glob_alphaE)
+        t_step = time.perf_counter() - t0
+        prm = O.make_params(K, 26, 91, proposal=0, h=2, nr=200, elastic=True, J=1.0, kT=2.6,
+                            lambda_el=p.lambda_el, zone_alpha=p.zone_alpha, zone_beta=p.zone_beta,
+                            Sigma=(0.03, 0, 0, 0, 0, 0), seed=400)
+        g = np.arange(K)
+        z, y, x = np.meshgrid(g, g, g, indexing="ij")
+        sites = np.nonzero((((x | y | z) & 1) == 0).ravel())[0]
+        np.random.default_rng(5).shuffle(sites)
+        done, t_tr, batch = 0, 0.0, 64
+        while t_tr < a.cpu_seconds and done < sites.size:
+            pick = sites[done:done + batch]
+            t0 = time.perf_counter()
+            O.trials(prm, q, Ct, St, sig, 0, pick)
+            t_tr += time.perf_counter() - t0
+            done += pick.size
+            batch = min(4096, batch * 2)
+        t_sub = 200 * t_step + K ** 3 * t_tr / done
+        out["cpu_baseline"] = {"value": K ** 3 / t_sub, "unit": "site-trials/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{done} random site-trials of colour pass 0 on run 0's random start "
+                                         f"({t_tr:.1f} s) + 1 explicit step at {K}^3 ({t_step:.1f} s), combined as "
+                                         f"K^3 trials + 200 steps per sub-load; serial FP64 C, -O2"}
+    print(json.dumps(out), flush=True)
+
+
 def bench_refresh(a):
     """Explicit global steps (Sec. 5 relaxation) on a lattice whose 54 B/site working set
     exceeds the 256 MB Infinity Cache."""
@@ -598,6 +675,8 @@ def main():
         return bench_refresh(a)
     if a.workload == "growth":
         return bench_growth(a)
+    if a.workload == "texture":
+        return bench_texture(a)
     import numpy as np
     import torch
 

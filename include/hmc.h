@@ -136,7 +136,9 @@ hmc_status hmc_create(const hmc_params* p, int32_t Q, void* dev_workspace, size_
 
 void hmc_destroy(hmc_ctx ctx);
 
-/* Message of the last failed call on ctx (empty if none); valid until the next call. */
+/* Message of the last failed call on ctx (empty if none); valid until the next call.  With
+ * ctx NULL: the message of this thread's last hmc_create / hmc_batch_create (empty if it
+ * succeeded), which has no context to hold it. */
 const char* hmc_last_error(hmc_ctx ctx);
 
 /* Per-grain orientations: host array of Q Bunge triples (phi1, Phi, phi2) in radians.

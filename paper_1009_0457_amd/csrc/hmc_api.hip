@@ -374,9 +374,12 @@ hmc_status refresh(hmc_ctx c, int n_steps, bool cold)
 
 hmc_status run_pass(hmc_ctx c, int colour, hmc_trial_record* rec)
 {
-    HMC_TRY(c, launch_fill_u32(c->d.counters + kListCount + colour, 0u, 1, c->stream), "pass: reset list");
+    // Only trials that need a zone solve enter the colour's trial list; with the elastic term
+    // off for every replica the list stays empty and its count is neither read nor written.
+    const bool el = elastic_on(c);
+    if (el) HMC_TRY(c, launch_fill_u32(c->d.counters + kListCount + colour, 0u, 1, c->stream), "pass: reset list");
     HMC_TRY(c, launch_potts_pass(c, colour, rec), "pass: potts");
-    if (elastic_on(c)) {
+    if (el) {
         HMC_TRY(c, launch_zone_pass(c, colour, rec), "pass: zone solves");
         HMC_TRY(c, launch_apply_pass(c, colour), "pass: apply");
     }
@@ -437,22 +440,35 @@ hmc_status graph_sweep(hmc_ctx c, bool with_refresh)
     return HMC_OK;
 }
 
+// Message of this thread's last failed context creation (there is no context to hold it).
+thread_local std::string t_create_err;
+
+hmc_status create_fail(hmc_status st, const char* what, hipError_t e = hipSuccess)
+{
+    t_create_err = what;
+    if (e != hipSuccess) {
+        t_create_err += ": ";
+        t_create_err += hipGetErrorString(e);
+    }
+    return st;
+}
+
 hmc_status build_context(const hmc_params* p, int n, const hmc_replica* r, void* ws, size_t ws_bytes,
                          hipStream_t stream, bool batch, hmc_ctx* out)
 {
     const Layout L = layout_of(p, n, r);
-    if (!ws || ((uintptr_t)ws % kAlign) != 0) return HMC_EINVAL;
-    if (ws_bytes < L.total) return HMC_ESHAPE;
+    if (!ws || ((uintptr_t)ws % kAlign) != 0) return create_fail(HMC_EINVAL, "workspace null or not 256-byte aligned");
+    if (ws_bytes < L.total) return create_fail(HMC_ESHAPE, "workspace smaller than the layout needs");
     hmc_ctx c = new (std::nothrow) hmc_ctx_s();
-    if (!c) return HMC_EINVAL;
+    if (!c) return create_fail(HMC_EINVAL, "out of host memory");
     c->p = *p;
     c->n_rep = n;
     c->is_batch = batch;
     c->Q = (int32_t)L.grains;
     c->stream = stream;
-    if (hipGetDevice(&c->device) != hipSuccess) {
+    if (hipError_t e = hipGetDevice(&c->device); e != hipSuccess) {
         delete c;
-        return HMC_EDEVICE;
+        return create_fail(HMC_EDEVICE, "hipGetDevice", e);
     }
     c->total_sites = L.sites;
     c->colours = colours_of(p->neighbors);
@@ -572,10 +588,13 @@ hmc_status build_context(const hmc_params* p, int n, const hmc_replica* r, void*
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d.reps, c->reps.data(), c->reps.size() * sizeof(RepDev), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->d.sweep, &zero, sizeof zero, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         delete c;
-        return HMC_EDEVICE;
+        return create_fail(HMC_EDEVICE, "copying the replica tables to the workspace", e);
+    }
+    if (e = hipStreamSynchronize(stream); e != hipSuccess) {
+        delete c;
+        return create_fail(HMC_EDEVICE, "synchronising the stream after set-up", e);
     }
     // batches carry their loads from creation; a single lattice gets one from hmc_set_load
     c->have_load = batch;
@@ -811,27 +830,29 @@ size_t hmc_batch_workspace_bytes(const hmc_params* common, int32_t n, const hmc_
 
 hmc_status hmc_create(const hmc_params* p, int32_t Q, void* ws, size_t ws_bytes, hipStream_t stream, hmc_ctx* out)
 {
-    if (!out) return HMC_EINVAL;
+    t_create_err.clear();
+    if (!out) return create_fail(HMC_EINVAL, "null output handle");
     *out = nullptr;
     hmc_status st = check_common(p);
-    if (st != HMC_OK) return st;
+    if (st != HMC_OK) return create_fail(st, "invalid parameters");
     const hmc_replica r = replica_of_params(p, Q);
     st = check_replica(p, &r);
-    if (st != HMC_OK) return st;
+    if (st != HMC_OK) return create_fail(st, "invalid lattice size, grain count or physics constants");
     return build_context(p, 1, &r, ws, ws_bytes, stream, false, out);
 }
 
 hmc_status hmc_batch_create(const hmc_params* common, int32_t n, const hmc_replica* reps, void* ws, size_t ws_bytes,
                             hipStream_t stream, hmc_ctx* out)
 {
-    if (!out) return HMC_EINVAL;
+    t_create_err.clear();
+    if (!out) return create_fail(HMC_EINVAL, "null output handle");
     *out = nullptr;
     hmc_status st = check_common(common);
-    if (st != HMC_OK) return st;
-    if (n < 1 || n > kMaxReplicas || !reps) return HMC_EINVAL;
+    if (st != HMC_OK) return create_fail(st, "invalid common parameters");
+    if (n < 1 || n > kMaxReplicas || !reps) return create_fail(HMC_EINVAL, "replica count out of range");
     for (int i = 0; i < n; ++i) {
         st = check_replica(common, &reps[i]);
-        if (st != HMC_OK) return st;
+        if (st != HMC_OK) return create_fail(st, "invalid replica description");
     }
     return build_context(common, n, reps, ws, ws_bytes, stream, true, out);
 }
@@ -851,7 +872,7 @@ void hmc_destroy(hmc_ctx c)
     delete c;
 }
 
-const char* hmc_last_error(hmc_ctx c) { return c ? c->err.c_str() : "null context"; }
+const char* hmc_last_error(hmc_ctx c) { return c ? c->err.c_str() : t_create_err.c_str(); }
 
 hmc_status hmc_grain_tables(const double* euler, int32_t Q, double C11, double C12, double C44, double* C_out,
                             double* S_out)

@@ -34,7 +34,8 @@ struct TrialEntry {
 
 constexpr int kMaxReplicas = 4096;
 constexpr int kSiteBlock = 256;        // nodes per block of node-parallel kernels
-constexpr int kPassSites = 1024;       // active sites per block of a colour pass
+constexpr int kPassSites = 1024;       // active sites per chunk of a colour pass (one replica's)
+constexpr int kPassSplitBelow = 1024;  // passes with fewer chunks run one site per thread
 constexpr int kMaxChunkBlocks = 8192;  // blocks per replica of node-parallel reductions
 constexpr int kTileX = 32, kTileY = 8;   // node tile of the explicit step in x, y
 constexpr int kTileZMax = 32;            // deepest tile in z (node layers per block)

@@ -195,27 +195,33 @@ __device__ __forceinline__ void block_sum2(uint32_t& a, uint32_t& b)
     b = s_b[0] + s_b[1] + s_b[2] + s_b[3];
 }
 
-// One block covers kPassSites = 4 x 256 active sites of one replica (the replica is uniform
-// per block); each thread takes four of them, 256 apart.  Phase 1 draws every trial and
+// A chunk of kPassSites = 4 x 256 active sites belongs to one replica.  With SPT = 4 one
+// block covers a chunk and each thread takes four sites, 256 apart; with SPT = 1 four blocks
+// share a chunk, one site per thread (the same sites and draws, a quarter each).  Lattices
+// with few chunks per pass (128^3 with 8 colours has 256) take SPT = 1: four times the
+// wavefronts to hide the chain of dependent reads of a site.  Phase 1 draws every trial and
 // keeps only the real flips (q_new != q_old), which a wavefront then compacts through LDS
 // so that phase 2 -- the 26 neighbour reads, the decision or the screen -- runs once per 64
 // real flips instead of once per site slot (inside grains most proposals are no-ops, and a
 // single real flip would otherwise hold the whole wavefront).  A colour pass has tens of
 // thousands of blocks on large lattices, so the block appends its elastic trials with one
 // atomic on the list counter and adds its statistics to one of the spread counter copies.
-static_assert(kPassSites == 4 * 256, "four sites per thread of a 256-thread block");
+static_assert(kPassSites == 4 * 256, "a chunk is four sites per thread of a 256-thread block");
 // SCREEN: the lower-bound screen's FP64 path is compiled in only where it is used, since it
 // more than doubles the kernel's registers (126 against 48 VGPRs: 4 against 8 wavefronts per
 // SIMD, which hide the chain of dependent reads of every site).
-template <int M, bool SCREEN>
+template <int M, bool SCREEN, int SPT>
 __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
 {
-    constexpr int SPT = kPassSites / 256;
+    static_assert(SPT == 1 || SPT == 4, "one or four sites per thread");
+    constexpr int SUB = kPassSites / (256 * SPT);    // blocks per chunk
     __shared__ uint32_t s_item[4][SPT * 64][3];      // per wavefront: coords, q_old | q_new << 16, r1
     const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);   // neighbouring rows share an L2
-    const int r = a.pass_rep[lb];
+    const int chunk = lb / SUB, sub = lb % SUB;
+    const int r = a.pass_rep[chunk];
     const RepDev R = a.reps[r];
-    const uint32_t first = (uint32_t)(lb - R.pass_first) * (uint32_t)kPassSites + threadIdx.x;
+    const uint32_t first =
+        (uint32_t)(chunk - R.pass_first) * (uint32_t)kPassSites + (uint32_t)sub * 256u + threadIdx.x;
     const uint32_t n_active = (uint32_t)(R.n3 / (M == 26 ? 8 : 2));
     const bool elastic = R.elastic != 0;
     int16_t* spins = a.spins + R.site_off;
@@ -480,14 +486,26 @@ hipError_t launch_potts_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
     a.plane = c->total_sites;
     a.colour = colour;
     a.screen = (c->p.zone_screen != 0 && c->d.sigma != nullptr) ? 1 : 0;
-    const dim3 grid((unsigned)c->pass_blocks), block(256);
+    // one site per thread while a pass has fewer chunks than 4 per compute unit
+    const bool one = c->pass_blocks < kPassSplitBelow;
+    const dim3 grid((unsigned)(one ? 4 * c->pass_blocks : c->pass_blocks)), block(256);
     const int tok = prof_begin(c, kProfPotts);
     if (c->p.neighbors == 26) {
-        if (a.screen) hipLaunchKernelGGL((k_potts_pass<26, true>), grid, block, 0, c->stream, a);
-        else hipLaunchKernelGGL((k_potts_pass<26, false>), grid, block, 0, c->stream, a);
+        if (one) {
+            if (a.screen) hipLaunchKernelGGL((k_potts_pass<26, true, 1>), grid, block, 0, c->stream, a);
+            else hipLaunchKernelGGL((k_potts_pass<26, false, 1>), grid, block, 0, c->stream, a);
+        } else {
+            if (a.screen) hipLaunchKernelGGL((k_potts_pass<26, true, 4>), grid, block, 0, c->stream, a);
+            else hipLaunchKernelGGL((k_potts_pass<26, false, 4>), grid, block, 0, c->stream, a);
+        }
     } else {
-        if (a.screen) hipLaunchKernelGGL((k_potts_pass<6, true>), grid, block, 0, c->stream, a);
-        else hipLaunchKernelGGL((k_potts_pass<6, false>), grid, block, 0, c->stream, a);
+        if (one) {
+            if (a.screen) hipLaunchKernelGGL((k_potts_pass<6, true, 1>), grid, block, 0, c->stream, a);
+            else hipLaunchKernelGGL((k_potts_pass<6, false, 1>), grid, block, 0, c->stream, a);
+        } else {
+            if (a.screen) hipLaunchKernelGGL((k_potts_pass<6, true, 4>), grid, block, 0, c->stream, a);
+            else hipLaunchKernelGGL((k_potts_pass<6, false, 4>), grid, block, 0, c->stream, a);
+        }
     }
     prof_end(c, tok);
     return hipGetLastError();

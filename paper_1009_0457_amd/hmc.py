@@ -124,6 +124,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"HIP library not built: {LIB_PATH} (run paper_1009_0457_amd.build)")
+        # torch (which supplies device memory and streams) is loaded first: with this
+        # library's HIP runtime loaded before torch's, HIP has reported no visible device.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, res, args in _SIGS:
             f = getattr(L, name)
@@ -141,9 +144,14 @@ def _ptr(t):
     return C.c_void_p(int(t.data_ptr()))
 
 
-def _check(status, ctx=None):
+def _check(status, ctx=None, creating=False):
+    """Raise on a failed call.  A failed context creation has no context to hold its
+    message; the library keeps it per thread (hmc_last_error(NULL))."""
     if status != HMC_OK:
-        msg = lib().hmc_last_error(ctx).decode() if ctx else ""
+        if ctx:
+            msg = lib().hmc_last_error(ctx).decode()
+        else:
+            msg = lib().hmc_last_error(None).decode() if creating else ""
         raise HmcError(status, msg)
 
 
@@ -161,7 +169,7 @@ def hmc_workspace_bytes(p: hmc_params, Q: int) -> int:
 def hmc_create(p: hmc_params, Q: int, workspace, stream_handle: int):
     ctx = C.c_void_p()
     _check(lib().hmc_create(C.byref(p), Q, _ptr(workspace), workspace.numel(), C.c_void_p(stream_handle),
-                            C.byref(ctx)))
+                            C.byref(ctx)), creating=True)
     return ctx
 
 
@@ -307,7 +315,7 @@ def hmc_batch_workspace_bytes(common: hmc_params, reps) -> int:
 def hmc_batch_create(common: hmc_params, reps, workspace, stream_handle: int):
     ctx = C.c_void_p()
     _check(lib().hmc_batch_create(C.byref(common), len(reps), _rep_array(reps), _ptr(workspace), workspace.numel(),
-                                  C.c_void_p(stream_handle), C.byref(ctx)))
+                                  C.c_void_p(stream_handle), C.byref(ctx)), creating=True)
     return ctx
 
 

@@ -107,7 +107,8 @@ def mean_abs_deviation(phi_deg, fractions):
 
 def texture_run(K=100, runs=10, *, Q=91, coarsen_steps=100, kT=2.6, load_MPa=30.0, substeps=75,
                 refresh_steps=200, neighbors=26, zone_h=2, zone_steps=200, lambda_scale=1.0, screen=True,
-                record_every=5, C=(250.8, 150.0, 123.5), seed=300, philox_seed=400, device="cuda:0"):
+                record_every=5, C=(250.8, 150.0, 123.5), seed=300, philox_seed=400, profile=False,
+                device="cuda:0"):
     """Sec. 7's texture experiment as one fused batch of ``runs`` replicas on the library.
 
     Every site starts as an independent random choice among Q rotations about z; the lattice
@@ -118,7 +119,11 @@ def texture_run(K=100, runs=10, *, Q=91, coarsen_steps=100, kT=2.6, load_MPa=30.
     energy scale of every replica; 0 runs the same schedule without any load (the control).
 
     Returns a dict: t (sweeps since the end of coarsening, every record_every), fractions
-    (len(t), runs, Q) volume fractions per orientation, and the library's counters."""
+    (len(t), runs, Q) volume fractions per orientation, the library's counters, the wall
+    time of the loaded phase (seconds, spin read-backs included) and, with ``profile``, the
+    library's kernel times of that phase."""
+    import time
+
     from . import hmc as H
     from .synth import texture_run_inputs
 
@@ -145,6 +150,11 @@ def texture_run(K=100, runs=10, *, Q=91, coarsen_steps=100, kT=2.6, load_MPa=30.
             return np.stack([orientation_fractions(b.get_spins(r).cpu().numpy(), Q) for r in range(runs)])
 
         ts, fr = [0], [snapshot()]
+        b.reset_stats()
+        if profile:
+            b.kernel_times()
+            b.set_profiling(True)
+        t0 = time.perf_counter()
         for i in range(1, substeps + 1):
             if lambda_scale != 0.0:
                 b.set_load([load_MPa * i / substeps, 0.0, 0.0, 0.0, 0.0, 0.0])
@@ -154,7 +164,12 @@ def texture_run(K=100, runs=10, *, Q=91, coarsen_steps=100, kT=2.6, load_MPa=30.
                 ts.append(i)
                 fr.append(snapshot())
         b.synchronize()
+        wall = time.perf_counter() - t0
         st = b.stats()
+        kt = None
+        if profile:
+            b.set_profiling(False)
+            kt = b.kernel_times()
     finally:
         b.close()
-    return {"t": np.array(ts), "fractions": np.array(fr), "stats": st}
+    return {"t": np.array(ts), "fractions": np.array(fr), "stats": st, "wall_s": wall, "kernel_times": kt}

@@ -140,6 +140,14 @@ def test_shape_limits():
     assert ws > 64
     st = L.hmc_create(C.byref(p), 8, C.c_void_p(aligned), 16, None, C.byref(ctx))
     assert st == H.HMC_ESHAPE
+    # a failed creation has no context; its message is kept per thread
+    assert b"workspace smaller" in L.hmc_last_error(None)
+    q = H.hmc_params.from_buffer_copy(p)
+    q.neighbors = 7
+    assert L.hmc_create(C.byref(q), 8, C.c_void_p(aligned), 16, None, C.byref(ctx)) == H.HMC_EINVAL
+    assert L.hmc_last_error(None) == b"invalid parameters"
+    with pytest.raises(H.HmcError, match="invalid parameters"):
+        H._check(H.HMC_EINVAL, None, creating=True)
 
 
 def test_load_range():
@@ -160,4 +168,4 @@ def test_null_context_calls_are_rejected():
     L = _lib_or_skip()
     assert L.hmc_sweep(None, 1) == H.HMC_EINVAL
     assert L.hmc_set_load(None, None) == H.HMC_EINVAL
-    assert L.hmc_last_error(None) == b"null context"
+    assert isinstance(L.hmc_last_error(None), bytes)

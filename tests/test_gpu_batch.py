@@ -101,6 +101,40 @@ def test_batch_equals_replicas_run_alone(graphs):
     b.close()
 
 
+def test_batch_of_large_replicas_equals_alone():
+    """Four 128^3 replicas under load fill 1024 chunks per colour pass, so the batch runs the
+    four-sites-per-thread colour pass while each replica alone (256 chunks) runs the
+    one-site-per-thread pass: spins and stress fields must still agree bit for bit."""
+    common = H.hmc_default_params(128, 26, 1)
+    common.refresh_every = 2
+    common.refresh_steps = 40
+    common.cold_steps = 200
+    common.zone_steps = 50
+    common.refresh_tile_z = 8      # the same explicit-step tiles alone and in the batch
+    reps, micros = [], []
+    for r in range(4):
+        m = voronoi_polycrystal(128, 300, 60 + r)
+        rep = H.hmc_default_replica(common, 128, m.Q)
+        rep.kT, rep.seed = 0.6, 30 + r
+        rep.sigma_MPa[r % 3] = 120.0 + 20 * r
+        reps.append(rep)
+        micros.append(m)
+    say(f"[batch] 4 replicas of 128^3 under load, 3 sweeps")
+    b = H.Batch(common, reps)
+    for r, m in enumerate(micros):
+        b.set_replica(r, m.euler, m.spins)
+    b.stress_refresh(-1, True)
+    b.sweep(3)
+    b.synchronize()
+    for r, (rep, m) in enumerate(zip(reps, micros)):
+        spins, sig, st = run_alone(common, rep, m, 3)
+        say(f"    replica {r}: changed {int(np.count_nonzero(spins != m.spins))} sites, zone solves {st['zone_solves']}")
+        assert st["zone_solves"] > 0
+        assert np.array_equal(b.get_spins(r).cpu().numpy(), spins), r
+        assert np.array_equal(b.get_stress(r).cpu().numpy(), sig), r
+    b.close()
+
+
 def test_batch_zero_load_matches_oracle():
     """Zero-load replicas of a batch against the oracle, bit for bit."""
     common = common_params(h=1)

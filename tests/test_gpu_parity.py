@@ -64,7 +64,8 @@ ZERO_CASES = [
     (18, 26, 12, 0, 5, 0.7),     # edge not a multiple of any tile
     (64, 26, 500, 0, 6, 0.5),    # full workload, zero-load twin
     (64, 26, 500, 1, 3, 0.5),
-    (128, 26, 4000, 0, 2, 0.7),  # large workload, zero-load twin
+    (128, 26, 4000, 0, 2, 0.7),  # large workload, zero-load twin (one site per thread)
+    (128, 6, 4000, 0, 2, 0.7),   # 1024 chunks per pass: four sites per thread
 ]
 
 

@@ -1,0 +1,100 @@
+"""Sec. 7's texture experiment rerun on synthetic inputs, on the library.
+
+10 runs of a 100^3 lattice (one million sites) whose sites start as random choices among
+91 rotations about z (0..90 degrees), coarsened 100 sweeps at kT/J = 2.6 without load,
+then loaded in 75 sub-loads up to 30 MPa of uniaxial tension along x, each sub-load
+followed by a quasi-static refresh and one sweep.  The same runs without load (same seeds,
+so the same coarsened start) are the control, and a run with ten times the elastic energy
+scale checks the response.  Checks: the soft orientations (0 and 90 degrees for a load along
+x) gain volume against the control in every run; the gain grows with the elastic energy
+scale about in proportion; the Gaussian variance g of Eq. (text_evl) falls.  The measured
+numbers are printed (the paper's Fig. 4 data are not in its text).
+"""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1009_0457_amd import texture as T
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PHI = np.arange(91.0)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def runs(paper):
+    K, Q = int(paper["K_texture_run"]), int(paper["n_orient_z"])
+    out = {}
+    for lam in (0.0, 1.0, 10.0):
+        say(f"[texture] K={K} Q={Q} runs=10 lambda_scale={lam}")
+        out[lam] = T.texture_run(K, 10, Q=Q, coarsen_steps=int(paper["coarsen_steps"]), kT=paper["alpha_coarsen"],
+                                 load_MPa=paper["load_MPa"], substeps=int(paper["load_substeps"]), record_every=15,
+                                 lambda_scale=lam)
+        say(f"    loaded phase {out[lam]['wall_s']:.2f} s, zone solves {out[lam]['stats']['zone_solves']}")
+    return out
+
+
+def soft(run):
+    return np.array([[T.soft_fraction(PHI, f) for f in ft] for ft in run["fractions"]])
+
+
+def test_same_start_for_every_scale(runs):
+    a = runs[0.0]["fractions"][0]
+    assert np.array_equal(a, runs[1.0]["fractions"][0]) and np.array_equal(a, runs[10.0]["fractions"][0])
+
+
+def test_soft_orientations_grow_against_control(runs):
+    d1 = soft(runs[1.0])[-1] - soft(runs[0.0])[-1]
+    d10 = soft(runs[10.0])[-1] - soft(runs[0.0])[-1]
+    se = lambda a: a.std(ddof=1) / np.sqrt(a.size)
+    say(f"    soft-fraction gain at 30 MPa over the control: x1 {d1.mean():.5f} +- {se(d1):.5f}, "
+        f"x10 {d10.mean():.5f} +- {se(d10):.5f}, ratio {d10.mean() / d1.mean():.2f}")
+    m1 = np.array([T.mean_abs_deviation(PHI, f) for f in runs[1.0]["fractions"][-1]])
+    m0 = np.array([T.mean_abs_deviation(PHI, f) for f in runs[0.0]["fractions"][-1]])
+    say(f"    mean |deviation| change against the control: {(m1 - m0).mean():.4f} deg")
+    assert np.all(d1 > 0) and d1.mean() > 5 * se(d1)
+    assert np.all(m1 < m0)
+    assert 5.0 < d10.mean() / d1.mean() < 15.0
+
+
+def test_gaussian_variance_falls(runs, paper):
+    t = runs[1.0]["t"]
+    minutes = paper["minutes_per_mc_step"]
+    for lam in (0.0, 1.0, 10.0):
+        g = np.array([T.fit_g(PHI, f.mean(0)) for f in runs[lam]["fractions"]])
+        tau, beta = T.fit_variance_law(t, g, paper["load_MPa"])
+        say(f"    x{lam}: g(t) = {' '.join(f'{v:.1f}' for v in g)}; tau {tau * minutes:.0f} min, beta {beta:.3f} deg/MPa^2")
+        if lam > 0:
+            g0 = np.array([T.fit_g(PHI, f.mean(0)) for f in runs[0.0]["fractions"]])
+            assert g[-1] < g0[-1]
+    g10 = np.array([T.fit_g(PHI, f.mean(0)) for f in runs[10.0]["fractions"]])
+    assert g10[-1] < 0.8 * g10[0]
+
+
+def test_library_first_then_torch():
+    """The binding loads torch's HIP runtime before its own whatever the caller imports first."""
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1009_0457_amd import hmc as H\n"
+            "p = H.hmc_default_params(16, 26, 1)\n"
+            "p.lambda_el = 0.0\n"
+            "lat = H.Lattice(p, 4)\n"
+            "lat.set_orientations(__import__('numpy').zeros((4, 3)))\n"
+            "lat.set_spins(__import__('numpy').arange(16 ** 3, dtype='int32') %% 4)\n"
+            "lat.sweep(2)\n"
+            "print('swept', int(lat.stats()['site_trials']))\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=110)
+    say(r.stdout.strip(), r.stderr.strip()[-400:])
+    assert r.returncode == 0 and f"swept {2 * 16 ** 3}" in r.stdout
