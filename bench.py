@@ -541,7 +541,7 @@ def bench_texture(a):
 
     K, runs, substeps = 100, 10, 75
     log(f"[bench] texture: {runs} x {K}^3, 91 orientations about z, 30 MPa in {substeps} sub-loads")
-    out_run = T.texture_run(K, runs, substeps=substeps, record_every=substeps, profile=True)
+    out_run = T.texture_run(K, runs, substeps=substeps, record_every=substeps, profile=True, tile_z=a.tile_z)
     wall = out_run["wall_s"]
     kt = out_run["kernel_times"]
     st = out_run["stats"]
@@ -559,7 +559,8 @@ def bench_texture(a):
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"texture: {runs} runs of {K}^3, 91 rotations about z, coarsened 100 sweeps at "
                                   f"kT/J 2.6, 30 MPa xx in {substeps} sub-loads (refresh 200 steps, cold 2000, then "
-                                  f"one sweep), 26 neighbours, 5^3 zone x 200, screen on", "sites": runs * K ** 3},
+                                  f"one sweep), 26 neighbours, 5^3 zone x 200, screen on", "sites": runs * K ** 3,
+                      "tile_z": a.tile_z},
            "roofline": {"kernel": "explicit step", "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
                         "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
                         "avg_launch_ms": round(ms, 4),

@@ -108,7 +108,7 @@ def mean_abs_deviation(phi_deg, fractions):
 def texture_run(K=100, runs=10, *, Q=91, coarsen_steps=100, kT=2.6, load_MPa=30.0, substeps=75,
                 refresh_steps=200, neighbors=26, zone_h=2, zone_steps=200, lambda_scale=1.0, screen=True,
                 record_every=5, C=(250.8, 150.0, 123.5), seed=300, philox_seed=400, profile=False,
-                device="cuda:0"):
+                tile_z=0, device="cuda:0"):
     """Sec. 7's texture experiment as one fused batch of ``runs`` replicas on the library.
 
     Every site starts as an independent random choice among Q rotations about z; the lattice
@@ -133,6 +133,7 @@ def texture_run(K=100, runs=10, *, Q=91, coarsen_steps=100, kT=2.6, load_MPa=30.
     common.refresh_every = 1 << 30          # refreshes are explicit, once per sub-load
     common.zone_screen = 1 if screen else 0
     common.C11, common.C12, common.C44 = C
+    common.refresh_tile_z = tile_z          # 0: the library's automatic depth
     reps = []
     for r in range(runs):
         rep = H.hmc_default_replica(common, K, Q)
