@@ -88,6 +88,10 @@ def parse():
                          "texture: the ten 100^3 runs of the loaded texture experiment as one batch")
     ap.add_argument("--neighbors", type=int, choices=[6, 26], default=None,
                     help="growth: 6 neighbours / 2 colours or 26 / 8 (default 26)")
+    ap.add_argument("--zone-h", type=int, default=None, choices=[0, 1, 2, 3],
+                    help="large: zone half-width other than the workload's 2 (a different configuration; "
+                         "for the zone-size comparison)")
+    ap.add_argument("--zone-steps", type=int, default=None, help="large: zone relaxation steps n_r")
     ap.add_argument("--replicas", type=int, default=64)
     ap.add_argument("--zone-variant", type=int, default=0, help="zone-solve kernel (0 = automatic)")
     ap.add_argument("--tile-z", type=int, default=0, help="node layers per block of the explicit step (0 = automatic)")
@@ -691,9 +695,10 @@ def main():
     log(f"[bench] building {K}^3 microstructure with {cfg.n_grains} grains")
     micro = voronoi_polycrystal(K, cfg.n_grains if K == cfg.K else max(8, cfg.n_grains * K ** 3 // cfg.K ** 3),
                                 cfg.seed)
-    p = H.hmc_default_params(K, cfg.neighbors, cfg.zone_h)
+    zh = cfg.zone_h if a.zone_h is None else a.zone_h
+    p = H.hmc_default_params(K, cfg.neighbors, zh)
     p.kT = cfg.kT
-    p.zone_steps = cfg.zone_steps
+    p.zone_steps = cfg.zone_steps if a.zone_steps is None else a.zone_steps
     p.refresh_every = cfg.refresh_every
     p.proposal = 0 if a.proposal == "neighbor" else 1
     p.seed = cfg.philox_seed
@@ -768,7 +773,7 @@ def main():
                         "avg_launch_ms": round(rs["total_ms"] / rs["launches"], 4),
                         "note": f"working set {(13 * 4 + 2) * K ** 3 / 2 ** 20:.0f} MiB (cache-resident at 128^3)"}
     out = {
-        "metric": METRIC,
+        "metric": METRIC if p.zone_h == 2 else METRIC.replace("5^3 zone", f"{2 * p.zone_h + 1}^3 zone"),
         "value": value,
         "unit": "site-trials/s",
         "n_gpus": 1,
@@ -782,7 +787,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"large-{K}: {K}^3 periodic, 26 neighbours / 8 colours, {micro.Q} Voronoi grains, "
                                f"{'no load (elastic term off)' if a.zero_load else 'biaxial 150/150 MPa'}, kT {p.kT}, "
-                               f"5^3 zone x {p.zone_steps} steps, refresh every "
+                               f"{2 * p.zone_h + 1}^3 zone x {p.zone_steps} steps, refresh every "
                                f"{p.refresh_every} sweeps x {p.refresh_steps} steps, proposal {a.proposal}",
                    "K": K, "neighbors": p.neighbors, "zone_h": p.zone_h, "zone_steps": p.zone_steps,
                    "proposal": a.proposal, "zone_variant": a.zone_variant},

@@ -63,11 +63,11 @@ typedef struct {
     int32_t refresh_steps;  /* explicit steps of each such warm refresh */
     int32_t cold_steps;     /* explicit steps hmc_stress_refresh uses for cold_start with
                                n_steps < 0 */
-    int32_t zone_variant;   /* zone-solve kernel: 0 automatic (3 for h = 1, 2; 2 for h = 0;
-                               1 for h = 3), 1 one wavefront per trial, 2 node columns across a
+    int32_t zone_variant;   /* zone-solve kernel: 0 automatic (3 for h >= 1; 2 for h = 0),
+                               1 one wavefront per trial, 2 node columns across a
                                256-lane work-group (h <= 2), 3 node columns of whole trials per
                                wavefront, x neighbours exchanged by cross-lane moves
-                               (1 <= h <= 2).  Other values: HMC_EINVAL. */
+                               (1 <= h <= 3).  Other values: HMC_EINVAL. */
     int32_t zone_screen;    /* 1: skip the zone solve of a trial whose rejection is already
                                certain: the point-zone energy 1/2 sigma_p.(S_old - S_new) sigma_p
                                is a lower bound of the zone's (its relaxation only adds

@@ -23,7 +23,7 @@ def zone_variants_for(zone_h: int) -> list[int]:
     out = [1]
     if zone_h <= 2:
         out.append(2)
-    if 1 <= zone_h <= 2:
+    if zone_h >= 1:
         out.append(3)
     return out
 

@@ -12,7 +12,7 @@
 // Three kernels compute this solve with different layouts (hmc_params.zone_variant):
 // k_zone (a wavefront per trial), k_zone_col (node columns of several trials across a
 // 256-lane work-group) and k_zone_lane (whole trials inside one wavefront, x neighbours by
-// cross-lane moves; the default for h = 1, 2).  State and arithmetic are FP32; the final
+// cross-lane moves; the default for h = 1, 2, 3).  State and arithmetic are FP32; the final
 // energy is accumulated in FP64.  The decision uses the same predicate as the integer
 // path: accept iff dE <= 0 or r1 < 2^32 exp(-dE/kT).
 //
@@ -612,12 +612,14 @@ struct LaneShiftShape {
     static constexpr int PAD = 8;                       // leading zeros of the force array
 };
 
+// h = 3 (56 lanes of one trial per wavefront) holds 7 x 21 stiffness registers per lane:
+// with one wavefront per SIMD it keeps them without spilling.
 template <int H>
-__global__ __launch_bounds__(64, 2) void k_zone_lane(ZoneArgs a)
+__global__ __launch_bounds__(64, H == 3 ? 1 : 2) void k_zone_lane(ZoneArgs a)
 {
     using S = LaneShiftShape<H>;
     constexpr int N = S::N, NN = S::NN, LT = S::LT, TW = S::TW, Z = S::Z, ROW = S::ROW, TB = S::TB;
-    static_assert(H >= 1 && TW >= 1 && 3 * NN <= LT, "lane-shift variant needs 1 <= h <= 2");
+    static_assert(H >= 1 && H <= 3 && TW >= 1 && 3 * NN <= LT, "lane-shift variant needs 1 <= h <= 3");
     static_assert(TB % 64 == LT % 64 && TB >= S::BODY + NN, "block stride");
 
     // blocks 0..Z-1 belong to trials, block Z to lanes outside every trial
@@ -894,13 +896,14 @@ hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
     a.alpha = (float)c->p.zone_alpha;
     a.beta = (float)c->p.zone_beta;
     const int h = c->p.zone_h;
-    // automatic: lane shifts for h = 1, 2; node columns for h = 0; a wavefront per trial for h = 3
+    // automatic: lane shifts for h >= 1 (at h = 3, 1.39e6 solves/s against 3.75e5 for a
+    // wavefront per trial, 128^3 workload, n_r = 400); node columns for h = 0
     const int v = c->p.zone_variant;
-    const bool laneshift = (v == 0 && (h == 1 || h == 2)) || v == 3;
+    const bool laneshift = (v == 0 && h >= 1) || v == 3;
     const bool column = !laneshift && ((v == 0 && h <= 2) || v == 2);
     const int tok = prof_begin(c, kProfZone);
     if (laneshift) {
-        const int per_wg = h == 1 ? LaneShiftShape<1>::Z : LaneShiftShape<2>::Z;
+        const int per_wg = h == 1 ? LaneShiftShape<1>::Z : h == 2 ? LaneShiftShape<2>::Z : LaneShiftShape<3>::Z;
         int64_t g = (c->max_list + per_wg - 1) / per_wg;
         // many more work-groups than resident slots: a work-group takes at most a group or
         // two, and the hardware's dispatch balances the tail (measured: 8192 -> 65536
@@ -913,6 +916,7 @@ hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
         switch (h) {
             case 1: hipLaunchKernelGGL(k_zone_lane<1>, grid, block, 0, c->stream, a); break;
             case 2: hipLaunchKernelGGL(k_zone_lane<2>, grid, block, 0, c->stream, a); break;
+            case 3: hipLaunchKernelGGL(k_zone_lane<3>, grid, block, 0, c->stream, a); break;
             default: return hipErrorInvalidValue;
         }
     } else if (column) {

@@ -103,7 +103,7 @@ def test_create_validates_before_touching_the_device(field, value, status):
 
 def test_zone_variant_limits():
     L = _lib_or_skip()
-    for h, variant, ok in ((0, 3, False), (3, 3, False), (3, 2, False), (1, 3, True), (2, 3, True), (3, 1, True),
+    for h, variant, ok in ((0, 3, False), (3, 3, True), (3, 2, False), (1, 3, True), (2, 3, True), (3, 1, True),
                            (0, 2, True)):
         p = H.hmc_default_params(16, 26, h)
         p.zone_variant = variant

@@ -353,7 +353,8 @@ def test_elastic_lockstep_sampled_at_workload_size(which, variant):
     lat.close()
 
 
-@pytest.mark.parametrize("h,variant", [(0, 0), (0, 1), (1, 0), (1, 2), (2, 0), (2, 1), (2, 2), (3, 0)])
+@pytest.mark.parametrize("h,variant", [(0, 0), (0, 1), (1, 0), (1, 2), (2, 0), (2, 1), (2, 2), (3, 0), (3, 1),
+                                       (3, 3)])
 def test_elastic_lockstep_zone_sizes(h, variant):
     """Every zone size the library accepts, both kernels, on a lattice whose edge is not a
     multiple of the zone (ragged wrap-around), with uniform proposals (many solves)."""
