@@ -121,10 +121,13 @@ def z_rotation_euler(n: int = 91, step_deg: float = 1.0) -> np.ndarray:
     return e
 
 
-def texture_run_inputs(K: int = 100, runs: int = 10, Q: int = 91, seed: int = 300):
-    """Sec. 7's texture runs: every site an independent uniform choice among Q rotations
-    about z (0..90 degrees); one (euler, spins) pair per run, run r drawn with seed + r."""
-    e = z_rotation_euler(Q, 90.0 / (Q - 1))
+def texture_run_inputs(K: int = 100, runs: int = 10, Q: int = 91, seed: int = 300, euler=None):
+    """Sec. 7's texture runs: every site an independent uniform choice among Q orientations,
+    by default the rotations about z by 0..90 degrees; one (euler, spins) pair per run, run r
+    drawn with seed + r."""
+    e = z_rotation_euler(Q, 90.0 / (Q - 1)) if euler is None else np.ascontiguousarray(euler, np.float64)
+    if e.shape != (Q, 3):
+        raise ValueError("euler must hold Q Bunge triples")
     return [(e, random_spins(K, Q, seed + r)) for r in range(runs)]
 
 

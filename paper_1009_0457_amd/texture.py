@@ -23,7 +23,8 @@ import math
 import numpy as np
 
 __all__ = ["signed_deviation", "orientation_fractions", "gaussian_density", "fit_g", "fit_variance_law",
-           "young_x", "young_phi", "soft_fraction", "mean_abs_deviation"]
+           "young_x", "young_phi", "modulus_ratio", "modulus_density", "soft_fraction", "mean_abs_deviation",
+           "texture_run"]
 
 
 def signed_deviation(phi_deg):
@@ -93,6 +94,23 @@ def young_phi(x, a=0.388, b=16.40, c=0.541):
     return 45.0 - np.sqrt(-2.0 * b * b * np.log((x - c) / a))
 
 
+def modulus_ratio(euler, C=(250.8, 150.0, 123.5), axis=0):
+    """x = E / C11 of every orientation along a lab axis (0 = x): E = 1 / S'_aa of the rotated
+    compliance, from the library's per-grain tables (Sec. 5, Eq. stiffrot)."""
+    from . import hmc as H
+
+    _, S = H.hmc_grain_tables(euler, *C)
+    return 1.0 / S[:, axis, axis] / C[0]
+
+
+def modulus_density(x, fractions, lo=0.55, hi=0.929, nbins=91):
+    """Volume fractions binned by modulus ratio x on [lo, hi] (Sec. 7 integrates its 999
+    orientations into 91 points); returns (bin centres, fractions per bin)."""
+    edges = np.linspace(lo, hi, nbins + 1)
+    k = np.clip(np.searchsorted(edges, np.asarray(x, float), side="right") - 1, 0, nbins - 1)
+    return 0.5 * (edges[1:] + edges[:-1]), np.bincount(k, weights=np.asarray(fractions, float), minlength=nbins)
+
+
 def soft_fraction(phi_deg, fractions, within_deg=10.0):
     """Volume fraction within within_deg of a soft orientation."""
     return float(np.asarray(fractions)[np.abs(signed_deviation(phi_deg)) <= within_deg].sum())
@@ -108,10 +126,11 @@ def mean_abs_deviation(phi_deg, fractions):
 def texture_run(K=100, runs=10, *, Q=91, coarsen_steps=100, kT=2.6, load_MPa=30.0, substeps=75,
                 refresh_steps=200, neighbors=26, zone_h=2, zone_steps=200, lambda_scale=1.0, screen=True,
                 record_every=5, C=(250.8, 150.0, 123.5), seed=300, philox_seed=400, profile=False,
-                tile_z=0, device="cuda:0"):
+                tile_z=0, euler=None, device="cuda:0"):
     """Sec. 7's texture experiment as one fused batch of ``runs`` replicas on the library.
 
-    Every site starts as an independent random choice among Q rotations about z; the lattice
+    Every site starts as an independent random choice among Q orientations (``euler``, Q Bunge
+    triples; by default the rotations about z by 0..90 degrees); the lattice
     coarsens for ``coarsen_steps`` sweeps without load; then, for sub-load i = 1..substeps,
     the uniaxial load i/substeps * load_MPa along x is set, the stress field is relaxed to its
     quasi-static state (a cold start of cold_steps the first time, then warm refreshes of
@@ -143,7 +162,7 @@ def texture_run(K=100, runs=10, *, Q=91, coarsen_steps=100, kT=2.6, load_MPa=30.
         reps.append(rep)
     b = H.Batch(common, reps, device=device)
     try:
-        for r, (eu, q0) in enumerate(texture_run_inputs(K, runs, Q, seed)):
+        for r, (eu, q0) in enumerate(texture_run_inputs(K, runs, Q, seed, euler)):
             b.set_replica(r, eu, q0)
         b.sweep(coarsen_steps)
 

@@ -98,3 +98,41 @@ def test_library_first_then_torch():
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=110)
     say(r.stdout.strip(), r.stderr.strip()[-400:])
     assert r.returncode == 0 and f"swept {2 * 16 ** 3}" in r.stdout
+
+
+# --------------------------------------------------------------------------------------
+# Sec. 7's second study: 999 orientations spanning all three Euler angles, 20 runs,
+# texture measured by the effective Young's modulus along the load
+# --------------------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def runs999(paper):
+    from paper_1009_0457_amd.synth import haar_euler
+
+    eu = haar_euler(np.random.default_rng(999), 999)
+    out = {"euler": eu}
+    for lam in (0.0, 1.0, 10.0):
+        say(f"[texture 999] K=100 Q=999 runs=20 lambda_scale={lam}")
+        out[lam] = T.texture_run(100, 20, Q=999, coarsen_steps=int(paper["coarsen_steps"]), kT=paper["alpha_coarsen"],
+                                 load_MPa=paper["load_MPa"], substeps=int(paper["load_substeps"]),
+                                 record_every=int(paper["load_substeps"]), lambda_scale=lam, euler=eu, seed=700,
+                                 philox_seed=800)
+        say(f"    loaded phase {out[lam]['wall_s']:.2f} s, zone solves {out[lam]['stats']['zone_solves']}")
+    return out
+
+
+def test_999_orientations_soften_against_control(runs999, paper):
+    C = (paper["C11_paper"], paper["C12_paper"], paper["C44_paper"])
+    x = T.modulus_ratio(runs999["euler"], C)
+    xm = {lam: (runs999[lam]["fractions"][-1] * x).sum(-1) for lam in (0.0, 1.0, 10.0)}
+    x0 = (runs999[0.0]["fractions"][0] * x).sum(-1)
+    assert np.array_equal(runs999[0.0]["fractions"][0], runs999[1.0]["fractions"][0])
+    d1, d10 = xm[1.0] - xm[0.0], xm[10.0] - xm[0.0]
+    se = lambda a: a.std(ddof=1) / np.sqrt(a.size)
+    soft = x < np.quantile(x, 1 / 3)
+    sf = {lam: runs999[lam]["fractions"][-1][:, soft].sum(-1).mean() for lam in (0.0, 1.0, 10.0)}
+    say(f"    mean E_x/C11: start {x0.mean():.5f}; change against the control x1 {d1.mean():.2e} +- {se(d1):.1e}, "
+        f"x10 {d10.mean():.2e} +- {se(d10):.1e} (ratio {d10.mean() / d1.mean():.2f}); softest third of the "
+        f"orientations holds {sf[0.0]:.4f} / {sf[1.0]:.4f} / {sf[10.0]:.4f} of the volume")
+    assert np.all(d1 < 0) and -d1.mean() > 5 * se(d1)
+    assert 5.0 < d10.mean() / d1.mean() < 15.0
+    assert sf[10.0] > sf[1.0] > sf[0.0]

@@ -67,3 +67,27 @@ def test_young_fit_endpoints_and_inverse(paper):
     assert abs(T.young_x(45.0, **kw) - paper["x_high"]) < 5e-4
     phi = np.linspace(0.0, 44.9, 50)
     assert np.abs(T.young_phi(T.young_x(phi)) - phi).max() < 1e-9
+
+
+def test_modulus_ratio_about_z_follows_the_papers_fit(paper):
+    """x(phi) = E_x / C11 of the library's rotated tables for rotations about z against the
+    Gaussian fit of Eq. (young_gau) with the paper's constants: endpoints and shape agree to
+    the printed digits of the fit (0.55 and 0.929; measured deviation at most 0.0024)."""
+    pytest.importorskip("torch")
+    from paper_1009_0457_amd import hmc as H
+    from paper_1009_0457_amd.synth import z_rotation_euler
+    if not __import__("os").path.exists(H.LIB_PATH):
+        pytest.skip("library not built")
+    C = (paper["C11_paper"], paper["C12_paper"], paper["C44_paper"])
+    x = T.modulus_ratio(z_rotation_euler(91), C)
+    fit = T.young_x(PHI, paper["fit_a"], paper["fit_b_deg"], paper["fit_c"])
+    assert abs(x[0] - paper["x_low"]) < 5e-3 and abs(x[45] - paper["x_high"]) < 5e-3
+    assert np.abs(x - fit).max() < 5e-3
+    assert np.allclose(x, x[::-1], atol=1e-12)          # E(phi) = E(90 - phi)
+
+
+def test_modulus_density_bins():
+    x = np.array([0.55, 0.6, 0.929, 0.7, 0.7])
+    f = np.array([0.1, 0.2, 0.3, 0.15, 0.25])
+    c, d = T.modulus_density(x, f, nbins=10)
+    assert abs(d.sum() - 1.0) < 1e-12 and d[0] == pytest.approx(0.1) and d[-1] == pytest.approx(0.3)
