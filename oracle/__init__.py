@@ -98,6 +98,9 @@ def lib():
         L.ora_sweeps.argtypes = [C.POINTER(Params), _i32p, _f64p, _f64p, _f64p, _f64p, _f64p,
                                  C.c_uint32, C.c_int]
         L.ora_gs_sweeps.argtypes = [C.POINTER(Params), _i32p, C.c_uint32, C.c_int]
+        L.ora_global_mp8.argtypes = L.ora_global.argtypes
+        L.ora_residual_mp8.argtypes = [C.c_int, _i32p, _f64p, _f64p, _f64p, _f64p, C.c_void_p,
+                                       C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -230,6 +233,16 @@ def solver_defaults(C11, C12, C44, K, h):
     return za, zb, ga, gb, ga
 
 
+def solver_defaults_mp8(C11, C12, C44, K):
+    """(glob_alpha, glob_beta, glob_alphaE) of the 2 x 2 x 2-points-per-cell variant: L = 8 x
+    the largest Mandel eigenvalue of the stiffness (the identity material's Hessian peaks at 8
+    there, against 4 for one point per voxel); mu = 1/2 (C11 - C12) (2 sin(2 pi / K))^2, the
+    slowest shear wave on the (K/2)^3 mesh."""
+    lam = max(C11 + 2 * C12, C11 - C12, 2 * C44)
+    a, b = polyak(8.0 * lam, 0.5 * (C11 - C12) * (2 * math.sin(2 * math.pi / K)) ** 2)
+    return a, b, a
+
+
 def calibration(K: int, l0=1.0e-3, gamma_s=0.45, gamma_mc=2.4, m_s=1.0e-13, m_star=0.27):
     """Characteristic scales of Sec. 4 (Eqs. chatime, chaeng, elamc) from Table 1 values.
 
@@ -272,6 +285,35 @@ def global_solve(K, q, Ct, St, Sigma_GPa, nsteps, cold, alpha, beta, alphaE, u=N
                      np.ascontiguousarray(St).ravel(), np.asarray(Sigma_GPa, np.float64), nsteps,
                      int(cold), alpha, beta, alphaE, u, E, _vp(sig), info)
     return u.reshape(3, n3), E, sig.reshape(6, n3), {"U": info[0], "res_u": info[1], "res_E": info[2]}
+
+
+def global_solve_mp8(K, q, Ct, St, Sigma_GPa, nsteps, cold, alpha, beta, alphaE, u=None, E=None):
+    """The global solve with 2 x 2 x 2 material points (sites) per background cell of 2^3
+    sites (Appendix); u lives on the (K/2)^3 mesh nodes.  Returns (u (3,(K/2)^3), E, sigma
+    (6,K^3) of the points, info)."""
+    if K % 2:
+        raise ValueError("K must be even")
+    n3, nn = K ** 3, (K // 2) ** 3
+    u = np.zeros(3 * nn) if u is None else np.ascontiguousarray(u, np.float64).ravel().copy()
+    E = np.zeros(6) if E is None else np.ascontiguousarray(E, np.float64).copy()
+    sig = np.zeros(6 * n3)
+    info = np.zeros(3)
+    lib().ora_global_mp8(K, np.ascontiguousarray(q, np.int32), np.ascontiguousarray(Ct).ravel(),
+                         np.ascontiguousarray(St).ravel(), np.asarray(Sigma_GPa, np.float64), nsteps,
+                         int(cold), alpha, beta, alphaE, u, E, _vp(sig), info)
+    return u.reshape(3, nn), E, sig.reshape(6, n3), {"U": info[0], "res_u": info[1], "res_E": info[2]}
+
+
+def residual_mp8(K, q, Ct, u, E):
+    """(residual forces (3,(K/2)^3), point stresses (6,K^3), stored energy) of the variant."""
+    nn, n3 = (K // 2) ** 3, K ** 3
+    r = np.zeros(3 * nn)
+    sig = np.zeros(6 * n3)
+    U = C.c_double()
+    lib().ora_residual_mp8(K, np.ascontiguousarray(q, np.int32), np.ascontiguousarray(Ct).ravel(),
+                           np.ascontiguousarray(u, np.float64).ravel(), np.asarray(E, np.float64), r, _vp(sig),
+                           C.byref(U))
+    return r.reshape(3, nn), sig.reshape(6, n3), U.value
 
 
 def elastic_energy(K, q, Ct, u, E) -> float:

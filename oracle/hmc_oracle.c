@@ -15,6 +15,8 @@
  *   - Red/black (here: 2- or 8-colour) checkerboard with updates deferred to the end of
  *     each half step: Sec. 6.  The Gauss-Seidel scheme Sec. 6 compares it with (every site
  *     in turn, each accepted change written at once) is here too, at zero load.
+ *   - Global solve with 2 x 2 x 2 material points per background cell (Appendix), as a
+ *     variant of the one-point default.
  *   - Local elastic energy change from a zone Omega_1 under constant boundary traction,
  *     "stored energy minus boundary work": Sec. 3, Eq. (H_1, second form) and Fig. 1;
  *     the point-zone limit is Eq. (eladriv).
@@ -456,6 +458,127 @@ void ora_global(int K, const int32_t* q, const double* Ctab, const double* Stab,
 }
 
 /* Stored elastic energy 1/2 sum_v eps_v . C_{q_v} eps_v of a given state (u, E). */
+/* Variant with 2 x 2 x 2 material points per background cell (the arrangement of the
+ * paper's MPM, Appendix: particles per cell fixed, two per direction).  The mesh has
+ * (K/2)^3 periodic nodes at the corners of cells of 2 x 2 x 2 sites; every site is a material
+ * point at local coordinates +-1/2 of its cell, with its own stiffness.  Its strain is the
+ * gradient of the trilinear interpolation of the cell's 8 corner displacements there (cell
+ * edge 2 sites, so d/dx = d/dxi), its nodal forces the transpose.  Otherwise the relaxation is
+ * the one of ora_global: average-stress control, heavy ball, Reuss cold start. */
+static double mp_grad(int c, int p, int dir)
+{
+    double f = 0.125;
+    for (int d = 0; d < 3; ++d) {
+        const double xc = ((c >> d) & 1) ? 1.0 : -1.0;
+        const double xp = ((p >> d) & 1) ? 0.5 : -0.5;
+        f *= (d == dir) ? xc : (1.0 + xc * xp);
+    }
+    return f;
+}
+
+static void global_residual_mp8(int K, const int32_t* q, const double* Ctab, const double* u, const double* E,
+                                double* r, double* sig_sum, double* sig_out, double* energy)
+{
+    const int64_t Kc = K / 2, nn = Kc * Kc * Kc, n3 = (int64_t)K * K * K;
+    if (r) memset(r, 0, sizeof(double) * 3 * (size_t)nn);
+    for (int I = 0; I < 6; ++I) sig_sum[I] = 0;
+    double U = 0;
+    for (int64_t Z = 0; Z < Kc; ++Z)
+        for (int64_t Y = 0; Y < Kc; ++Y)
+            for (int64_t X = 0; X < Kc; ++X) {
+                int64_t node[8];
+                double uc[8][3], f[8][3] = {{0}};
+                for (int c = 0; c < 8; ++c) {
+                    node[c] = site_of(X + (c & 1), Y + ((c >> 1) & 1), Z + ((c >> 2) & 1), (int)Kc);
+                    for (int j = 0; j < 3; ++j) uc[c][j] = u[j * nn + node[c]];
+                }
+                for (int p = 0; p < 8; ++p) {
+                    const int64_t v = site_of(2 * X + (p & 1), 2 * Y + ((p >> 1) & 1), 2 * Z + ((p >> 2) & 1), K);
+                    double g[3][3] = {{0}}, e[6], s[6];
+                    for (int c = 0; c < 8; ++c)
+                        for (int i = 0; i < 3; ++i) {
+                            const double w = mp_grad(c, p, i);
+                            for (int j = 0; j < 3; ++j) g[j][i] += w * uc[c][j];
+                        }
+                    e[0] = g[0][0] + E[0];
+                    e[1] = g[1][1] + E[1];
+                    e[2] = g[2][2] + E[2];
+                    e[3] = g[1][2] + g[2][1] + E[3];
+                    e[4] = g[0][2] + g[2][0] + E[4];
+                    e[5] = g[0][1] + g[1][0] + E[5];
+                    matvec6(Ctab + 36 * (int64_t)q[v], e, s);
+                    for (int I = 0; I < 6; ++I) sig_sum[I] += s[I];
+                    if (sig_out)
+                        for (int I = 0; I < 6; ++I) sig_out[I * n3 + v] = s[I];
+                    U += 0.5 * dot6(s, e);
+                    for (int c = 0; c < 8; ++c) {
+                        const double gx = mp_grad(c, p, 0), gy = mp_grad(c, p, 1), gz = mp_grad(c, p, 2);
+                        f[c][0] += gx * s[0] + gy * s[5] + gz * s[4];
+                        f[c][1] += gx * s[5] + gy * s[1] + gz * s[3];
+                        f[c][2] += gx * s[4] + gy * s[3] + gz * s[2];
+                    }
+                }
+                if (r)
+                    for (int c = 0; c < 8; ++c)
+                        for (int j = 0; j < 3; ++j) r[j * nn + node[c]] -= f[c][j];
+            }
+    if (energy) *energy = U;
+}
+
+/* u: 3 x (K/2)^3 node displacements (K even). */
+void ora_global_mp8(int K, const int32_t* q, const double* Ctab, const double* Stab, const double Sigma[6],
+                    int nsteps, int cold, double alpha, double beta, double alphaE,
+                    double* u, double* E, double* sigma_out, double* info)
+{
+    const int64_t n3 = (int64_t)K * K * K, nn = n3 / 8;
+    if (cold) {
+        memset(u, 0, sizeof(double) * 3 * (size_t)nn);
+        double Sm[36] = {0};
+        for (int64_t v = 0; v < n3; ++v)
+            for (int a = 0; a < 36; ++a) Sm[a] += Stab[36 * (int64_t)q[v] + a];
+        for (int a = 0; a < 36; ++a) Sm[a] /= (double)n3;
+        matvec6(Sm, Sigma, E);
+    }
+    double* w = (double*)calloc(3 * (size_t)nn, sizeof(double));
+    double* r = (double*)malloc(sizeof(double) * 3 * (size_t)nn);
+    double wE[6] = {0}, ssum[6];
+    for (int t = 0; t < nsteps; ++t) {
+        global_residual_mp8(K, q, Ctab, u, E, r, ssum, NULL, NULL);
+        for (int64_t a = 0; a < 3 * nn; ++a) {
+            w[a] = beta * w[a] + alpha * r[a];
+            u[a] += w[a];
+        }
+        for (int I = 0; I < 6; ++I) {
+            const double rE = Sigma[I] - ssum[I] / (double)n3;
+            wE[I] = beta * wE[I] + alphaE * rE;
+            E[I] += wE[I];
+        }
+    }
+    double U;
+    global_residual_mp8(K, q, Ctab, u, E, r, ssum, sigma_out, &U);
+    if (info) {
+        double rn = 0, re = 0;
+        for (int64_t a = 0; a < 3 * nn; ++a) rn += r[a] * r[a];
+        for (int I = 0; I < 6; ++I) {
+            const double d = Sigma[I] - ssum[I] / (double)n3;
+            re += d * d;
+        }
+        info[0] = U;
+        info[1] = sqrt(rn);
+        info[2] = sqrt(re);
+    }
+    free(w);
+    free(r);
+}
+
+/* Residual forces (3 x (K/2)^3) and the point stresses of the variant above at (u, E). */
+void ora_residual_mp8(int K, const int32_t* q, const double* Ctab, const double* u, const double* E, double* r,
+                      double* sig_out, double* U)
+{
+    double ssum[6];
+    global_residual_mp8(K, q, Ctab, u, E, r, ssum, sig_out, U);
+}
+
 double ora_elastic_energy(int K, const int32_t* q, const double* Ctab, const double* u, const double* E)
 {
     double ssum[6], U;
