@@ -80,7 +80,13 @@ typedef struct {
                                still gives at least 1024 work-groups (2 rather than 1; 1 if none
                                does): shallower tiles recompute more halo voxels but fill the GPU
                                on small lattices.  Other values: HMC_EINVAL. */
-    int32_t reserved0;      /* must be 0 */
+    int32_t material_points;/* material points of the global solve: 0 or 1, one per site at the
+                               centre of its voxel (mesh = lattice, the default); 8, two per
+                               direction in background cells of 2 x 2 x 2 sites (the paper's MPM
+                               arrangement, Appendix; mesh of (K/2)^3 nodes, K >= 4, single
+                               lattices only, no adjoint and no displacement read-out).  Set it
+                               with hmc_set_material_points, which also sets glob_*.  Other
+                               values: HMC_EINVAL. */
     double J;               /* grain-boundary energy per unlike bond (MC units) */
     double kT;              /* Monte Carlo temperature T_mc (MC units), > 0 */
     double C11, C12, C44;   /* cubic stiffness in the crystal frame (GPa) */
@@ -122,6 +128,13 @@ typedef struct {
  * L = 4 max(C11+2C12, C11-C12, 2C44), mu = (C11-C12)/2 (2 sin(pi/K))^2 for the global grid
  * and mu = (C11-C12)/2 / (2h+1)^2 for the zone.  Returns HMC_EINVAL for bad arguments. */
 hmc_status hmc_default_params(hmc_params* p, int32_t K, int32_t neighbors, int32_t zone_h);
+
+/* Set p->material_points (0, 1 or 8) and the global relaxation constants glob_alpha, glob_beta
+ * and glob_alphaE for it, from p->K and p's stiffness: Polyak's heavy-ball values for the
+ * stability bound L = 4 (one point per voxel) or 8 (eight per cell) times the largest Mandel
+ * eigenvalue of the stiffness and the slowest shear wave of the mesh, 1/2 (C11 - C12)
+ * (2 sin(pi/n))^2 with n = K or K/2 mesh cells per edge.  HMC_EINVAL for other counts. */
+hmc_status hmc_set_material_points(hmc_params* p, int32_t n);
 
 /* Bytes of device workspace hmc_create needs for these parameters and Q grains
  * (0 if the parameters are invalid). */

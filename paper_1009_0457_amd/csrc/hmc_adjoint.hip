@@ -586,6 +586,7 @@ hmc_status load_ckpt(hmc_ctx c, char* base, const AdjLayout& L, int j, float* u_
 hmc_status check_adj(hmc_ctx c, int n_steps, int k, void* ws, size_t bytes, AdjLayout* L)
 {
     if (c->is_batch || c->n_rep != 1) return afail(c, HMC_ESTATE, "the adjoint acts on a single lattice");
+    if (c->p.material_points == 8) return afail(c, HMC_ESTATE, "the adjoint covers one material point per voxel");
     if (!c->elastic_buffers) return afail(c, HMC_ESTATE, "elastic term disabled (lambda_el == 0)");
     if (n_steps < 1 || k < 1) return afail(c, HMC_EINVAL, "need n_steps >= 1 and ckpt_every >= 1");
     if (!ws || ((uintptr_t)ws % 256) != 0) return afail(c, HMC_EINVAL, "adjoint workspace must be 256-byte aligned");

@@ -36,7 +36,7 @@ hmc_status check_common(const hmc_params* p)
     if (p->refresh_tile_z != 0 && p->refresh_tile_z != 1 && p->refresh_tile_z != 2 && p->refresh_tile_z != 4 &&
         p->refresh_tile_z != 8 && p->refresh_tile_z != 16 && p->refresh_tile_z != 32)
         return HMC_EINVAL;
-    if (p->reserved0 != 0) return HMC_EINVAL;
+    if (p->material_points != 0 && p->material_points != 1 && p->material_points != 8) return HMC_EINVAL;
     if (p->zone_steps < 0 || p->refresh_steps < 0 || p->cold_steps < 0 || p->refresh_every < 1) return HMC_EINVAL;
     const double vals[] = {p->J, p->kT, p->C11, p->C12, p->C44, p->lambda_el, p->zone_alpha, p->zone_beta,
                            p->glob_alpha, p->glob_beta, p->glob_alphaE};
@@ -69,6 +69,7 @@ hmc_status check_replica(const hmc_params* p, const hmc_replica* r)
     if (!(r->kT > 0)) return HMC_EINVAL;
     if (!load_in_range(r->sigma_MPa)) return HMC_EINVAL;
     if (r->lambda_el != 0.0 && r->K < 2 * p->zone_h + 2) return HMC_ESHAPE;
+    if (p->material_points == 8 && r->K < 4) return HMC_ESHAPE;
     return HMC_OK;
 }
 
@@ -355,6 +356,24 @@ bool elastic_on(const hmc_ctx c) { return c->elastic_buffers && c->any_elastic()
 // ------------------------------------------------------------------------------------
 hmc_status refresh(hmc_ctx c, int n_steps, bool cold)
 {
+    if (c->p.material_points == 8) {
+        // nodes and velocities in place in the first displacement buffer, corner forces in
+        // the second
+        if (cold) {
+            HMC_TRY(c, launch_fill_f32(c->d.u[0], 0.f, 3 * c->total_sites, c->stream), "refresh: clear u");
+            HMC_TRY(c, launch_reuss(c), "refresh: uniform-stress start");
+        } else {
+            HMC_TRY(c, launch_zero_wE(c), "refresh: clear wE");
+        }
+        HMC_TRY(c, launch_fill_f32(c->d.w, 0.f, 3 * c->total_sites, c->stream), "refresh: clear w");
+        c->cur_u = 0;
+        HMC_TRY(c, launch_mp8_steps(c, n_steps), "refresh: explicit steps (8 points per cell)");
+        HMC_TRY(c, launch_mp8_final(c, true), "refresh: point stresses");
+        c->host_refresh_steps += n_steps;
+        c->have_state = true;
+        c->have_stress = true;
+        return HMC_OK;
+    }
     if (cold) {
         HMC_TRY(c, launch_fill_f32(c->d.u[0], 0.f, 3 * c->total_sites, c->stream), "refresh: clear u");
         HMC_TRY(c, launch_fill_f32(c->d.w, 0.f, 3 * c->total_sites, c->stream), "refresh: clear w");
@@ -651,7 +670,10 @@ hmc_status energy_of(hmc_ctx c, int rep, int64_t* unlike, double* U)
     HMC_TRY(c, hipMemcpyAsync(&slots, c->d.bonds, sizeof slots, hipMemcpyDeviceToHost, c->stream), "energy");
     double u = 0.0;
     if (c->elastic_buffers && c->have_state && c->have_orient) {
-        HMC_TRY(c, launch_global_final(c, false), "energy");
+        if (c->p.material_points == 8)
+            HMC_TRY(c, launch_mp8_final(c, false), "energy");
+        else
+            HMC_TRY(c, launch_global_final(c, false), "energy");
         HMC_TRY(c, hipMemcpyAsync(&u, c->d.state + (int64_t)rep * kStateDoubles + kU, sizeof u, hipMemcpyDeviceToHost,
                                   c->stream),
                 "energy");
@@ -790,6 +812,19 @@ hmc_status hmc_default_params(hmc_params* p, int32_t K, int32_t neighbors, int32
     return HMC_OK;
 }
 
+hmc_status hmc_set_material_points(hmc_params* p, int32_t n)
+{
+    if (!p || (n != 0 && n != 1 && n != 8) || p->K < 2) return HMC_EINVAL;
+    p->material_points = n;
+    hmc_replica r;
+    const hmc_status st = hmc_default_replica(&r, p, p->K, 1);
+    if (st != HMC_OK) return st;
+    p->glob_alpha = r.glob_alpha;
+    p->glob_beta = r.glob_beta;
+    p->glob_alphaE = r.glob_alphaE;
+    return HMC_OK;
+}
+
 hmc_status hmc_default_replica(hmc_replica* r, const hmc_params* common, int32_t K, int32_t Q)
 {
     if (!r || !common || K < 2) return HMC_EINVAL;
@@ -802,8 +837,9 @@ hmc_status hmc_default_replica(hmc_replica* r, const hmc_params* common, int32_t
     const double E0 = gamma_s * l0 * l0 / ((double)K * K) / gamma_mc;
     r->lambda_el = 1.0e9 * std::pow(l0 / K, 3) / (2.0 * E0);
     const double lam = std::fmax(common->C11 + 2 * common->C12, std::fmax(common->C11 - common->C12, 2 * common->C44));
-    const double L = 4.0 * lam, shear = 0.5 * (common->C11 - common->C12);
-    const double sK = 2.0 * std::sin(M_PI / K);
+    const bool mp8 = common->material_points == 8;
+    const double L = (mp8 ? 8.0 : 4.0) * lam, shear = 0.5 * (common->C11 - common->C12);
+    const double sK = 2.0 * std::sin(M_PI / (mp8 ? 0.5 * K : (double)K));
     const double sl = std::sqrt(L), sm = std::sqrt(shear * sK * sK);
     r->glob_alpha = 4.0 / ((sl + sm) * (sl + sm));
     r->glob_beta = ((sl - sm) / (sl + sm)) * ((sl - sm) / (sl + sm));
@@ -850,6 +886,8 @@ hmc_status hmc_batch_create(const hmc_params* common, int32_t n, const hmc_repli
     hmc_status st = check_common(common);
     if (st != HMC_OK) return create_fail(st, "invalid common parameters");
     if (n < 1 || n > kMaxReplicas || !reps) return create_fail(HMC_EINVAL, "replica count out of range");
+    if (common->material_points == 8)
+        return create_fail(HMC_EINVAL, "eight material points per cell: single lattices only");
     for (int i = 0; i < n; ++i) {
         st = check_replica(common, &reps[i]);
         if (st != HMC_OK) return create_fail(st, "invalid replica description");
@@ -1030,6 +1068,7 @@ hmc_status hmc_get_displacement(hmc_ctx c, float* out)
     c->err.clear();
     if (!out) return state_fail(c, HMC_EINVAL, "null output");
     if (!c->elastic_buffers || !c->have_state) return state_fail(c, HMC_ESTATE, "no elastic state");
+    if (c->p.material_points == 8) return state_fail(c, HMC_ESTATE, "displacements live on the coarse mesh");
     return copy_field(c, 0, 3, c->d.u[c->cur_u], out, nullptr, "get_displacement");
 }
 
@@ -1053,6 +1092,7 @@ hmc_status hmc_set_elastic_state(hmc_ctx c, const float* u_dev, const double E_h
     if (!u_dev || !E_host) return state_fail(c, HMC_EINVAL, "null argument");
     if (!c->elastic_buffers) return state_fail(c, HMC_ESTATE, "elastic term disabled (lambda_el == 0)");
     if (c->is_batch) return state_fail(c, HMC_ESTATE, "not available on batches");
+    if (c->p.material_points == 8) return state_fail(c, HMC_ESTATE, "displacements live on the coarse mesh");
     for (int I = 0; I < 6; ++I)
         if (!std::isfinite(E_host[I])) return state_fail(c, HMC_ENUMERIC, "non-finite strain");
     double st[12];

@@ -208,6 +208,10 @@ hipError_t seq_begin(hmc_ctx_s* c, hipStream_t s);
 hipError_t seq_step(hmc_ctx_s* c, hipStream_t s, int i, const float* uin, float* uout, double* E_record);
 hipError_t seq_end(hmc_ctx_s* c, hipStream_t s, int n);
 hipError_t launch_global_final(hmc_ctx_s* c, bool write_sigma);
+// 2 x 2 x 2 material points per background cell (hmc_mp8.hip): n explicit steps, the final
+// point stresses and stored energy.
+hipError_t launch_mp8_steps(hmc_ctx_s* c, int n_steps);
+hipError_t launch_mp8_final(hmc_ctx_s* c, bool write_sigma);
 hipError_t launch_zero_wE(hmc_ctx_s* c);
 hipError_t launch_unlike_bonds(hmc_ctx_s* c, int rep);
 hipError_t launch_texture(hmc_ctx_s* c, int rep, int nbins);

@@ -30,7 +30,7 @@ class hmc_params(C.Structure):
     _fields_ = [("K", C.c_int32), ("neighbors", C.c_int32), ("proposal", C.c_int32), ("zone_h", C.c_int32),
                 ("zone_steps", C.c_int32), ("refresh_every", C.c_int32), ("refresh_steps", C.c_int32),
                 ("cold_steps", C.c_int32), ("zone_variant", C.c_int32), ("zone_screen", C.c_int32),
-                ("refresh_tile_z", C.c_int32), ("reserved0", C.c_int32),
+                ("refresh_tile_z", C.c_int32), ("material_points", C.c_int32),
                 ("J", C.c_double), ("kT", C.c_double), ("C11", C.c_double), ("C12", C.c_double),
                 ("C44", C.c_double), ("lambda_el", C.c_double), ("zone_alpha", C.c_double),
                 ("zone_beta", C.c_double), ("glob_alpha", C.c_double), ("glob_beta", C.c_double),
@@ -97,6 +97,7 @@ _SIGS = [
     ("hmc_set_profiling", C.c_int, [C.c_void_p, C.c_int32]),
     ("hmc_get_kernel_times", C.c_int, [C.c_void_p, C.POINTER(hmc_kernel_times)]),
     ("hmc_set_graphs", C.c_int, [C.c_void_p, C.c_int32]),
+    ("hmc_set_material_points", C.c_int, [C.POINTER(hmc_params), C.c_int32]),
     ("hmc_default_replica", C.c_int, [C.POINTER(hmc_replica), C.POINTER(hmc_params), C.c_int32, C.c_int32]),
     ("hmc_batch_workspace_bytes", C.c_size_t, [C.POINTER(hmc_params), C.c_int32, C.POINTER(hmc_replica)]),
     ("hmc_batch_create", C.c_int, [C.POINTER(hmc_params), C.c_int32, C.POINTER(hmc_replica), C.c_void_p,
@@ -293,6 +294,11 @@ def hmc_get_kernel_times(ctx) -> dict:
 
 def hmc_set_graphs(ctx, enable):
     _check(lib().hmc_set_graphs(ctx, int(bool(enable))), ctx)
+
+
+def hmc_set_material_points(p: hmc_params, n: int) -> hmc_params:
+    _check(lib().hmc_set_material_points(C.byref(p), int(n)))
+    return p
 
 
 def hmc_default_replica(common: hmc_params, K, Q) -> hmc_replica:

@@ -88,7 +88,7 @@ def test_grain_table_derivatives_match_central_differences_of_the_oracle():
     ("neighbors", 8, H.HMC_EINVAL), ("zone_h", 4, H.HMC_EINVAL), ("kT", 0.0, H.HMC_EINVAL),
     ("kT", float("nan"), H.HMC_ENUMERIC), ("proposal", 2, H.HMC_EINVAL), ("refresh_every", 0, H.HMC_EINVAL),
     ("C44", -1.0, H.HMC_ENUMERIC), ("zone_variant", 4, H.HMC_EINVAL), ("zone_variant", -1, H.HMC_EINVAL),
-    ("refresh_tile_z", 3, H.HMC_EINVAL), ("refresh_tile_z", 64, H.HMC_EINVAL), ("reserved0", 1, H.HMC_EINVAL),
+    ("refresh_tile_z", 3, H.HMC_EINVAL), ("refresh_tile_z", 64, H.HMC_EINVAL), ("material_points", 3, H.HMC_EINVAL),
 ])
 def test_create_validates_before_touching_the_device(field, value, status):
     L = _lib_or_skip()
@@ -169,3 +169,33 @@ def test_null_context_calls_are_rejected():
     assert L.hmc_sweep(None, 1) == H.HMC_EINVAL
     assert L.hmc_set_load(None, None) == H.HMC_EINVAL
     assert isinstance(L.hmc_last_error(None), bytes)
+
+
+def test_material_points_constants_and_limits():
+    """hmc_set_material_points: Polyak constants for L = 8 x the largest Mandel eigenvalue and
+    the slowest shear wave of the (K/2)^3 mesh; invalid counts and batches are refused before
+    any device call."""
+    L = _lib_or_skip()
+    p = H.hmc_default_params(24, 26, 2)
+    a1, b1 = p.glob_alpha, p.glob_beta
+    H.hmc_set_material_points(p, 8)
+    lam = max(p.C11 + 2 * p.C12, p.C11 - p.C12, 2 * p.C44)
+    sl, sm = math.sqrt(8 * lam), math.sqrt(0.5 * (p.C11 - p.C12)) * 2 * math.sin(2 * math.pi / 24)
+    assert p.material_points == 8
+    assert p.glob_alpha == pytest.approx(4 / (sl + sm) ** 2, rel=1e-12)
+    assert p.glob_beta == pytest.approx(((sl - sm) / (sl + sm)) ** 2, rel=1e-12)
+    assert p.glob_alphaE == p.glob_alpha
+    H.hmc_set_material_points(p, 1)
+    assert (p.glob_alpha, p.glob_beta) == pytest.approx((a1, b1), rel=1e-14)
+    assert L.hmc_set_material_points(C.byref(p), 4) == H.HMC_EINVAL
+    q = H.hmc_default_params(2, 26, 0)
+    q.material_points = 8
+    assert L.hmc_workspace_bytes(C.byref(q), 4) == 0           # K >= 4 with 8 points per cell
+    p.material_points = 8
+    reps = (H.hmc_replica * 1)()
+    reps[0] = H.hmc_default_replica(p, 24, 8)
+    ctx = C.c_void_p()
+    buf = (C.c_char * 512)()
+    aligned = (C.addressof(buf) + 255) // 256 * 256
+    assert L.hmc_batch_create(C.byref(p), 1, reps, C.c_void_p(aligned), 16, None, C.byref(ctx)) == H.HMC_EINVAL
+    assert b"single lattices" in L.hmc_last_error(None)

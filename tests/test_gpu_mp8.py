@@ -1,0 +1,138 @@
+"""GPU parity of the global solve with 2 x 2 x 2 material points per background cell (the
+paper's MPM arrangement, Appendix) against the oracle's FP64 variant, through the C ABI:
+point stress fields, macroscopic strain and stored energy after cold and warm refreshes on
+lattices whose mesh edge is even and odd; the polycrystal modulus of Sec. 5 at 24^3; sweeps on
+the resulting stress field; and the calls the variant refuses."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1009_0457_amd import hmc as H
+from paper_1009_0457_amd.synth import voronoi_polycrystal
+from test_gpu_parity import compare_pass, oracle_params, zone_tol
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def lattice(K, micro, C=None, **over):
+    p = H.hmc_default_params(K, 26, 1)
+    if C is not None:
+        p.C11, p.C12, p.C44 = C
+    for k, v in over.items():
+        setattr(p, k, v)
+    H.hmc_set_material_points(p, 8)
+    lat = H.Lattice(p, micro.Q)
+    lat.set_orientations(micro.euler)
+    lat.set_spins(micro.spins)
+    return p, lat
+
+
+@pytest.mark.parametrize("K,ng,steps", [(8, 5, 150), (16, 20, 300), (18, 25, 250)])
+def test_refresh_matches_oracle(K, ng, steps):
+    say(f"[mp8 refresh] K={K} grains={ng} steps={steps}")
+    micro = voronoi_polycrystal(K, ng, 40 + K)
+    p, lat = lattice(K, micro)
+    sig_mpa = np.array([120.0, -40.0, 80.0, 30.0, -20.0, 10.0])
+    lat.set_load(sig_mpa)
+    lat.stress_refresh(steps, True)
+    got = lat.get_stress().cpu().numpy().astype(np.float64)
+    E_got = lat.macro_strain()
+    _, U_got = lat.energy()
+    Ct, St, _ = O.tables(micro.euler, p.C11, p.C12, p.C44)
+    u, E, sig, info = O.global_solve_mp8(K, micro.spins, Ct, St, sig_mpa * 1e-3, steps, True, p.glob_alpha,
+                                         p.glob_beta, p.glob_alphaE)
+    rel = np.linalg.norm(got - sig) / np.linalg.norm(sig)
+    say(f"    stress rel err {rel:.2e}, E err {np.abs(E_got - E).max() / np.abs(E).max():.2e}, "
+        f"U {U_got:.6e} vs {info['U']:.6e}, oracle residual {info['res_u']:.1e}")
+    assert rel < 1e-4
+    assert np.abs(E_got - E).max() < 1e-5 * np.abs(E).max()
+    assert abs(U_got - info["U"]) < 1e-5 * abs(info["U"])
+    # a warm refresh after a load change continues from the same state on both sides
+    sig2 = np.array([60.0, 90.0, -30.0, 0.0, 25.0, -15.0])
+    lat.set_load(sig2)
+    lat.stress_refresh(steps // 2, False)
+    got2 = lat.get_stress().cpu().numpy().astype(np.float64)
+    _, E2, sig_o2, _ = O.global_solve_mp8(K, micro.spins, Ct, St, sig2 * 1e-3, steps // 2, False, p.glob_alpha,
+                                          p.glob_beta, p.glob_alphaE, u=u, E=E)
+    rel2 = np.linalg.norm(got2 - sig_o2) / np.linalg.norm(sig_o2)
+    say(f"    warm: stress rel err {rel2:.2e}")
+    assert rel2 < 1e-4
+    assert np.abs(lat.macro_strain() - E2).max() < 1e-5 * np.abs(E2).max()
+    lat.close()
+
+
+def test_polycrystal_modulus_matches_oracle(paper):
+    """Sec. 5 (paper constants, 300 grains at 24^3): the apparent modulus along x, y, z."""
+    C = (paper["C11_paper"], paper["C12_paper"], paper["C44_paper"])
+    K = 24
+    micro = voronoi_polycrystal(K, 300, 12)
+    p, lat = lattice(K, micro, C)
+    Ct, St, _ = O.tables(micro.euler, *C)
+    Eg, Eo = [], []
+    for ax in range(3):
+        s = np.zeros(6)
+        s[ax] = 100.0
+        lat.set_load(s)
+        lat.stress_refresh(800, True)
+        Eg.append(0.1 / lat.macro_strain()[ax])
+        _, E, _, _ = O.global_solve_mp8(K, micro.spins, Ct, St, s * 1e-3, 800, True, p.glob_alpha, p.glob_beta,
+                                        p.glob_alphaE)
+        Eo.append(0.1 / E[ax])
+    say(f"[mp8 modulus] GPU {np.round(Eg, 3)} GPa, oracle {np.round(Eo, 3)} GPa, mean {np.mean(Eg):.2f}")
+    assert np.abs(np.array(Eg) / np.array(Eo) - 1).max() < 1e-5
+    lat.close()
+
+
+def test_sweeps_on_the_eight_point_stress_field():
+    """Sweeps with the zone solve read the point stresses of the 8-point refresh; warm
+    refreshes every second sweep; the result is deterministic and the decisions are the
+    oracle's for one colour pass replayed from the same state."""
+    K = 16
+    micro = voronoi_polycrystal(K, 12, 7)
+    outs = []
+    for _ in range(2):
+        p, lat = lattice(K, micro, refresh_every=2, refresh_steps=60, cold_steps=300, kT=0.6)
+        lat.set_load([150.0, 0, 0, 0, 0, 0])
+        lat.stress_refresh(-1, True)
+        lat.sweep(4)
+        st = lat.stats()
+        outs.append(lat.get_spins().cpu().numpy())
+        assert st["zone_solves"] > 0 and st["refresh_steps"] == 300 + 2 * 60
+        sig = lat.get_stress().cpu().numpy().astype(np.float64)
+        snap = outs[-1].copy()
+        s_idx = lat.sweep_index()
+        rec = lat.colour_pass(0, records=True)
+        Ct, St, _ = O.tables(micro.euler, p.C11, p.C12, p.C44)
+        prm = oracle_params(p, micro.Q, True, (0.15, 0, 0, 0, 0, 0))
+        ref = O.colour_pass(prm, snap.copy(), Ct, St, sig, s_idx, 0, want_records=True)
+        sites = np.nonzero(O.colour_of(K, 26) == 0)[0]
+        tol, _ = zone_tol(sig[:, sites], St, snap[sites], ref["dPi"][sites])
+        n, k, w = compare_pass(rec, ref[sites], sites, p, tol, "8-point stress field, colour 0")
+        say(f"    lockstep colour 0: {n} solves, flagged {k}, worst err/tol {w:.3f}")
+        assert n > 20
+        lat.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_refused_calls():
+    K = 8
+    micro = voronoi_polycrystal(K, 4, 3)
+    p, lat = lattice(K, micro)
+    lat.set_load([100.0, 0, 0, 0, 0, 0])
+    lat.stress_refresh(50, True)
+    with pytest.raises(H.HmcError, match="coarse mesh"):
+        lat.get_displacement()
+    with pytest.raises(H.HmcError, match="one material point"):
+        lat.elastic_forward(10, 5)
+    lat.close()
