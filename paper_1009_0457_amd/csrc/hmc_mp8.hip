@@ -13,8 +13,10 @@
 // Hessian peaks at 8 here, against 4 for one point per voxel).
 //
 // One step is three launches on the context's stream: a cell pass (one thread per cell: gather
-// the 8 corner displacements, the 8 points' strains and stresses, the cell's 24 corner forces
-// written to a cell-major force array, and per-block sums of the point stresses), a node pass
+// the 8 corner displacements, their differences along the cell's 12 edges, the 8 points'
+// strains as bilinear interpolations of those and their stresses, the transpose back onto the
+// edges and the cell's 24 corner forces written to a cell-major force array, and per-block
+// sums of the point stresses), a node pass
 // (one thread per node: the forces of its 8 cells, the heavy-ball update of u and w in place)
 // and a one-block fold of the stress sums into E.  Single-lattice contexts only.  Node fields
 // occupy the first (K/2)^3 entries of each displacement plane; the corner forces use the second
@@ -25,17 +27,9 @@ namespace hmc {
 
 namespace {
 
-// d N_c / d x_dir at material point p of a cell (c, p: bits x, y, z), times 8.
-__host__ __device__ constexpr float mp_w8(int c, int p, int dir)
-{
-    float f = 1.0f;
-    for (int d = 0; d < 3; ++d) {
-        const float xc = ((c >> d) & 1) ? 1.0f : -1.0f;
-        const float xp = ((p >> d) & 1) ? 0.5f : -0.5f;
-        f *= (d == dir) ? xc : (1.0f + xc * xp);
-    }
-    return f;
-}
+// Weight of the edge at bit b (0 or 1) of a cell direction for the point at sub-position p
+// there: the trilinear shape functions' factor 1 +- xi_p with xi_p = +-1/2.
+__host__ __device__ constexpr float mp_w(int b, int p) { return b == p ? 1.5f : 0.5f; }
 
 struct Mp8Args {
     const int16_t* spins;
@@ -70,49 +64,88 @@ __global__ __launch_bounds__(256) void k_mp8_cells(Mp8Args a)
 #pragma unroll
             for (int j = 0; j < 3; ++j) uc[c][j] = a.u[(int64_t)j * a.plane + node];
         }
-        float f[8][3];
+        // Edge differences of the cell along each direction: D[d][e][j] for the 4 edges e
+        // parallel to d (e = the other two bits, lower direction first).  The gradient at a
+        // point is their bilinear interpolation, d/dx = 1/8 sum_e w w D (cell edge 2 sites).
+        float D[3][4][3];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) f[c][0] = f[c][1] = f[c][2] = 0.f;
+        for (int e = 0; e < 4; ++e) {
+            const int b1 = e & 1, b2 = e >> 1;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                D[0][e][j] = uc[1 + 2 * b1 + 4 * b2][j] - uc[0 + 2 * b1 + 4 * b2][j];
+                D[1][e][j] = uc[b1 + 2 + 4 * b2][j] - uc[b1 + 0 + 4 * b2][j];
+                D[2][e][j] = uc[b1 + 2 * b2 + 4][j] - uc[b1 + 2 * b2 + 0][j];
+            }
+        }
+        // per-edge force sums, the transpose: G[d][e][j] = 1/8 sum_p w w t_d(p)[j]
+        float G[3][4][3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) G[d][e][0] = G[d][e][1] = G[d][e][2] = 0.f;
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
-            const int64_t v = (int64_t)(2 * X + (p & 1)) +
-                              (int64_t)K * ((2 * Y + ((p >> 1) & 1)) + (int64_t)K * (2 * Z + ((p >> 2) & 1)));
-            float g[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};   // g[j][i] = d u_j / d x_i
+            const int px = p & 1, py = (p >> 1) & 1, pz = (p >> 2) & 1;
+            const int64_t v = (int64_t)(2 * X + px) + (int64_t)K * ((2 * Y + py) + (int64_t)K * (2 * Z + pz));
+            // point sub-positions along the two other directions of each d, lower first
+            const int q1[3] = {py, px, px}, q2[3] = {pz, pz, py};
+            float g[3][3];   // g[d][j] = d u_j / d x_d
 #pragma unroll
-            for (int c = 0; c < 8; ++c)
+            for (int d = 0; d < 3; ++d)
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const float w = 0.125f * mp_w8(c, p, i);
+                for (int j = 0; j < 3; ++j) {
+                    float gs = 0.f;
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) g[j][i] += w * uc[c][j];
+                    for (int e = 0; e < 4; ++e) gs += (0.125f * mp_w(e & 1, q1[d]) * mp_w(e >> 1, q2[d])) * D[d][e][j];
+                    g[d][j] = gs;
                 }
-            float e[6], s[6];
-            e[0] = g[0][0] + E[0];
-            e[1] = g[1][1] + E[1];
-            e[2] = g[2][2] + E[2];
-            e[3] = (g[1][2] + g[2][1]) + E[3];
-            e[4] = (g[0][2] + g[2][0]) + E[4];
-            e[5] = (g[0][1] + g[1][0]) + E[5];
-            symv21(a.Ctab + (int64_t)a.spins[v] * kTab, e, s);
+            float e6[6], s[6];
+            e6[0] = g[0][0] + E[0];
+            e6[1] = g[1][1] + E[1];
+            e6[2] = g[2][2] + E[2];
+            e6[3] = (g[2][1] + g[1][2]) + E[3];
+            e6[4] = (g[2][0] + g[0][2]) + E[4];
+            e6[5] = (g[1][0] + g[0][1]) + E[5];
+            symv21(a.Ctab + (int64_t)a.spins[v] * kTab, e6, s);
             if (FINAL) {
-                double d = 0.0;
+                double dd = 0.0;
 #pragma unroll
-                for (int I = 0; I < 6; ++I) d += (double)s[I] * (double)e[I];
-                acc[0] += 0.5 * d;
+                for (int I = 0; I < 6; ++I) dd += (double)s[I] * (double)e6[I];
+                acc[0] += 0.5 * dd;
                 if (a.sigma)
 #pragma unroll
                     for (int I = 0; I < 6; ++I) a.sigma[(int64_t)I * a.plane + v] = s[I];
             } else {
 #pragma unroll
                 for (int I = 0; I < 6; ++I) acc[I] += (double)s[I];
+                // traction rows t_d = sigma e_d (Voigt: xx yy zz yz xz xy)
+                const float t[3][3] = {{s[0], s[5], s[4]}, {s[5], s[1], s[3]}, {s[4], s[3], s[2]}};
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    const float gx = 0.125f * mp_w8(c, p, 0), gy = 0.125f * mp_w8(c, p, 1),
-                                gz = 0.125f * mp_w8(c, p, 2);
-                    f[c][0] += gx * s[0] + gy * s[5] + gz * s[4];
-                    f[c][1] += gx * s[5] + gy * s[1] + gz * s[3];
-                    f[c][2] += gx * s[4] + gy * s[3] + gz * s[2];
-                }
+                for (int d = 0; d < 3; ++d)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float w = 0.125f * mp_w(e & 1, q1[d]) * mp_w(e >> 1, q2[d]);
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) G[d][e][j] += w * t[d][j];
+                    }
+            }
+        }
+        // corner forces: + G at the upper end of every edge, - G at the lower end
+        float f[8][3];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) f[c][0] = f[c][1] = f[c][2] = 0.f;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int b1 = e & 1, b2 = e >> 1;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                f[1 + 2 * b1 + 4 * b2][j] += G[0][e][j];
+                f[0 + 2 * b1 + 4 * b2][j] -= G[0][e][j];
+                f[b1 + 2 + 4 * b2][j] += G[1][e][j];
+                f[b1 + 0 + 4 * b2][j] -= G[1][e][j];
+                f[b1 + 2 * b2 + 4][j] += G[2][e][j];
+                f[b1 + 2 * b2 + 0][j] -= G[2][e][j];
             }
         }
         if (!FINAL)

@@ -551,8 +551,8 @@ __global__ __launch_bounds__(256, 2) void k_zone_col(ZoneArgs a)
 }
 
 // ------------------------------------------------------------------------------------
-// Lane-shift variant (1 <= h <= 2).  Each trial occupies LT = (2h+2)(2h+1) consecutive lanes
-// of one wavefront, laid out as lane l = x + (2h+2) y over node columns x in [0, 2h+2),
+// Lane-shift variant (1 <= h <= 3).  Each trial occupies LT = (2h+2)(2h+1) consecutive lanes
+// (12, 30 and 56) of one wavefront, laid out as lane l = x + (2h+2) y over node columns x in [0, 2h+2),
 // y in [0, 2h+1); a wavefront holds 64 / LT trials and never splits one.  Lane (x, y) owns
 // node column (x, y) in registers and, for x < 2h+1, the voxel column (x, y); the top row
 // of node columns (y = 2h+1) is split into (column, component) items held by the trial's
