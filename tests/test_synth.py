@@ -1,5 +1,8 @@
 """CPU checks of the seeded input generators (they hold no arithmetic of the method)."""
+import os
+
 import numpy as np
+import pytest
 
 from paper_1009_0457_amd.synth import batched_configs, refined_polycrystal, voronoi_polycrystal
 
@@ -39,3 +42,28 @@ def test_batched_configs_follow_the_ensemble_recipe():
         assert abs(np.linalg.norm(n) - 1.0) < 1e-12
         assert np.allclose(c.sigma_MPa[:3], load * n ** 2)
     assert [c.philox_seed for c in cfgs] == list(range(1, 65))
+
+
+def test_texture_run_inputs():
+    from paper_1009_0457_amd.synth import texture_run_inputs, z_rotation_euler
+    runs = texture_run_inputs(6, 3, 91, 5)
+    assert len(runs) == 3
+    e, q = runs[1]
+    assert np.array_equal(e, z_rotation_euler(91))
+    assert np.allclose(np.degrees(e[:, 0]), np.arange(91)) and not e[:, 1:].any()
+    assert q.dtype == np.int32 and q.min() >= 0 and q.max() < 91 and q.size == 216
+    assert not np.array_equal(runs[0][1], runs[1][1])
+    with pytest.raises(ValueError):
+        texture_run_inputs(6, 1, 10, 5, euler=np.zeros((9, 3)))
+
+
+def test_bench_refuses_several_gpus():
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert r.returncode == 2
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert out["n_gpus"] == 2 and "one GPU" in out["error"]
