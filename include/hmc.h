@@ -83,8 +83,8 @@ typedef struct {
     int32_t material_points;/* material points of the global solve: 0 or 1, one per site at the
                                centre of its voxel (mesh = lattice, the default); 8, two per
                                direction in background cells of 2 x 2 x 2 sites (the paper's MPM
-                               arrangement, Appendix; mesh of (K/2)^3 nodes, K >= 4, single
-                               lattices only, no adjoint and no displacement read-out).  Set it
+                               arrangement, Appendix; mesh of (K/2)^3 nodes, K >= 4; no adjoint
+                               and no displacement read-out).  Set it
                                with hmc_set_material_points, which also sets glob_*.  Other
                                values: HMC_EINVAL. */
     double J;               /* grain-boundary energy per unlike bond (MC units) */

@@ -886,8 +886,6 @@ hmc_status hmc_batch_create(const hmc_params* common, int32_t n, const hmc_repli
     hmc_status st = check_common(common);
     if (st != HMC_OK) return create_fail(st, "invalid common parameters");
     if (n < 1 || n > kMaxReplicas || !reps) return create_fail(HMC_EINVAL, "replica count out of range");
-    if (common->material_points == 8)
-        return create_fail(HMC_EINVAL, "eight material points per cell: single lattices only");
     for (int i = 0; i < n; ++i) {
         st = check_replica(common, &reps[i]);
         if (st != HMC_OK) return create_fail(st, "invalid replica description");

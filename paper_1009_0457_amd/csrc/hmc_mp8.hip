@@ -18,9 +18,9 @@
 // edges and the cell's 24 corner forces written to a cell-major force array, and per-block
 // sums of the point stresses), a node pass
 // (one thread per node: the forces of its 8 cells, the heavy-ball update of u and w in place)
-// and a one-block fold of the stress sums into E.  Single-lattice contexts only.  Node fields
-// occupy the first (K/2)^3 entries of each displacement plane; the corner forces use the second
-// displacement buffer, which holds exactly 24 floats per cell.
+// and a one-block fold of the stress sums into E, per replica.  A replica's node fields occupy
+// the first (K/2)^3 entries of its slice of each displacement plane; its corner forces use its
+// slice of the second displacement buffer, which holds exactly 24 floats per cell.
 #include "hmc_device.h"
 
 namespace hmc {
@@ -35,7 +35,8 @@ struct Mp8Args {
     const int16_t* spins;
     const float* Ctab;
     const float* u;        // 3 planes of `plane` floats, nodes first
-    float* F;              // 24 x n_cells corner forces (cell-major per component)
+    float* F;              // 24 x n_cells corner forces: row k of the cells at plane k / 8,
+                           // offset (k % 8) n_cells (a replica's slice of 3 planes of `plane`)
     float* sigma;          // final pass: 6 planes of point stresses (or null)
     double* partials;
     const double* state;
@@ -152,7 +153,8 @@ __global__ __launch_bounds__(256) void k_mp8_cells(Mp8Args a)
 #pragma unroll
             for (int c = 0; c < 8; ++c)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) a.F[(int64_t)(3 * c + j) * nc + cell] = f[c][j];
+                for (int j = 0; j < 3; ++j)
+                    a.F[(int64_t)((3 * c + j) >> 3) * a.plane + (int64_t)((3 * c + j) & 7) * nc + cell] = f[c][j];
     }
     if (FINAL)
         block_sum_to<1>(a.partials, acc);
@@ -175,7 +177,8 @@ __global__ __launch_bounds__(256) void k_mp8_nodes(const float* __restrict__ F, 
             const int64_t cell = (int64_t)((c & 1) ? Xm : X) +
                                  (int64_t)Kc * (((c >> 1) & 1 ? Ym : Y) + (int64_t)Kc * ((c >> 2) & 1 ? Zm : Z));
 #pragma unroll
-            for (int j = 0; j < 3; ++j) r[j] -= F[(int64_t)(3 * c + j) * nc + cell];
+            for (int j = 0; j < 3; ++j)
+                r[j] -= F[(int64_t)((3 * c + j) >> 3) * plane + (int64_t)((3 * c + j) & 7) * nc + cell];
         }
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
@@ -188,9 +191,10 @@ __global__ __launch_bounds__(256) void k_mp8_nodes(const float* __restrict__ F, 
 }
 
 // One block: fixed-order sum of the cell pass's stress sums, then the macroscopic update.
-__global__ __launch_bounds__(256) void k_mp8_E(double* state, const double* partials, int nblocks, const RepDev* reps)
+__global__ __launch_bounds__(256) void k_mp8_E(double* state, const double* partials, int nblocks, const RepDev* reps,
+                                               int rep)
 {
-    const RepDev R = reps[0];
+    const RepDev R = reps[rep];
     double s[6] = {0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblocks; b += 256)
 #pragma unroll
@@ -213,42 +217,49 @@ __global__ __launch_bounds__(256) void k_mp8_U(double* state, const double* part
     if (threadIdx.x == 0) state[kU] = tot;
 }
 
-int mp8_blocks(const hmc_ctx_s* c)
+int mp8_blocks(const RepDev& R)
 {
-    const int64_t Kc = c->reps[0].K / 2, nc = Kc * Kc * Kc;
+    const int64_t Kc = R.K / 2, nc = Kc * Kc * Kc;
     const int64_t b = (nc + 255) / 256;
     return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
 }
 
-Mp8Args mp8_args(hmc_ctx_s* c)
+// Replica r's slices: its spins, grain tables, node fields, force rows and state.
+Mp8Args mp8_args(hmc_ctx_s* c, int r)
 {
+    const RepDev& R = c->reps[r];
     Mp8Args a;
-    a.spins = c->d.spins;
-    a.Ctab = c->d.Ctab;
-    a.u = c->d.u[0];
-    a.F = c->d.u[1];
+    a.spins = c->d.spins + R.site_off;
+    a.Ctab = c->d.Ctab + R.grain_off * kTab;
+    a.u = c->d.u[0] + R.site_off;
+    a.F = c->d.u[1] + R.site_off;
     a.sigma = nullptr;
     a.partials = c->d.partials;
-    a.state = c->d.state;
-    a.K = c->reps[0].K;
+    a.state = c->d.state + (int64_t)r * kStateDoubles;
+    a.K = R.K;
     a.plane = c->total_sites;
     return a;
 }
 
 }  // namespace
 
+// Replicas of a batch run one after another within each step (their cell passes share the
+// partial-sum buffer, which each replica's fold reads before the next replica's pass).
 hipError_t launch_mp8_steps(hmc_ctx_s* c, int n_steps)
 {
-    const RepDev& R = c->reps[0];
-    const Mp8Args a = mp8_args(c);
-    const int nb = mp8_blocks(c);
     for (int s = 0; s < n_steps; ++s) {
         const int tok = prof_begin(c, kProfRefreshStep);
-        hipLaunchKernelGGL(k_mp8_cells<false>, dim3(nb), dim3(256), 0, c->stream, a);
-        hipLaunchKernelGGL(k_mp8_nodes, dim3(nb), dim3(256), 0, c->stream, (const float*)c->d.u[1], c->d.u[0], c->d.w,
-                           R.K, c->total_sites, R.glob_alpha, R.glob_beta);
-        hipLaunchKernelGGL(k_mp8_E, dim3(1), dim3(256), 0, c->stream, c->d.state, (const double*)c->d.partials, nb,
-                           (const RepDev*)c->d.reps);
+        for (int r = 0; r < c->n_rep; ++r) {
+            const RepDev& R = c->reps[r];
+            const Mp8Args a = mp8_args(c, r);
+            const int nb = mp8_blocks(R);
+            hipLaunchKernelGGL(k_mp8_cells<false>, dim3(nb), dim3(256), 0, c->stream, a);
+            hipLaunchKernelGGL(k_mp8_nodes, dim3(nb), dim3(256), 0, c->stream, (const float*)a.F,
+                               c->d.u[0] + R.site_off, c->d.w + R.site_off, R.K, c->total_sites, R.glob_alpha,
+                               R.glob_beta);
+            hipLaunchKernelGGL(k_mp8_E, dim3(1), dim3(256), 0, c->stream, c->d.state + (int64_t)r * kStateDoubles,
+                               (const double*)c->d.partials, nb, (const RepDev*)c->d.reps, r);
+        }
         prof_end(c, tok);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -258,12 +269,15 @@ hipError_t launch_mp8_steps(hmc_ctx_s* c, int n_steps)
 
 hipError_t launch_mp8_final(hmc_ctx_s* c, bool write_sigma)
 {
-    Mp8Args a = mp8_args(c);
-    a.sigma = write_sigma ? c->d.sigma : nullptr;
-    const int nb = mp8_blocks(c);
     const int tok = prof_begin(c, kProfRefreshOther);
-    hipLaunchKernelGGL(k_mp8_cells<true>, dim3(nb), dim3(256), 0, c->stream, a);
-    hipLaunchKernelGGL(k_mp8_U, dim3(1), dim3(256), 0, c->stream, c->d.state, (const double*)c->d.partials, nb);
+    for (int r = 0; r < c->n_rep; ++r) {
+        Mp8Args a = mp8_args(c, r);
+        a.sigma = write_sigma ? c->d.sigma + c->reps[r].site_off : nullptr;
+        const int nb = mp8_blocks(c->reps[r]);
+        hipLaunchKernelGGL(k_mp8_cells<true>, dim3(nb), dim3(256), 0, c->stream, a);
+        hipLaunchKernelGGL(k_mp8_U, dim3(1), dim3(256), 0, c->stream, c->d.state + (int64_t)r * kStateDoubles,
+                           (const double*)c->d.partials, nb);
+    }
     prof_end(c, tok);
     return hipGetLastError();
 }

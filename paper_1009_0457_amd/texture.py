@@ -126,7 +126,7 @@ def mean_abs_deviation(phi_deg, fractions):
 def texture_run(K=100, runs=10, *, Q=91, coarsen_steps=100, kT=2.6, load_MPa=30.0, substeps=75,
                 refresh_steps=200, neighbors=26, zone_h=2, zone_steps=200, lambda_scale=1.0, screen=True,
                 record_every=5, C=(250.8, 150.0, 123.5), seed=300, philox_seed=400, profile=False,
-                tile_z=0, euler=None, device="cuda:0"):
+                tile_z=0, euler=None, material_points=1, device="cuda:0"):
     """Sec. 7's texture experiment as one fused batch of ``runs`` replicas on the library.
 
     Every site starts as an independent random choice among Q orientations (``euler``, Q Bunge
@@ -136,6 +136,8 @@ def texture_run(K=100, runs=10, *, Q=91, coarsen_steps=100, kT=2.6, load_MPa=30.
     quasi-static state (a cold start of cold_steps the first time, then warm refreshes of
     refresh_steps) and one sweep follows.  ``lambda_scale`` multiplies the elastic-to-MC
     energy scale of every replica; 0 runs the same schedule without any load (the control).
+    ``material_points`` = 8 relaxes the stress field with 2 x 2 x 2 material points per
+    background cell (the paper's MPM arrangement) instead of one per voxel.
 
     Returns a dict: t (sweeps since the end of coarsening, every record_every), fractions
     (len(t), runs, Q) volume fractions per orientation, the library's counters, the wall
@@ -153,6 +155,7 @@ def texture_run(K=100, runs=10, *, Q=91, coarsen_steps=100, kT=2.6, load_MPa=30.
     common.zone_screen = 1 if screen else 0
     common.C11, common.C12, common.C44 = C
     common.refresh_tile_z = tile_z          # 0: the library's automatic depth
+    common.material_points = material_points   # each replica's relaxation constants follow it
     reps = []
     for r in range(runs):
         rep = H.hmc_default_replica(common, K, Q)

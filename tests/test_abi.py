@@ -173,7 +173,7 @@ def test_null_context_calls_are_rejected():
 
 def test_material_points_constants_and_limits():
     """hmc_set_material_points: Polyak constants for L = 8 x the largest Mandel eigenvalue and
-    the slowest shear wave of the (K/2)^3 mesh; invalid counts and batches are refused before
+    the slowest shear wave of the (K/2)^3 mesh; invalid counts and lattices are refused before
     any device call."""
     L = _lib_or_skip()
     p = H.hmc_default_params(24, 26, 2)
@@ -191,11 +191,12 @@ def test_material_points_constants_and_limits():
     q = H.hmc_default_params(2, 26, 0)
     q.material_points = 8
     assert L.hmc_workspace_bytes(C.byref(q), 4) == 0           # K >= 4 with 8 points per cell
+    # replicas of a batch take the constants for their own K from hmc_default_replica
     p.material_points = 8
-    reps = (H.hmc_replica * 1)()
-    reps[0] = H.hmc_default_replica(p, 24, 8)
-    ctx = C.c_void_p()
-    buf = (C.c_char * 512)()
-    aligned = (C.addressof(buf) + 255) // 256 * 256
-    assert L.hmc_batch_create(C.byref(p), 1, reps, C.c_void_p(aligned), 16, None, C.byref(ctx)) == H.HMC_EINVAL
-    assert b"single lattices" in L.hmc_last_error(None)
+    r = H.hmc_default_replica(p, 40, 8)
+    sl, sm = math.sqrt(8 * lam), math.sqrt(0.5 * (p.C11 - p.C12)) * 2 * math.sin(2 * math.pi / 40)
+    assert r.glob_alpha == pytest.approx(4 / (sl + sm) ** 2, rel=1e-12)
+    reps = (H.hmc_replica * 2)()
+    reps[0], reps[1] = r, H.hmc_default_replica(p, 2, 8)
+    assert L.hmc_batch_workspace_bytes(C.byref(p), 1, reps) > 0
+    assert L.hmc_batch_workspace_bytes(C.byref(p), 2, reps) == 0     # K = 2 is too small for it
