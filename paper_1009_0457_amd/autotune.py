@@ -13,8 +13,6 @@ per explicit step, so they do not depend on how many trials happened to be real 
 """
 from __future__ import annotations
 
-from . import hmc as H
-
 TILE_DEPTHS = (1, 2, 4, 8, 16, 32)
 
 
