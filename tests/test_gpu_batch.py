@@ -161,15 +161,18 @@ def test_batch_zero_load_matches_oracle():
     b.close()
 
 
-def test_graph_replays_match_eager_sweeps():
+@pytest.mark.parametrize("material_points", [1, 8])
+def test_graph_replays_match_eager_sweeps(material_points):
     """A single lattice on its own stream: every graph replay (sweeps with and without the
-    refresh) equals the eager sweep, with eager work and synchronisation in between."""
+    refresh, the refresh with one material point per voxel or eight per cell) equals the eager
+    sweep, with eager work and synchronisation in between."""
     K = 16
     m = voronoi_polycrystal(K, 10, 5)
     p = H.hmc_default_params(K, 26, 1)
     p.refresh_every = 2
     p.refresh_steps = 50
     p.kT = 0.7
+    H.hmc_set_material_points(p, material_points)
     outs = {}
     for mode in ("eager", "graph"):
         s = torch.cuda.Stream()
