@@ -612,10 +612,12 @@ struct LaneShiftShape {
     static constexpr int PAD = 8;                       // leading zeros of the force array
 };
 
-// h = 3 (56 lanes of one trial per wavefront) holds 7 x 21 stiffness registers per lane:
-// with one wavefront per SIMD it keeps them without spilling.
+// h = 3 (56 lanes of one trial per wavefront) holds 7 x 21 stiffness registers per lane and
+// spills some 34 registers at two wavefronts per SIMD; measured on the 128^3 workload with a
+// 7^3 zone x 400 steps, that still beats one wavefront per SIMD without spills (36.9 against
+// 44.2 ms per colour launch).
 template <int H>
-__global__ __launch_bounds__(64, H == 3 ? 1 : 2) void k_zone_lane(ZoneArgs a)
+__global__ __launch_bounds__(64, 2) void k_zone_lane(ZoneArgs a)
 {
     using S = LaneShiftShape<H>;
     constexpr int N = S::N, NN = S::NN, LT = S::LT, TW = S::TW, Z = S::Z, ROW = S::ROW, TB = S::TB;
@@ -896,7 +898,7 @@ hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
     a.alpha = (float)c->p.zone_alpha;
     a.beta = (float)c->p.zone_beta;
     const int h = c->p.zone_h;
-    // automatic: lane shifts for h >= 1 (at h = 3, 1.39e6 solves/s against 3.75e5 for a
+    // automatic: lane shifts for h >= 1 (at h = 3, 1.67e6 solves/s against 3.75e5 for a
     // wavefront per trial, 128^3 workload, n_r = 400); node columns for h = 0
     const int v = c->p.zone_variant;
     const bool laneshift = (v == 0 && h >= 1) || v == 3;
