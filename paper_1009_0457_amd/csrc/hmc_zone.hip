@@ -612,12 +612,12 @@ struct LaneShiftShape {
     static constexpr int PAD = 8;                       // leading zeros of the force array
 };
 
-// h = 3 (56 lanes of one trial per wavefront) holds 7 x 21 stiffness registers per lane and
-// spills some 34 registers at two wavefronts per SIMD; measured on the 128^3 workload with a
-// 7^3 zone x 400 steps, that still beats one wavefront per SIMD without spills (36.9 against
-// 44.2 ms per colour launch).
+// Wavefronts per SIMD, measured on the 128^3 workload: h = 1 (3^3 x 50 steps) runs 3 with a
+// few registers spilled, 0.357 against 0.418 ms per colour launch at 2; h = 2 runs 2 (3 spill
+// 131 registers and take 9.6 against 5.7 ms); h = 3 (7 x 21 stiffness registers per lane)
+// spills some 34 registers at 2 and still beats 1 without spills (36.9 against 44.2 ms).
 template <int H>
-__global__ __launch_bounds__(64, 2) void k_zone_lane(ZoneArgs a)
+__global__ __launch_bounds__(64, H == 1 ? 3 : 2) void k_zone_lane(ZoneArgs a)
 {
     using S = LaneShiftShape<H>;
     constexpr int N = S::N, NN = S::NN, LT = S::LT, TW = S::TW, Z = S::Z, ROW = S::ROW, TB = S::TB;
