@@ -1,0 +1,106 @@
+"""Edge cases of the library through the C ABI: empty work (no sweeps, no relaxation steps),
+a single grain, and the largest lattice the library accepts (K = 1024, 2^30 sites) with
+sampled parity against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1009_0457_amd import hmc as H
+from paper_1009_0457_amd.synth import random_spins, voronoi_polycrystal
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_empty_work_is_a_no_op():
+    K = 12
+    m = voronoi_polycrystal(K, 6, 2)
+    p = H.hmc_default_params(K, 26, 1)
+    lat = H.Lattice(p, m.Q)
+    lat.set_orientations(m.euler)
+    lat.set_spins(m.spins)
+    lat.sweep(0)
+    assert np.array_equal(lat.get_spins().cpu().numpy(), m.spins)
+    assert lat.stats()["site_trials"] == 0 and lat.sweep_index() == 0
+    lat.close()
+
+
+@pytest.mark.parametrize("material_points", [1, 8])
+def test_zero_relaxation_steps_give_the_reuss_field(material_points):
+    """A cold refresh of 0 steps leaves the uniform-stress start: sigma_v = C_v <S> Sigma."""
+    K = 12
+    m = voronoi_polycrystal(K, 6, 4)
+    p = H.hmc_default_params(K, 26, 1)
+    H.hmc_set_material_points(p, material_points)
+    lat = H.Lattice(p, m.Q)
+    lat.set_orientations(m.euler)
+    lat.set_spins(m.spins)
+    sig = np.array([80.0, 0.0, -40.0, 20.0, 0.0, 10.0])
+    lat.set_load(sig)
+    lat.stress_refresh(0, True)
+    got = lat.get_stress().cpu().numpy().astype(np.float64)
+    Ct, St, _ = O.tables(m.euler, p.C11, p.C12, p.C44)
+    E = St[m.spins].mean(axis=0) @ (sig * 1e-3)
+    want = np.einsum("nij,j->in", Ct[m.spins], E)
+    assert np.abs(got - want).max() < 1e-5 * np.abs(want).max()
+    assert np.abs(lat.macro_strain() - E).max() < 1e-6 * np.abs(E).max()
+    lat.close()
+
+
+def test_single_grain_never_flips():
+    """Q = 1 under load: every proposal is the site's own spin, so no trial is a real flip
+    and no zone solve runs."""
+    K = 10
+    p = H.hmc_default_params(K, 26, 2)
+    lat = H.Lattice(p, 1)
+    lat.set_orientations(np.array([[0.3, 0.7, 1.1]]))
+    lat.set_spins(np.zeros(K ** 3, np.int32))
+    lat.set_load([100.0, 0, 0, 0, 0, 0])
+    lat.stress_refresh(-1, True)
+    lat.sweep(3)
+    st = lat.stats()
+    assert st["site_trials"] == 3 * K ** 3 and st["real_flips"] == 0 and st["zone_solves"] == 0
+    assert not lat.get_spins().cpu().numpy().any()
+    lat.close()
+
+
+def test_largest_lattice_sampled_parity():
+    """K = 1024 (2^30 sites, the largest edge the library accepts), zero load, 26 neighbours:
+    one colour pass, then 20 000 sampled sites of that colour against the oracle's trials from
+    the same snapshot (bit-exact), and every other site unchanged."""
+    K, Q = 1024, 8
+    say(f"[largest] K={K} Q={Q}: drawing spins")
+    spins = random_spins(K, Q, 77)
+    p = H.hmc_default_params(K, 26, 1)
+    p.lambda_el = 0.0
+    p.kT = 0.8
+    lat = H.Lattice(p, Q)
+    lat.set_orientations(np.zeros((Q, 3)))
+    lat.set_spins(spins)
+    lat.set_sweep_index(5)
+    say("    colour pass 0")
+    lat.colour_pass(0)
+    post = lat.get_spins().cpu().numpy()
+    lat.close()
+    col0 = np.zeros(K ** 3, bool).reshape(K, K, K)
+    col0[0::2, 0::2, 0::2] = True
+    col0 = col0.ravel()
+    assert np.array_equal(post[~col0], spins[~col0])
+    sites = np.random.default_rng(3).choice(np.nonzero(col0)[0], 20000, replace=False)
+    prm = O.make_params(K, 26, Q, proposal=0, elastic=False, J=p.J, kT=p.kT, seed=p.seed)
+    d = np.zeros(Q * 36)
+    rec = O.trials(prm, spins, d, d, None, 5, sites)
+    want = np.where((rec["flags"] & 2) != 0, rec["q_new"], spins[sites])
+    changed = int(np.count_nonzero(want != spins[sites]))
+    say(f"    {changed} of 20000 sampled sites flipped; mismatches {int(np.count_nonzero(post[sites] != want))}")
+    assert changed > 0 and np.array_equal(post[sites], want)
