@@ -275,7 +275,8 @@ typedef struct {
 } hmc_replica;
 
 /* Fill *r for a K^3 replica with Q grains: kT and seed from common, lambda_el = 2.6667e6/K
- * and the global heavy-ball constants for K as in hmc_default_params, zero load. */
+ * and the global heavy-ball constants for K and common->material_points as in
+ * hmc_set_material_points, zero load. */
 hmc_status hmc_default_replica(hmc_replica* r, const hmc_params* common, int32_t K, int32_t Q);
 
 /* Workspace bytes of a batch of n replicas (0 if any description is invalid). */
