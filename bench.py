@@ -472,6 +472,10 @@ def bench_growth(a):
     b.synchronize()
     t_batch = time.perf_counter() - t0
     st = b.stats()
+    # the grain-size measurement of every run on the GPU (hmc_grain_labels)
+    t0 = time.perf_counter()
+    n_grains = [b.grain_labels(r)[1] for r in range(runs)]
+    t_labels = time.perf_counter() - t0
     b.close()
     # the same runs one after another
     t_plain = 0.0
@@ -511,6 +515,8 @@ def bench_growth(a):
                                 f"{2 * sites / 2 ** 20:.1f} MiB of spins, cache-resident"},
            "runs_alone": {"value": trials / t_plain, "ms_per_step": t_plain / a.steps * 1e3},
            "batched_over_alone": t_plain / t_batch,
+           "grain_count_ms_per_run": round(t_labels / runs * 1e3, 3),
+           "mean_grain_volume": K ** 3 * runs / float(sum(n_grains)),
            "real_flip_fraction": st["real_flips"] / max(1, st["site_trials"]),
            "acceptance": st["accepted"] / max(1, st["real_flips"])}
     if not a.no_cpu_baseline:

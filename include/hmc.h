@@ -300,6 +300,14 @@ hmc_status hmc_batch_energy(hmc_ctx ctx, int32_t r, int64_t* unlike_bonds, doubl
 hmc_status hmc_batch_texture_histogram(hmc_ctx ctx, int32_t r, const double axis[3], double bin_deg,
                                        int32_t nbins, int64_t* counts_host);
 
+/* Grains of replica r (0 for a single lattice): the face-connected clusters of equal spins on
+ * the periodic lattice, whose mean volume K^3 / n is the grain size of Sec. 6's growth law.
+ * Writes labels_dev[v] (dev, K_r^3 int32, caller-owned) = the smallest site index of the grain
+ * of site v, and *n_grains (host).  Iterates label propagation and pointer jumping on the
+ * context's stream until nothing changes, synchronising that stream once per round.  Reads the
+ * spins as they are after all work enqueued so far. */
+hmc_status hmc_grain_labels(hmc_ctx ctx, int32_t r, int32_t* labels_dev, int64_t* n_grains);
+
 /* ---- Adjoint of the global explicit solve (single-lattice contexts) ------------------
  * U(theta, Sigma) = stored elastic energy after a cold start and n_steps explicit steps of
  * the global relaxation (as hmc_stress_refresh(ctx, n_steps, 1)), as a function of every

@@ -1253,6 +1253,17 @@ hmc_status hmc_batch_energy(hmc_ctx c, int32_t r, int64_t* unlike, double* U)
     return energy_of(c, r, unlike, U);
 }
 
+hmc_status hmc_grain_labels(hmc_ctx c, int32_t r, int32_t* labels_dev, int64_t* n_grains)
+{
+    if (!c) return HMC_EINVAL;
+    c->err.clear();
+    if (bad_rep(c, r) || !labels_dev || !n_grains) return state_fail(c, HMC_EINVAL, "bad replica or null argument");
+    if (!c->have_spins) return state_fail(c, HMC_ESTATE, "no spins set");
+    int rounds = 0;
+    HMC_TRY(c, launch_grain_labels(c, r, labels_dev, n_grains, &rounds), "grain labels");
+    return HMC_OK;
+}
+
 hmc_status hmc_batch_texture_histogram(hmc_ctx c, int32_t r, const double axis[3], double bin_deg, int32_t nbins,
                                        int64_t* counts)
 {

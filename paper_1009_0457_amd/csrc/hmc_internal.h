@@ -94,7 +94,7 @@ constexpr double kSumScale = 67108864.0;       // 2^26
 constexpr int kSeqState = 16;
 
 // Counters (uint32): list counts per colour, error flag.
-enum CounterSlot { kListCount = 0, kErrFlag = 8, kCounters = 16 };
+enum CounterSlot { kListCount = 0, kErrFlag = 8, kLabelChanged = 9, kCounters = 16 };
 
 // 64-bit statistics slots, kept in kStatCopies copies that blocks pick by index (fewer
 // same-address atomics) and that the host sums.
@@ -211,6 +211,9 @@ hipError_t launch_global_final(hmc_ctx_s* c, bool write_sigma);
 // 2 x 2 x 2 material points per background cell (hmc_mp8.hip): n explicit steps, the final
 // point stresses and stored energy.
 hipError_t launch_mp8_steps(hmc_ctx_s* c, int n_steps);
+// Grains of replica rep (hmc_grains.hip): per-site labels (the smallest site index of each
+// face-connected cluster of equal spins) and their number; host-synchronous.
+hipError_t launch_grain_labels(hmc_ctx_s* c, int rep, int32_t* labels, int64_t* n_grains, int* rounds);
 hipError_t launch_mp8_final(hmc_ctx_s* c, bool write_sigma);
 hipError_t launch_zero_wE(hmc_ctx_s* c);
 hipError_t launch_unlike_bonds(hmc_ctx_s* c, int rep);

@@ -98,6 +98,7 @@ _SIGS = [
     ("hmc_get_kernel_times", C.c_int, [C.c_void_p, C.POINTER(hmc_kernel_times)]),
     ("hmc_set_graphs", C.c_int, [C.c_void_p, C.c_int32]),
     ("hmc_set_material_points", C.c_int, [C.POINTER(hmc_params), C.c_int32]),
+    ("hmc_grain_labels", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int64)]),
     ("hmc_default_replica", C.c_int, [C.POINTER(hmc_replica), C.POINTER(hmc_params), C.c_int32, C.c_int32]),
     ("hmc_batch_workspace_bytes", C.c_size_t, [C.POINTER(hmc_params), C.c_int32, C.POINTER(hmc_replica)]),
     ("hmc_batch_create", C.c_int, [C.POINTER(hmc_params), C.c_int32, C.POINTER(hmc_replica), C.c_void_p,
@@ -353,6 +354,12 @@ def hmc_batch_texture_histogram(ctx, r, axis, bin_deg=10.0, nbins=6):
     return out
 
 
+def hmc_grain_labels(ctx, r, labels_dev) -> int:
+    n = C.c_int64()
+    _check(lib().hmc_grain_labels(ctx, int(r), _ptr(labels_dev), C.byref(n)), ctx)
+    return int(n.value)
+
+
 def hmc_grain_tables(euler, C11, C12, C44):
     e = np.ascontiguousarray(euler, np.float64)
     Q = e.shape[0]
@@ -473,6 +480,12 @@ class Lattice:
 
     def texture_histogram(self, axis, bin_deg=10.0, nbins=6):
         return hmc_texture_histogram(self.ctx, axis, bin_deg, nbins)
+
+    def grain_labels(self):
+        """(per-site grain labels on the device, number of grains)."""
+        out = self.torch.empty(self.n3, dtype=self.torch.int32, device=self.device)
+        n = hmc_grain_labels(self.ctx, 0, out)
+        return out, n
 
     def get_stress(self):
         out = self.torch.empty((6, self.n3), dtype=self.torch.float32, device=self.device)
@@ -627,6 +640,11 @@ class Batch(Lattice):
 
     def energy(self, r=0):
         return hmc_batch_energy(self.ctx, r)
+
+    def grain_labels(self, r=0):
+        out = self.torch.empty(self.n3s[r], dtype=self.torch.int32, device=self.device)
+        n = hmc_grain_labels(self.ctx, r, out)
+        return out, n
 
     def texture_histogram(self, axis, bin_deg=10.0, nbins=6, r=0):
         return hmc_batch_texture_histogram(self.ctx, r, axis, bin_deg, nbins)

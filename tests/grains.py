@@ -9,6 +9,11 @@ from scipy.sparse.csgraph import connected_components
 
 
 def grain_count(spins, K):
+    return int(grain_labels(spins, K).max()) + 1
+
+
+def grain_labels(spins, K):
+    """Component index (0..n-1, scipy's numbering) of every site."""
     g = np.asarray(spins).reshape(K, K, K)          # [z, y, x]
     idx = np.arange(K ** 3).reshape(K, K, K)
     rows, cols = [], []
@@ -19,7 +24,7 @@ def grain_count(spins, K):
     r = np.concatenate(rows)
     c = np.concatenate(cols)
     A = coo_matrix((np.ones(r.size, np.int8), (r, c)), shape=(K ** 3, K ** 3))
-    return int(connected_components(A, directed=False)[0])
+    return connected_components(A, directed=False)[1]
 
 
 def mean_grain_volume(spins, K):
