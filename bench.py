@@ -92,7 +92,7 @@ def parse():
                          "for the zone-size comparison)")
     ap.add_argument("--zone-steps", type=int, default=None, help="large: zone relaxation steps n_r")
     ap.add_argument("--material-points", type=int, choices=[1, 8], default=1,
-                    help="refresh: one material point per voxel (default) or 2x2x2 per cell of 2^3 sites")
+                    help="refresh, texture: one material point per voxel (default) or 2x2x2 per cell of 2^3 sites")
     ap.add_argument("--replicas", type=int, default=64)
     ap.add_argument("--zone-variant", type=int, default=0, help="zone-solve kernel (0 = automatic)")
     ap.add_argument("--tile-z", type=int, default=0, help="node layers per block of the explicit step (0 = automatic)")
@@ -552,7 +552,9 @@ def bench_texture(a):
 
     K, runs, substeps = 100, 10, 75
     log(f"[bench] texture: {runs} x {K}^3, 91 orientations about z, 30 MPa in {substeps} sub-loads")
-    out_run = T.texture_run(K, runs, substeps=substeps, record_every=substeps, profile=True, tile_z=a.tile_z)
+    mp = 8 if a.material_points == 8 else 1
+    out_run = T.texture_run(K, runs, substeps=substeps, record_every=substeps, profile=True, tile_z=a.tile_z,
+                            material_points=mp)
     wall = out_run["wall_s"]
     kt = out_run["kernel_times"]
     st = out_run["stats"]
@@ -560,7 +562,8 @@ def bench_texture(a):
     ks = kt["refresh_step"]
     ms = ks["total_ms"] / max(1, ks["launches"])
     node_steps = runs * K ** 3
-    ach = 50.0 * node_steps / (ms * 1e-3) / 1e9
+    per_site = 268.0 / 8 if mp == 8 else 50.0
+    ach = per_site * node_steps / (ms * 1e-3) / 1e9
     PHI = np.arange(91.0)
     F0, F1 = out_run["fractions"][0].mean(0), out_run["fractions"][-1].mean(0)
     log(f"[bench] loaded phase {wall:.2f} s; explicit step {ms * 1e3:.1f} us x {ks['launches']}")
@@ -570,12 +573,13 @@ def bench_texture(a):
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"texture: {runs} runs of {K}^3, 91 rotations about z, coarsened 100 sweeps at "
                                   f"kT/J 2.6, 30 MPa xx in {substeps} sub-loads (refresh 200 steps, cold 2000, then "
-                                  f"one sweep), 26 neighbours, 5^3 zone x 200, screen on", "sites": runs * K ** 3,
-                      "tile_z": a.tile_z},
+                                  f"one sweep), 26 neighbours, 5^3 zone x 200, screen on"
+                                  + (", 2x2x2 material points per cell" if mp == 8 else ""), "sites": runs * K ** 3,
+                      "tile_z": a.tile_z, "material_points": mp},
            "roofline": {"kernel": "explicit step", "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
                         "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
                         "avg_launch_ms": round(ms, 4),
-                        "note": "50 B per node-step (the explicit step's algorithmic bytes) over all runs"},
+                        "note": f"{per_site} B per site-step (the explicit step's algorithmic bytes) over all runs"},
            "kernel_ms": {k: round(v["total_ms"], 2) for k, v in kt.items()},
            "zone_solve_fraction": st["zone_solves"] / trials,
            "texture": {"soft10_before": T.soft_fraction(PHI, F0), "soft10_after": T.soft_fraction(PHI, F1),

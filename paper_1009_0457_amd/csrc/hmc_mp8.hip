@@ -18,9 +18,12 @@
 // edges and the cell's 24 corner forces written to a cell-major force array, and per-block
 // sums of the point stresses), a node pass
 // (one thread per node: the forces of its 8 cells, the heavy-ball update of u and w in place)
-// and a one-block fold of the stress sums into E, per replica.  A replica's node fields occupy
-// the first (K/2)^3 entries of its slice of each displacement plane; its corner forces use its
-// slice of the second displacement buffer, which holds exactly 24 floats per cell.
+// and a fold of the stress sums into E (one block per replica); each launch covers every replica
+// of a batch.  A replica's node fields occupy the first (K/2)^3 entries of its slice of each
+// displacement plane; its corner forces use its slice of the second displacement buffer, which
+// holds exactly 24 floats per cell.
+#include <algorithm>
+
 #include "hmc_device.h"
 
 namespace hmc {
@@ -31,30 +34,50 @@ namespace {
 // there: the trilinear shape functions' factor 1 +- xi_p with xi_p = +-1/2.
 __host__ __device__ constexpr float mp_w(int b, int p) { return b == p ? 1.5f : 0.5f; }
 
+// Work-groups per replica of the cell and node passes: one per 256 cells, at most 4096 (the
+// passes stride beyond).  The same count alone and in a batch, so each replica's partial sums
+// are the same numbers in the same order either way.
+__host__ __device__ inline int mp8_blocks(int K)
+{
+    const int64_t Kc = K / 2, nc = Kc * Kc * Kc;
+    const int64_t b = (nc + 255) / 256;
+    return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+// All replicas in one launch: work-group (x, y) is block x of replica y; blocks beyond the
+// replica's count return at once.  A replica's partial sums go to its own node-block slots
+// (RepDev::node_first onwards, never fewer than its cell-pass blocks).
 struct Mp8Args {
     const int16_t* spins;
     const float* Ctab;
-    const float* u;        // 3 planes of `plane` floats, nodes first
-    float* F;              // 24 x n_cells corner forces: row k of the cells at plane k / 8,
-                           // offset (k % 8) n_cells (a replica's slice of 3 planes of `plane`)
+    const float* u;        // 3 planes of `plane` floats; a replica's nodes first in its slice
+    float* F;              // corner forces: row k of a replica's cells at plane k / 8, offset
+                           // (k % 8) n_cells of its slice (3 planes of `plane`)
     float* sigma;          // final pass: 6 planes of point stresses (or null)
     double* partials;
     const double* state;
-    int K;
+    const RepDev* reps;
     int64_t plane;
 };
 
 template <bool FINAL>
 __global__ __launch_bounds__(256) void k_mp8_cells(Mp8Args a)
 {
-    const int K = a.K, Kc = K >> 1;
+    const RepDev& R = a.reps[blockIdx.y];
+    const int K = R.K, Kc = K >> 1, nb = mp8_blocks(K);
+    if ((int)blockIdx.x >= nb) return;   // the whole work-group leaves together
     const int64_t nc = (int64_t)Kc * Kc * Kc;
+    const int16_t* spins = a.spins + R.site_off;
+    const float* Ctab = a.Ctab + R.grain_off * kTab;
+    const float* u = a.u + R.site_off;
+    float* F = a.F + R.site_off;
+    const double* st = a.state + (int64_t)blockIdx.y * kStateDoubles;
     float E[6];
 #pragma unroll
-    for (int I = 0; I < 6; ++I) E[I] = (float)a.state[kE + I];
+    for (int I = 0; I < 6; ++I) E[I] = (float)st[kE + I];
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cell < nc;
-         cell += (int64_t)gridDim.x * blockDim.x) {
+         cell += (int64_t)nb * blockDim.x) {
         const int X = (int)(cell % Kc), Y = (int)((cell / Kc) % Kc), Z = (int)(cell / ((int64_t)Kc * Kc));
         const int X1 = X + 1 < Kc ? X + 1 : 0, Y1 = Y + 1 < Kc ? Y + 1 : 0, Z1 = Z + 1 < Kc ? Z + 1 : 0;
         float uc[8][3];
@@ -63,7 +86,7 @@ __global__ __launch_bounds__(256) void k_mp8_cells(Mp8Args a)
             const int64_t node = (int64_t)((c & 1) ? X1 : X) +
                                  (int64_t)Kc * (((c >> 1) & 1 ? Y1 : Y) + (int64_t)Kc * ((c >> 2) & 1 ? Z1 : Z));
 #pragma unroll
-            for (int j = 0; j < 3; ++j) uc[c][j] = a.u[(int64_t)j * a.plane + node];
+            for (int j = 0; j < 3; ++j) uc[c][j] = u[(int64_t)j * a.plane + node];
         }
         // Edge differences of the cell along each direction: D[d][e][j] for the 4 edges e
         // parallel to d (e = the other two bits, lower direction first).  The gradient at a
@@ -108,7 +131,7 @@ __global__ __launch_bounds__(256) void k_mp8_cells(Mp8Args a)
             e6[3] = (g[2][1] + g[1][2]) + E[3];
             e6[4] = (g[2][0] + g[0][2]) + E[4];
             e6[5] = (g[1][0] + g[0][1]) + E[5];
-            symv21(a.Ctab + (int64_t)a.spins[v] * kTab, e6, s);
+            symv21(Ctab + (int64_t)spins[v] * kTab, e6, s);
             if (FINAL) {
                 double dd = 0.0;
 #pragma unroll
@@ -116,7 +139,7 @@ __global__ __launch_bounds__(256) void k_mp8_cells(Mp8Args a)
                 acc[0] += 0.5 * dd;
                 if (a.sigma)
 #pragma unroll
-                    for (int I = 0; I < 6; ++I) a.sigma[(int64_t)I * a.plane + v] = s[I];
+                    for (int I = 0; I < 6; ++I) a.sigma[(int64_t)I * a.plane + R.site_off + v] = s[I];
             } else {
 #pragma unroll
                 for (int I = 0; I < 6; ++I) acc[I] += (double)s[I];
@@ -154,21 +177,27 @@ __global__ __launch_bounds__(256) void k_mp8_cells(Mp8Args a)
             for (int c = 0; c < 8; ++c)
 #pragma unroll
                 for (int j = 0; j < 3; ++j)
-                    a.F[(int64_t)((3 * c + j) >> 3) * a.plane + (int64_t)((3 * c + j) & 7) * nc + cell] = f[c][j];
+                    F[(int64_t)((3 * c + j) >> 3) * a.plane + (int64_t)((3 * c + j) & 7) * nc + cell] = f[c][j];
     }
     if (FINAL)
-        block_sum_to<1>(a.partials, acc);
+        block_sum_to<1>(a.partials, acc, R.node_first + (int)blockIdx.x);
     else
-        block_sum_to<6>(a.partials, acc);
+        block_sum_to<6>(a.partials, acc, R.node_first + (int)blockIdx.x);
 }
 
 // Node n gathers corner c of cell n - c (bits x, y, z) from every one of its 8 cells.
-__global__ __launch_bounds__(256) void k_mp8_nodes(const float* __restrict__ F, float* u, float* w, int K,
-                                                   int64_t plane, float alpha, float beta)
+__global__ __launch_bounds__(256) void k_mp8_nodes(const float* __restrict__ Fall, float* uall, float* wall,
+                                                   const RepDev* reps, int64_t plane)
 {
-    const int Kc = K >> 1;
+    const RepDev& R = reps[blockIdx.y];
+    const int K = R.K, Kc = K >> 1, nb = mp8_blocks(K);
+    if ((int)blockIdx.x >= nb) return;
     const int64_t nc = (int64_t)Kc * Kc * Kc;
-    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nc; n += (int64_t)gridDim.x * blockDim.x) {
+    const float* F = Fall + R.site_off;
+    float* u = uall + R.site_off;
+    float* w = wall + R.site_off;
+    const float alpha = R.glob_alpha, beta = R.glob_beta;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nc; n += (int64_t)nb * blockDim.x) {
         const int X = (int)(n % Kc), Y = (int)((n / Kc) % Kc), Z = (int)(n / ((int64_t)Kc * Kc));
         const int Xm = X > 0 ? X - 1 : Kc - 1, Ym = Y > 0 ? Y - 1 : Kc - 1, Zm = Z > 0 ? Z - 1 : Kc - 1;
         float r[3] = {0.f, 0.f, 0.f};
@@ -190,76 +219,72 @@ __global__ __launch_bounds__(256) void k_mp8_nodes(const float* __restrict__ F, 
     }
 }
 
-// One block: fixed-order sum of the cell pass's stress sums, then the macroscopic update.
-__global__ __launch_bounds__(256) void k_mp8_E(double* state, const double* partials, int nblocks, const RepDev* reps,
-                                               int rep)
+// One block per replica: fixed-order sum of its cell pass's stress sums, then its macroscopic
+// update.
+__global__ __launch_bounds__(256) void k_mp8_E(double* state, const double* partials, const RepDev* reps)
 {
-    const RepDev R = reps[rep];
+    const RepDev R = reps[blockIdx.x];
+    const int nb = mp8_blocks(R.K);
     double s[6] = {0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nblocks; b += 256)
+    for (int b = threadIdx.x; b < nb; b += 256)
 #pragma unroll
-        for (int I = 0; I < 6; ++I) s[I] += partials[(int64_t)b * 8 + I];
+        for (int I = 0; I < 6; ++I) s[I] += partials[(int64_t)(R.node_first + b) * 8 + I];
     const double tot = block_total<6>(s);
     if (threadIdx.x < 6) {
+        double* st = state + (int64_t)blockIdx.x * kStateDoubles;
         const int I = threadIdx.x;
         const double rE = R.Sigma[I] - tot / (double)R.n3;
-        const double wE = (double)R.glob_beta * state[kWE + I] + R.glob_alphaE * rE;
-        state[kWE + I] = wE;
-        state[kE + I] += wE;
+        const double wE = (double)R.glob_beta * st[kWE + I] + R.glob_alphaE * rE;
+        st[kWE + I] = wE;
+        st[kE + I] += wE;
     }
 }
 
-__global__ __launch_bounds__(256) void k_mp8_U(double* state, const double* partials, int nblocks)
+__global__ __launch_bounds__(256) void k_mp8_U(double* state, const double* partials, const RepDev* reps)
 {
+    const RepDev R = reps[blockIdx.x];
+    const int nb = mp8_blocks(R.K);
     double s[1] = {0.0};
-    for (int b = threadIdx.x; b < nblocks; b += 256) s[0] += partials[(int64_t)b * 8];
+    for (int b = threadIdx.x; b < nb; b += 256) s[0] += partials[(int64_t)(R.node_first + b) * 8];
     const double tot = block_total<1>(s);
-    if (threadIdx.x == 0) state[kU] = tot;
+    if (threadIdx.x == 0) state[(int64_t)blockIdx.x * kStateDoubles + kU] = tot;
 }
 
-int mp8_blocks(const RepDev& R)
+Mp8Args mp8_args(hmc_ctx_s* c)
 {
-    const int64_t Kc = R.K / 2, nc = Kc * Kc * Kc;
-    const int64_t b = (nc + 255) / 256;
-    return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
-}
-
-// Replica r's slices: its spins, grain tables, node fields, force rows and state.
-Mp8Args mp8_args(hmc_ctx_s* c, int r)
-{
-    const RepDev& R = c->reps[r];
     Mp8Args a;
-    a.spins = c->d.spins + R.site_off;
-    a.Ctab = c->d.Ctab + R.grain_off * kTab;
-    a.u = c->d.u[0] + R.site_off;
-    a.F = c->d.u[1] + R.site_off;
+    a.spins = c->d.spins;
+    a.Ctab = c->d.Ctab;
+    a.u = c->d.u[0];
+    a.F = c->d.u[1];
     a.sigma = nullptr;
     a.partials = c->d.partials;
-    a.state = c->d.state + (int64_t)r * kStateDoubles;
-    a.K = R.K;
+    a.state = c->d.state;
+    a.reps = c->d.reps;
     a.plane = c->total_sites;
     return a;
 }
 
+dim3 mp8_grid(const hmc_ctx_s* c)
+{
+    int nb = 1;
+    for (const RepDev& R : c->reps) nb = std::max(nb, mp8_blocks(R.K));
+    return dim3((unsigned)nb, (unsigned)c->n_rep);
+}
+
 }  // namespace
 
-// Replicas of a batch run one after another within each step (their cell passes share the
-// partial-sum buffer, which each replica's fold reads before the next replica's pass).
 hipError_t launch_mp8_steps(hmc_ctx_s* c, int n_steps)
 {
+    const Mp8Args a = mp8_args(c);
+    const dim3 grid = mp8_grid(c);
     for (int s = 0; s < n_steps; ++s) {
         const int tok = prof_begin(c, kProfRefreshStep);
-        for (int r = 0; r < c->n_rep; ++r) {
-            const RepDev& R = c->reps[r];
-            const Mp8Args a = mp8_args(c, r);
-            const int nb = mp8_blocks(R);
-            hipLaunchKernelGGL(k_mp8_cells<false>, dim3(nb), dim3(256), 0, c->stream, a);
-            hipLaunchKernelGGL(k_mp8_nodes, dim3(nb), dim3(256), 0, c->stream, (const float*)a.F,
-                               c->d.u[0] + R.site_off, c->d.w + R.site_off, R.K, c->total_sites, R.glob_alpha,
-                               R.glob_beta);
-            hipLaunchKernelGGL(k_mp8_E, dim3(1), dim3(256), 0, c->stream, c->d.state + (int64_t)r * kStateDoubles,
-                               (const double*)c->d.partials, nb, (const RepDev*)c->d.reps, r);
-        }
+        hipLaunchKernelGGL(k_mp8_cells<false>, grid, dim3(256), 0, c->stream, a);
+        hipLaunchKernelGGL(k_mp8_nodes, grid, dim3(256), 0, c->stream, (const float*)c->d.u[1], c->d.u[0], c->d.w,
+                           (const RepDev*)c->d.reps, c->total_sites);
+        hipLaunchKernelGGL(k_mp8_E, dim3(c->n_rep), dim3(256), 0, c->stream, c->d.state, (const double*)c->d.partials,
+                           (const RepDev*)c->d.reps);
         prof_end(c, tok);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -269,15 +294,12 @@ hipError_t launch_mp8_steps(hmc_ctx_s* c, int n_steps)
 
 hipError_t launch_mp8_final(hmc_ctx_s* c, bool write_sigma)
 {
+    Mp8Args a = mp8_args(c);
+    a.sigma = write_sigma ? c->d.sigma : nullptr;
     const int tok = prof_begin(c, kProfRefreshOther);
-    for (int r = 0; r < c->n_rep; ++r) {
-        Mp8Args a = mp8_args(c, r);
-        a.sigma = write_sigma ? c->d.sigma + c->reps[r].site_off : nullptr;
-        const int nb = mp8_blocks(c->reps[r]);
-        hipLaunchKernelGGL(k_mp8_cells<true>, dim3(nb), dim3(256), 0, c->stream, a);
-        hipLaunchKernelGGL(k_mp8_U, dim3(1), dim3(256), 0, c->stream, c->d.state + (int64_t)r * kStateDoubles,
-                           (const double*)c->d.partials, nb);
-    }
+    hipLaunchKernelGGL(k_mp8_cells<true>, mp8_grid(c), dim3(256), 0, c->stream, a);
+    hipLaunchKernelGGL(k_mp8_U, dim3(c->n_rep), dim3(256), 0, c->stream, c->d.state, (const double*)c->d.partials,
+                       (const RepDev*)c->d.reps);
     prof_end(c, tok);
     return hipGetLastError();
 }
