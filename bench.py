@@ -676,8 +676,8 @@ def bench_refresh(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in "
-                                   "DESIGN.md but not built", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU; sharding over several GPUs is not implemented",
+                          "n_gpus": a.gpus}))
         sys.exit(2)
     if a.copy_probe_mib:
         import torch
