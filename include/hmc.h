@@ -46,7 +46,15 @@ typedef enum {
     HMC_ESTATE = 3,    /* call out of order (e.g. sweep before spins/orientations, elastic
                           sweep before a stress field exists) */
     HMC_EDEVICE = 4,   /* a HIP call or kernel launch failed */
-    HMC_ENUMERIC = 5   /* non-finite input (Euler angles, load, parameters) or singular C */
+    HMC_ENUMERIC = 5   /* non-finite input (Euler angles, load, parameters) or singular C;
+                          or, from a call that synchronises the stream (hmc_energy,
+                          hmc_texture_histogram, hmc_get_stats, hmc_get_macro_strain,
+                          hmc_elastic_forward), a non-finite value that a kernel met since the
+                          last such report: an injected stress field, the global solve's stress
+                          field or stored energy, or a zone solve's energy change (whose trial
+                          was rejected; a non-finite input to one trial's zone can also reach
+                          the other trials solved in the same wavefront, which are rejected
+                          too).  The report clears it; the call's outputs are still written. */
 } hmc_status;
 
 typedef struct hmc_ctx_s* hmc_ctx;
@@ -204,7 +212,8 @@ hmc_status hmc_texture_histogram(hmc_ctx ctx, const double axis[3], double bin_d
                                  int32_t nbins, int64_t* counts_host);
 
 /* Stress field of the last refresh (dev, 6 x K^3 float) out / in.  hmc_set_stress injects
- * a field (tests) and marks the stress as present. */
+ * a field (tests) and marks the stress as present; a non-finite entry is reported as
+ * HMC_ENUMERIC by the next synchronising call. */
 hmc_status hmc_get_stress(hmc_ctx ctx, float* dev_out);
 hmc_status hmc_set_stress(hmc_ctx ctx, const float* dev_in);
 
@@ -317,8 +326,12 @@ hmc_status hmc_grain_labels(hmc_ctx ctx, int32_t r, int32_t* labels_dev, int64_t
  * segment at a time from those checkpoints and runs the reverse recurrence, returning
  * dU * dU/dtheta (host, Q x 3, per radian) and dU * dU/dSigma (host, 6, per MPa).  The
  * backward call leaves the context at the forward's final state.  The adjoint workspace must
- * not change between the two calls.  HMC_ESTATE on batches, without a forward, or with the
- * elastic term disabled.  The backward call recomputes segments on a second stream of the
+ * not change between the two calls.  The forward's record is discarded by any later change
+ * of the spins, orientations or load (hmc_set_spins, hmc_set_orientations, hmc_set_load,
+ * hmc_sweep, hmc_colour_pass): hmc_elastic_backward then returns HMC_ESTATE until the next
+ * forward, rather than a gradient of inputs the checkpoints were not taken from.  A backward
+ * call keeps the record (it may be repeated with another dU).  HMC_ESTATE on batches,
+ * without a forward, or with the elastic term disabled.  The backward call recomputes segments on a second stream of the
  * library's own (default priority, created on first use, released by hmc_destroy) while the
  * context's stream runs adjoint steps; events order the two, and the call returns only after
  * both are done (it returns host results), so the caller sees ordinary stream order. */

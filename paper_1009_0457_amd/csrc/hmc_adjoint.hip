@@ -640,7 +640,7 @@ hmc_status hmc_elastic_forward(hmc_ctx c, int32_t n_steps, int32_t ckpt_every, v
     c->adj_steps = n_steps;
     c->adj_every = ckpt_every;
     *U = u;
-    return HMC_OK;
+    return report_nonfinite(c);
 }
 
 hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, double* grad_euler,

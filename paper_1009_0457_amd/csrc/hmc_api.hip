@@ -451,7 +451,12 @@ hmc_status graph_sweep(hmc_ctx c, bool with_refresh)
     HMC_TRY(c, hipGraphLaunch(c->graph[k], c->stream), "graph: launch");
     // mirror what the replayed sweep did
     if (with_refresh) {
-        if (c->p.refresh_steps & 1) c->cur_u = 1 - c->cur_u;
+        // what refresh() leaves: the 8-point solve always ends in buffer 0, the one-point
+        // steps alternate the ping-pong buffers
+        if (c->p.material_points == 8)
+            c->cur_u = 0;
+        else if (c->p.refresh_steps & 1)
+            c->cur_u = 1 - c->cur_u;
         c->host_refresh_steps += c->p.refresh_steps;
         c->have_state = c->have_stress = true;
     }
@@ -681,7 +686,7 @@ hmc_status energy_of(hmc_ctx c, int rep, int64_t* unlike, double* U)
     HMC_TRY(c, hipStreamSynchronize(c->stream), "energy");
     *unlike = (int64_t)(slots / 2);
     *U = u;
-    return HMC_OK;
+    return report_nonfinite(c);
 }
 
 hmc_status texture_of(hmc_ctx c, int rep, const double axis[3], double bin_deg, int32_t nbins, int64_t* counts)
@@ -718,7 +723,7 @@ hmc_status texture_of(hmc_ctx c, int rep, const double axis[3], double bin_deg, 
             "texture");
     HMC_TRY(c, hipStreamSynchronize(c->stream), "texture");
     for (int b = 0; b < nbins; ++b) counts[b] = (int64_t)h[b];
-    return HMC_OK;
+    return report_nonfinite(c);
 }
 
 // Copies `planes` component planes of replica `rep` between a shared field and a dense
@@ -770,6 +775,25 @@ void prof_end(hmc_ctx_s* c, int token)
 {
     if (token < 0 || token >= (int)c->prof_pending.size()) return;
     (void)hipEventRecord(c->prof_pending[token].b, c->stream);
+}
+
+// Reads (and clears) the device's non-finite flag.  Called by the entry points that
+// synchronise the stream anyway; returns HMC_ENUMERIC with a message naming the kernels that
+// met a non-finite value since the last report.
+hmc_status report_nonfinite(hmc_ctx_s* c)
+{
+    uint32_t* dflag = c->d.counters + kNonFinite;
+    uint32_t flag = 0;
+    HMC_TRY(c, hipMemcpyAsync(&flag, dflag, sizeof flag, hipMemcpyDeviceToHost, c->stream), "non-finite flag");
+    HMC_TRY(c, hipStreamSynchronize(c->stream), "non-finite flag");
+    if (!flag) return HMC_OK;
+    HMC_TRY(c, launch_fill_u32(dflag, 0u, 1, c->stream), "non-finite flag");
+    std::string m = "non-finite value met on the device:";
+    if (flag & kNfInjected) m += " an injected stress field (hmc_set_stress);";
+    if (flag & kNfGlobal) m += " the global solve's stress field or stored energy;";
+    if (flag & kNfZone) m += " a zone solve's energy change (its trial was rejected);";
+    c->err = m;
+    return HMC_ENUMERIC;
 }
 
 }  // namespace hmc
@@ -943,6 +967,7 @@ hmc_status hmc_set_orientations(hmc_ctx c, const double* euler)
     c->err.clear();
     if (!euler) return state_fail(c, HMC_EINVAL, "null orientations");
     if (c->is_batch) return state_fail(c, HMC_ESTATE, "batches take orientations per replica");
+    c->adj_steps = 0;   // a recorded adjoint forward no longer matches the orientations
     hmc_status st = upload_tables(c, 0, euler);
     if (st != HMC_OK) return st;
     drop_graphs(c);
@@ -957,6 +982,7 @@ hmc_status hmc_set_spins(hmc_ctx c, const int32_t* spins_dev)
     c->err.clear();
     if (!spins_dev) return state_fail(c, HMC_EINVAL, "null spins");
     if (c->is_batch) return state_fail(c, HMC_ESTATE, "batches take spins per replica");
+    c->adj_steps = 0;
     hmc_status st = upload_spins(c, 0, spins_dev);
     c->have_spins = st == HMC_OK;
     return st;
@@ -972,6 +998,7 @@ hmc_status hmc_set_load(hmc_ctx c, const double sigma_MPa[6])
     for (int I = 0; I < 6; ++I)
         if (!std::isfinite(sigma_MPa[I])) return state_fail(c, HMC_ENUMERIC, "non-finite load");
     if (!load_in_range(sigma_MPa)) return state_fail(c, HMC_EINVAL, "load component beyond 5e4 MPa");
+    c->adj_steps = 0;
     for (auto& R : c->reps) {
         bool nz = false;
         for (int I = 0; I < 6; ++I) {
@@ -1008,6 +1035,7 @@ hmc_status hmc_sweep(hmc_ctx c, int32_t n_sweeps)
     const bool el = elastic_on(c);
     if (el && !c->have_stress) return state_fail(c, HMC_ESTATE, "elastic sweep needs a stress field (refresh first)");
     const bool graphs = c->use_graphs && !c->profiling && c->stream != nullptr;
+    if (n_sweeps > 0) c->adj_steps = 0;   // spins change
     for (int32_t a = 0; a < n_sweeps; ++a) {
         const int64_t s = c->sweep;
         const bool with_refresh = el && (s % c->p.refresh_every) == 0 && c->p.refresh_steps > 0;
@@ -1035,6 +1063,7 @@ hmc_status hmc_colour_pass(hmc_ctx c, int32_t colour, hmc_trial_record* rec)
     if (colour < 0 || colour >= c->colours) return state_fail(c, HMC_EINVAL, "colour out of range");
     if (!c->have_orient || !c->have_spins) return state_fail(c, HMC_ESTATE, "pass needs orientations and spins");
     if (elastic_on(c) && !c->have_stress) return state_fail(c, HMC_ESTATE, "elastic pass needs a stress field");
+    c->adj_steps = 0;   // spins change
     return run_pass(c, colour, rec);
 }
 
@@ -1056,6 +1085,8 @@ hmc_status hmc_set_stress(hmc_ctx c, const float* in)
     if (c->is_batch) return state_fail(c, HMC_ESTATE, "not available on batches");
     hmc_status st = copy_field(c, 0, 6, c->d.sigma, nullptr, in, "set_stress");
     if (st != HMC_OK) return st;
+    HMC_TRY(c, launch_check_finite(c->d.sigma, 6 * c->total_sites, c->d.counters + kNonFinite, kNfInjected, c->stream),
+            "set_stress");
     c->have_stress = true;
     return HMC_OK;
 }
@@ -1080,7 +1111,7 @@ hmc_status hmc_get_macro_strain(hmc_ctx c, double E[6])
     HMC_TRY(c, hipMemcpyAsync(tmp, c->d.state + kE, sizeof tmp, hipMemcpyDeviceToHost, c->stream), "get_macro_strain");
     HMC_TRY(c, hipStreamSynchronize(c->stream), "get_macro_strain");
     std::memcpy(E, tmp, sizeof tmp);
-    return HMC_OK;
+    return report_nonfinite(c);
 }
 
 hmc_status hmc_set_elastic_state(hmc_ctx c, const float* u_dev, const double E_host[6])
@@ -1143,7 +1174,7 @@ hmc_status hmc_get_stats(hmc_ctx c, hmc_stats* out)
     out->accepted = (int64_t)s[kStatAccepted];
     out->screened = (int64_t)s[kStatScreened];
     out->refresh_steps = c->host_refresh_steps;
-    return HMC_OK;
+    return report_nonfinite(c);
 }
 
 hmc_status hmc_reset_stats(hmc_ctx c)
@@ -1215,6 +1246,7 @@ hmc_status hmc_batch_set_replica(hmc_ctx c, int32_t r, const double* euler_host,
     if (!c) return HMC_EINVAL;
     c->err.clear();
     if (bad_rep(c, r) || !euler_host || !spins_dev) return state_fail(c, HMC_EINVAL, "bad replica or null input");
+    c->adj_steps = 0;
     hmc_status st = upload_tables(c, r, euler_host);
     if (st != HMC_OK) return st;
     st = upload_spins(c, r, spins_dev);

@@ -326,7 +326,10 @@ __global__ __launch_bounds__(256) void k_global_final(FinalArgs a)
 }
 
 // One block per replica: stored energy = fixed-order sum of the block partials.
-__global__ __launch_bounds__(256) void k_sum_U(double* state, const double* partials, const RepDev* reps)
+// A non-finite stress or strain anywhere in the replica makes its energy non-finite, which
+// raises kNfGlobal.
+__global__ __launch_bounds__(256) void k_sum_U(double* state, const double* partials, const RepDev* reps,
+                                               uint32_t* nonfinite)
 {
     const RepDev R = reps[blockIdx.x];
     const int t = threadIdx.x;
@@ -334,7 +337,10 @@ __global__ __launch_bounds__(256) void k_sum_U(double* state, const double* part
     for (int b = t; b < R.node_blocks; b += 256) s += partials[(int64_t)(R.node_first + b) * 8];
     const double v[1] = {s};
     const double tot = block_total<1>(v);
-    if (t == 0) state[(int64_t)blockIdx.x * kStateDoubles + kU] = tot;
+    if (t == 0) {
+        state[(int64_t)blockIdx.x * kStateDoubles + kU] = tot;
+        if (!isfinite(tot)) atomicOr(nonfinite, (uint32_t)kNfGlobal);
+    }
 }
 
 struct ReussArgs {
@@ -519,7 +525,8 @@ hipError_t launch_global_final(hmc_ctx_s* c, bool write_sigma)
     a.plane = c->total_sites;
     const int tok = prof_begin(c, kProfRefreshOther);
     hipLaunchKernelGGL(k_global_final, dim3(c->node_blocks), dim3(256), 0, c->stream, a);
-    hipLaunchKernelGGL(k_sum_U, dim3(c->n_rep), dim3(256), 0, c->stream, c->d.state, c->d.partials, c->d.reps);
+    hipLaunchKernelGGL(k_sum_U, dim3(c->n_rep), dim3(256), 0, c->stream, c->d.state, c->d.partials, c->d.reps,
+                       c->d.counters + kNonFinite);
     prof_end(c, tok);
     return hipGetLastError();
 }

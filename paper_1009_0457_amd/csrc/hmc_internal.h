@@ -94,7 +94,10 @@ constexpr double kSumScale = 67108864.0;       // 2^26
 constexpr int kSeqState = 16;
 
 // Counters (uint32): list counts per colour, error flag.
-enum CounterSlot { kListCount = 0, kErrFlag = 8, kLabelChanged = 9, kCounters = 16 };
+enum CounterSlot { kListCount = 0, kErrFlag = 8, kLabelChanged = 9, kNonFinite = 10, kCounters = 16 };
+// Bits of counters[kNonFinite], raised by kernels that meet a non-finite value and reported
+// (then cleared) by the next call that synchronises the stream.
+enum NonFiniteBit { kNfGlobal = 1, kNfZone = 2, kNfInjected = 4 };
 
 // 64-bit statistics slots, kept in kStatCopies copies that blocks pick by index (fewer
 // same-address atomics) and that the host sums.
@@ -185,6 +188,9 @@ namespace hmc {
 
 enum ProfClass { kProfPotts = 0, kProfZone, kProfApply, kProfRefreshStep, kProfRefreshOther, kProfClasses };
 int prof_begin(hmc_ctx_s* c, int cls);   // returns a token (-1 when off)
+// Synchronises the context's stream, reads and clears counters[kNonFinite]; HMC_ENUMERIC (with
+// the context's message set) if any kernel raised it since the last report.
+hmc_status report_nonfinite(hmc_ctx_s* c);
 void prof_end(hmc_ctx_s* c, int token);
 
 // ---- launchers (each returns hipGetLastError of its launch) ----
@@ -195,6 +201,8 @@ hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s);
 hipError_t launch_convert_spins(const int32_t* in, int16_t* out, int64_t n, int32_t Q, uint32_t* err,
                                 hipStream_t s);
 hipError_t launch_export_spins(const int16_t* in, int32_t* out, int64_t n, hipStream_t s);
+// Raises `bit` in *flag if any of the n floats at p is not finite.
+hipError_t launch_check_finite(const float* p, int64_t n, uint32_t* flag, uint32_t bit, hipStream_t s);
 hipError_t launch_potts_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec);
 hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec);
 hipError_t launch_apply_pass(hmc_ctx_s* c, int colour);

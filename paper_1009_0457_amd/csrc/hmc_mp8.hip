@@ -240,14 +240,18 @@ __global__ __launch_bounds__(256) void k_mp8_E(double* state, const double* part
     }
 }
 
-__global__ __launch_bounds__(256) void k_mp8_U(double* state, const double* partials, const RepDev* reps)
+__global__ __launch_bounds__(256) void k_mp8_U(double* state, const double* partials, const RepDev* reps,
+                                                uint32_t* nonfinite)
 {
     const RepDev R = reps[blockIdx.x];
     const int nb = mp8_blocks(R.K);
     double s[1] = {0.0};
     for (int b = threadIdx.x; b < nb; b += 256) s[0] += partials[(int64_t)(R.node_first + b) * 8];
     const double tot = block_total<1>(s);
-    if (threadIdx.x == 0) state[(int64_t)blockIdx.x * kStateDoubles + kU] = tot;
+    if (threadIdx.x == 0) {
+        state[(int64_t)blockIdx.x * kStateDoubles + kU] = tot;
+        if (!isfinite(tot)) atomicOr(nonfinite, (uint32_t)kNfGlobal);   // a non-finite point stress
+    }
 }
 
 Mp8Args mp8_args(hmc_ctx_s* c)
@@ -299,7 +303,7 @@ hipError_t launch_mp8_final(hmc_ctx_s* c, bool write_sigma)
     const int tok = prof_begin(c, kProfRefreshOther);
     hipLaunchKernelGGL(k_mp8_cells<true>, mp8_grid(c), dim3(256), 0, c->stream, a);
     hipLaunchKernelGGL(k_mp8_U, dim3(c->n_rep), dim3(256), 0, c->stream, c->d.state, (const double*)c->d.partials,
-                       (const RepDev*)c->d.reps);
+                       (const RepDev*)c->d.reps, c->d.counters + kNonFinite);
     prof_end(c, tok);
     return hipGetLastError();
 }

@@ -419,6 +419,14 @@ __global__ void k_convert_spins(const int32_t* in, int16_t* out, int64_t n, int3
     }
 }
 
+__global__ void k_check_finite(const float* p, int64_t n, uint32_t* flag, uint32_t bit)
+{
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        bad = bad || !isfinite(p[i]);
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, bit);
+}
+
 __global__ void k_export_spins(const int16_t* in, int32_t* out, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -454,6 +462,12 @@ hipError_t launch_convert_spins(const int32_t* in, int16_t* out, int64_t n, int3
 hipError_t launch_export_spins(const int16_t* in, int32_t* out, int64_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_export_spins, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const float* p, int64_t n, uint32_t* flag, uint32_t bit, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_check_finite, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, p, n, flag, bit);
     return hipGetLastError();
 }
 

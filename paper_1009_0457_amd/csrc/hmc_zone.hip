@@ -39,6 +39,7 @@ struct ZoneArgs {
     uint8_t* acc;
     hmc_trial_record* rec;          // indexed by site_off + site, or null
     unsigned long long* stats;
+    uint32_t* nonfinite;            // counters[kNonFinite]
     int nr;
     int64_t plane;
     float alpha, beta;
@@ -270,6 +271,7 @@ __global__ __launch_bounds__(64) void k_zone(ZoneArgs a)
 #pragma unroll
             for (int I = 0; I < 6; ++I) base += 0.5 * (double)eps[I] * (double)t[I];
             const double dPi = base + part;
+            if (!isfinite(dPi)) atomicOr(a.nonfinite, (uint32_t)kNfZone);
             const double dE = tc.J * (double)ent.gb + tc.lambda * dPi;
             const bool accept = (dE <= 0.0) || ((double)ent.r1 < ldexp(exp(-dE / tc.kT), 32));
             a.acc[e] = accept ? 1 : 0;
@@ -536,6 +538,7 @@ __global__ __launch_bounds__(256, 2) void k_zone_col(ZoneArgs a)
 #pragma unroll
             for (int I = 0; I < 6; ++I) base_e += 0.5 * (double)s_ctr[zs][I] * (double)s_ctr[zs][6 + I];
             const double dPi = base_e + sum;
+            if (!isfinite(dPi)) atomicOr(a.nonfinite, (uint32_t)kNfZone);
             const double dE = tc.J * (double)ent.gb + tc.lambda * dPi;
             const bool accept = (dE <= 0.0) || ((double)ent.r1 < ldexp(exp(-dE / tc.kT), 32));
             a.acc[e] = accept ? 1 : 0;
@@ -857,6 +860,7 @@ __global__ __launch_bounds__(64, H == 1 ? 3 : 2) void k_zone_lane(ZoneArgs a)
 #pragma unroll
             for (int I = 0; I < 6; ++I) base_e += 0.5 * (double)s_ctr[zs][I] * (double)s_ctr[zs][6 + I];
             const double dPi = base_e + sum;
+            if (!isfinite(dPi)) atomicOr(a.nonfinite, (uint32_t)kNfZone);
             const double dE = tc.J * (double)ent.gb + tc.lambda * dPi;
             const bool accept = (dE <= 0.0) || ((double)ent.r1 < ldexp(exp(-dE / tc.kT), 32));
             a.acc[e] = accept ? 1 : 0;
@@ -893,6 +897,7 @@ hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
     a.acc = c->d.accept;
     a.rec = rec;
     a.stats = c->d.stats;
+    a.nonfinite = c->d.counters + kNonFinite;
     a.nr = c->p.zone_steps;
     a.plane = c->total_sites;
     a.alpha = (float)c->p.zone_alpha;

@@ -542,7 +542,10 @@ class Lattice:
         nbytes = hmc_adjoint_workspace_bytes(self.ctx, n_steps, ckpt_every)
         if getattr(self, "adj_ws", None) is None or self.adj_ws.numel() < nbytes:
             self.adj_ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
-        return hmc_elastic_forward(self.ctx, n_steps, ckpt_every, self.adj_ws)
+        U = hmc_elastic_forward(self.ctx, n_steps, ckpt_every, self.adj_ws)
+        # counts forwards: an autograd node remembers the one its backward belongs to
+        self.adj_generation = getattr(self, "adj_generation", 0) + 1
+        return U
 
     def elastic_backward(self, dU=1.0):
         return hmc_elastic_backward(self.ctx, self.adj_ws, dU, self.Q)
@@ -562,12 +565,18 @@ def _make_energy_function():
             lattice.set_load(sigma_MPa.detach().cpu().double().numpy())
             U = lattice.elastic_forward(int(n_steps), int(ckpt_every))
             ctx.lattice = lattice
+            ctx.generation = lattice.adj_generation
             ctx.shapes = (euler.shape, euler.dtype, sigma_MPa.dtype, euler.device, sigma_MPa.device)
             return torch.tensor(U, dtype=torch.float64)
 
         @staticmethod
         def backward(ctx, gU):
             shape, edt, sdt, edev, sdev = ctx.shapes
+            if ctx.lattice.adj_generation != ctx.generation:
+                # the lattice's checkpoints now belong to a later forward (another
+                # stored_elastic_energy call on the same lattice): this node's gradient is gone
+                raise RuntimeError("stored_elastic_energy: another forward ran on this lattice before this "
+                                   "backward; evaluate one energy per lattice per backward")
             ge, gs = ctx.lattice.elastic_backward(float(gU))
             return (torch.from_numpy(ge).reshape(shape).to(dtype=edt, device=edev),
                     torch.from_numpy(gs).to(dtype=sdt, device=sdev), None, None, None)

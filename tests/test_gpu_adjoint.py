@@ -160,3 +160,91 @@ def test_checkpoint_interval_does_not_change_the_gradient():
         assert np.array_equal(ge, out[0][1])
         assert np.array_equal(gs, out[0][2])
 
+
+
+def test_forward_record_is_discarded_by_state_changes():
+    """The backward pass recomputes segments from the forward's checkpoints with the context's
+    current spins, stiffness tables and load; any change of those after the forward must make
+    the backward refuse (HMC_ESTATE) rather than return a gradient of other inputs.  A second
+    backward of the same forward is allowed.  Through autograd, two energies evaluated on one
+    lattice before a backward raise instead of both using the last forward's checkpoints."""
+    K, n, every = 10, 40, 10
+    m = voronoi_polycrystal(K, 6, 12)
+    sig = np.array([80.0, -40.0, 120.0, 15.0, -25.0, 30.0])
+    p = H.hmc_default_params(K, 26, 1)
+    lat = H.Lattice(p, m.Q)
+    lat.set_orientations(m.euler)
+    lat.set_spins(m.spins)
+    lat.set_load(sig)
+    for change in ("orientations", "spins", "load", "sweep", "colour pass"):
+        say(f"[adjoint record] change: {change}")
+        lat.elastic_forward(n, every)
+        g1 = lat.elastic_backward(1.0)
+        g2 = lat.elastic_backward(1.0)
+        assert np.array_equal(g1[0], g2[0]) and np.array_equal(g1[1], g2[1])
+        if change == "orientations":
+            lat.set_orientations(m.euler)
+        elif change == "spins":
+            lat.set_spins(m.spins)
+        elif change == "load":
+            lat.set_load(sig)
+        elif change == "sweep":
+            lat.sweep(1)
+        else:
+            lat.colour_pass(3)
+        with pytest.raises(H.HmcError) as e:
+            lat.elastic_backward(1.0)
+        assert e.value.status == H.HMC_ESTATE
+    lat.set_spins(m.spins)
+    st = torch.tensor(sig, dtype=torch.float64, requires_grad=True)
+    e1 = torch.tensor(m.euler, dtype=torch.float64, requires_grad=True)
+    e2 = torch.tensor(m.euler + 0.01, dtype=torch.float64, requires_grad=True)
+    U = H.stored_elastic_energy(e1, st, lat, n_steps=n, ckpt_every=every) + \
+        H.stored_elastic_energy(e2, st, lat, n_steps=n, ckpt_every=every)
+    with pytest.raises(RuntimeError, match="another forward"):
+        U.backward()
+    # one energy per lattice per backward still works
+    e3 = torch.tensor(m.euler, dtype=torch.float64, requires_grad=True)
+    H.stored_elastic_energy(e3, st, lat, n_steps=n, ckpt_every=every).backward()
+    assert torch.isfinite(e3.grad).all() and e3.grad.abs().max() > 0
+    lat.close()
+
+
+def test_adjoint_matches_oracle_central_differences_at_workload_size():
+    """The adjoint workload itself (64^3, 500 grains, six stress components, a cold start and
+    2000 explicit steps, checkpoints every 50) against FP64 central differences of the oracle's
+    stored energy for the 10 probe grains' 30 Euler angles and the 6 stress components
+    (h = 1e-4 rad, 1e-3 MPa), written by tests/golden/make_adjoint_fd.py from the oracle alone."""
+    from conftest import golden
+
+    g = golden("adjoint64_fd.txt")
+    micro, sig, probe = adjoint_config()
+    K = micro.K
+    p = H.hmc_default_params(K, 26, 2)
+    assert int(g["steps"]) == 2000
+    assert p.glob_alpha == g["glob_alpha"] and p.glob_beta == g["glob_beta"]
+    lat = H.Lattice(p, micro.Q)
+    lat.set_orientations(micro.euler)
+    lat.set_spins(micro.spins)
+    lat.set_load(sig)
+    say(f"[adjoint FD 64^3] K={K} grains={micro.Q} 2000 steps, checkpoints every 50")
+    U = lat.elastic_forward(2000, 50)
+    ge, gs = lat.elastic_backward(1.0)
+    lat.close()
+    assert U == pytest.approx(g["U"], rel=1e-5)
+    scale = np.abs(ge).max()
+    worst = 0.0
+    for q in probe:
+        for k in range(3):
+            fd = g[f"dU_dtheta_{int(q)}_{k}"]
+            err = abs(ge[q, k] - fd)
+            worst = max(worst, err / scale)
+            assert err <= 2e-4 * scale + 1e-4 * abs(fd), (int(q), k, ge[q, k], fd)
+    gscale = np.abs(gs).max()
+    worst_s = 0.0
+    for i in range(6):
+        fd = g[f"dU_dSigma_{i}"]
+        worst_s = max(worst_s, abs(gs[i] - fd) / gscale)
+        assert abs(gs[i] - fd) <= 2e-4 * gscale + 1e-4 * abs(fd), (i, gs[i], fd)
+    say(f"    U gpu {U:.8e} oracle {g['U']:.8e}; worst |adjoint - FD| / max|grad|: angles {worst:.2e}, "
+        f"stress {worst_s:.2e}")

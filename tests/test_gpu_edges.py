@@ -104,3 +104,56 @@ def test_largest_lattice_sampled_parity():
     changed = int(np.count_nonzero(want != spins[sites]))
     say(f"    {changed} of 20000 sampled sites flipped; mismatches {int(np.count_nonzero(post[sites] != want))}")
     assert changed > 0 and np.array_equal(post[sites], want)
+
+
+def test_non_finite_values_are_reported_not_silently_rejected():
+    """A NaN in the stress field would make every affected trial's energy NaN, and both branches
+    of the Metropolis predicate false: a silent rejection.  The kernels raise a device flag
+    instead, which the next synchronising call reports as HMC_ENUMERIC (and clears): for an
+    injected field, for a zone solve that read it, and for a global solve that met one."""
+    K = 12
+    m = voronoi_polycrystal(K, 6, 4)
+    p = H.hmc_default_params(K, 26, 1)
+    p.proposal = 1          # every trial a real flip, so the poisoned site is solved
+    lat = H.Lattice(p, m.Q)
+    lat.set_orientations(m.euler)
+    lat.set_spins(m.spins)
+    lat.set_load([0, 0, 120.0, 0, 0, 0])
+    lat.stress_refresh(300, True)
+    assert lat.stats()["site_trials"] == 0          # a clean state reports nothing
+    site = 5 + K * (3 + K * 7)
+    col = int(O.colour_of(K, 26)[site])
+    sig = lat.get_stress().cpu().numpy()
+    sig[2, site] = np.nan
+    lat.set_stress(sig)
+    with pytest.raises(H.HmcError) as e:
+        lat.stats()
+    assert e.value.status == H.HMC_ENUMERIC and "injected" in str(e.value)
+    lat.stats()                                     # reported once, then cleared
+    before = lat.get_spins().cpu().numpy()
+    rec = lat.colour_pass(col, records=True)
+    assert rec["flags"][site] & 1 and not rec["flags"][site] & 2 and np.isnan(rec["dPi"][site])
+    assert lat.get_spins().cpu().numpy()[site] == before[site]
+    with pytest.raises(H.HmcError) as e:
+        lat.stats()
+    assert e.value.status == H.HMC_ENUMERIC and "zone" in str(e.value)
+    # Other trials read finite stresses.  The zone kernel packs several trials into one
+    # wavefront and moves neighbour values across lanes, where lanes without a voxel multiply
+    # them by zero stiffness: 0 x NaN spreads the NaN to the trials sharing the poisoned trial's
+    # wavefront (at most 4 others for the 3^3 zone), which are rejected like it.  Every other
+    # trial of the pass is finite.
+    others = (O.colour_of(K, 26) == col) & ((rec["flags"] & 4) != 0)
+    others[site] = False
+    spread = others & ~np.isfinite(rec["dPi"])
+    say(f"    trials of the pass: {int(others.sum())}; non-finite besides the poisoned one: {int(spread.sum())}")
+    assert others.sum() > 50 and spread.sum() <= 4
+    assert not np.any(rec["flags"][spread] & 2)
+    # a non-finite displacement reaches the global solve's stress field
+    u = lat.get_displacement().cpu().numpy()
+    u[0, 17] = np.inf
+    lat.set_elastic_state(u, lat.macro_strain())
+    lat.stress_refresh(3, False)
+    with pytest.raises(H.HmcError) as e:
+        lat.energy()
+    assert e.value.status == H.HMC_ENUMERIC and "global" in str(e.value)
+    lat.close()
