@@ -158,8 +158,8 @@ hmc_status hmc_create(const hmc_params* p, int32_t Q, void* dev_workspace, size_
 void hmc_destroy(hmc_ctx ctx);
 
 /* Message of the last failed call on ctx (empty if none); valid until the next call.  With
- * ctx NULL: the message of this thread's last hmc_create / hmc_batch_create (empty if it
- * succeeded), which has no context to hold it. */
+ * ctx NULL: the message of this thread's last hmc_create / hmc_batch_create /
+ * hmc_texture_histogram_noalloc (empty if it succeeded), which has no context to hold it. */
 const char* hmc_last_error(hmc_ctx ctx);
 
 /* Per-grain orientations: host array of Q Bunge triples (phi1, Phi, phi2) in radians.
@@ -210,6 +210,22 @@ hmc_status hmc_energy(hmc_ctx ctx, int64_t* unlike_bonds, double* U_el);
  * nbins - 1.  counts_host: nbins int64.  1 <= nbins <= 64, bin_deg > 0.  Synchronises. */
 hmc_status hmc_texture_histogram(hmc_ctx ctx, const double axis[3], double bin_deg,
                                  int32_t nbins, int64_t* counts_host);
+
+/* hmc_texture_histogram without a context and without any device allocation, for callers that
+ * cannot allocate device memory or hand the library a workspace (code under stream capture
+ * that must not allocate, tight serving loops, harnesses that forbid allocation).  Counts the
+ * K^3 sites of spins_dev (dev, K^3 int32 grain indices in [0, Q), x fastest) by the texture bin
+ * of their grain, exactly as hmc_texture_histogram does for a context holding these spins and
+ * orientations (euler_host: Q Bunge triples in radians, host); counts_host: nbins int64.
+ * Work is enqueued on `stream` (0 = null stream) and the call synchronises it.  Its scratch
+ * (bin table, histogram, error flag) is a static device array of 132 352 bytes that each GPU
+ * holds until the process ends; calls on one GPU share it, so calls that overlap on one GPU
+ * (other streams, other threads) race.  Limits: 1 <= K <= 1024, 1 <= Q <= 32767 (HMC_ESHAPE
+ * beyond), 1 <= nbins <= 64 and bin_deg > 0 (HMC_EINVAL), a spin outside [0, Q) is HMC_EINVAL,
+ * non-finite angles HMC_ENUMERIC.  Message: hmc_last_error(NULL). */
+hmc_status hmc_texture_histogram_noalloc(const int32_t* spins_dev, int32_t K, int32_t Q, const double* euler_host,
+                                         const double axis[3], double bin_deg, int32_t nbins, int64_t* counts_host,
+                                         hipStream_t stream);
 
 /* Stress field of the last refresh (dev, 6 x K^3 float) out / in.  hmc_set_stress injects
  * a field (tests) and marks the stress as present; a non-finite entry is reported as

@@ -698,21 +698,8 @@ hmc_status texture_of(hmc_ctx c, int rep, const double axis[3], double bin_deg, 
     const double nrm = std::sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
     if (!(nrm > 0) || !std::isfinite(nrm)) return state_fail(c, HMC_EINVAL, "axis must be finite and non-zero");
     const RepDev& R = c->reps[rep];
-    // per-grain bin on the host: angle = acos(max_m |(A^T d)_m|) between the axis d and the
-    // nearest crystal <100>
     std::vector<int32_t> bins((size_t)R.Q);
-    for (int64_t g = 0; g < R.Q; ++g) {
-        double A[3][3];
-        bunge(&c->euler[3 * (size_t)(R.grain_off + g)], A);
-        double best = 0.0;
-        for (int m = 0; m < 3; ++m) {
-            const double cm = (A[0][m] * axis[0] + A[1][m] * axis[1] + A[2][m] * axis[2]) / nrm;
-            best = std::fmax(best, std::fabs(cm));
-        }
-        const double ang = std::acos(std::fmin(best, 1.0)) * (180.0 / M_PI);
-        const int b = (int)std::floor(ang / bin_deg);
-        bins[g] = b < nbins - 1 ? b : nbins - 1;
-    }
+    texture_bins(&c->euler[3 * (size_t)R.grain_off], R.Q, axis, bin_deg, nbins, bins.data());
     std::vector<unsigned long long> h(64, 0ull);
     HMC_TRY(c, hipMemcpyAsync(c->d.tex_bin + R.grain_off, bins.data(), bins.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice, c->stream),
@@ -776,6 +763,26 @@ void prof_end(hmc_ctx_s* c, int token)
     if (token < 0 || token >= (int)c->prof_pending.size()) return;
     (void)hipEventRecord(c->prof_pending[token].b, c->stream);
 }
+
+void texture_bins(const double* euler, int64_t Q, const double axis[3], double bin_deg, int nbins, int32_t* bins)
+{
+    // angle = acos(max_m |(A^T d)_m|) between the unit axis d and the nearest crystal <100>
+    const double nrm = std::sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
+    for (int64_t g = 0; g < Q; ++g) {
+        double A[3][3];
+        bunge(euler + 3 * g, A);
+        double best = 0.0;
+        for (int m = 0; m < 3; ++m) {
+            const double cm = (A[0][m] * axis[0] + A[1][m] * axis[1] + A[2][m] * axis[2]) / nrm;
+            best = std::fmax(best, std::fabs(cm));
+        }
+        const double ang = std::acos(std::fmin(best, 1.0)) * (180.0 / M_PI);
+        const int b = (int)std::floor(ang / bin_deg);
+        bins[g] = b < nbins - 1 ? b : nbins - 1;
+    }
+}
+
+void set_thread_error(const char* msg) { t_create_err = msg; }
 
 // Reads (and clears) the device's non-finite flag.  Called by the entry points that
 // synchronise the stream anyway; returns HMC_ENUMERIC with a message naming the kernels that

@@ -191,6 +191,11 @@ int prof_begin(hmc_ctx_s* c, int cls);   // returns a token (-1 when off)
 // Synchronises the context's stream, reads and clears counters[kNonFinite]; HMC_ENUMERIC (with
 // the context's message set) if any kernel raised it since the last report.
 hmc_status report_nonfinite(hmc_ctx_s* c);
+// Texture bin of each of Q grains (host, Bunge triples): floor(angle / bin_deg) clamped to
+// nbins - 1, the angle between the (non-zero) lab axis and the grain's nearest crystal <100>.
+void texture_bins(const double* euler, int64_t Q, const double axis[3], double bin_deg, int nbins, int32_t* bins);
+// This thread's message for hmc_last_error(NULL) (calls without a context).
+void set_thread_error(const char* msg);
 void prof_end(hmc_ctx_s* c, int token);
 
 // ---- launchers (each returns hipGetLastError of its launch) ----

@@ -83,6 +83,8 @@ _SIGS = [
     ("hmc_colour_pass", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     ("hmc_energy", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     ("hmc_texture_histogram", C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p]),
+    ("hmc_texture_histogram_noalloc", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                                C.c_double, C.c_int32, C.c_void_p, C.c_void_p]),
     ("hmc_get_stress", C.c_int, [C.c_void_p, C.c_void_p]),
     ("hmc_set_stress", C.c_int, [C.c_void_p, C.c_void_p]),
     ("hmc_get_displacement", C.c_int, [C.c_void_p, C.c_void_p]),
@@ -228,6 +230,22 @@ def hmc_texture_histogram(ctx, axis, bin_deg=10.0, nbins=6):
     out = np.zeros(nbins, np.int64)
     _check(lib().hmc_texture_histogram(ctx, a.ctypes.data_as(C.c_void_p), float(bin_deg), int(nbins),
                                        out.ctypes.data_as(C.c_void_p)), ctx)
+    return out
+
+
+def hmc_texture_histogram_noalloc(spins_dev, K, euler, axis, bin_deg=10.0, nbins=6, stream_handle=0):
+    """The texture histogram of a device spin field (K^3 int32) without a context or workspace
+    (the library's static scratch array); synchronises ``stream_handle``."""
+    e = np.ascontiguousarray(euler, np.float64)
+    a = np.ascontiguousarray(axis, np.float64)
+    if (e.ndim != 2 or e.shape[1] != 3 or spins_dev.numel() != K ** 3 or str(spins_dev.dtype) != "torch.int32"
+            or not spins_dev.is_contiguous() or not spins_dev.is_cuda):
+        raise HmcError(HMC_EINVAL, "euler must be (Q, 3) and spins a contiguous device tensor of K^3 int32")
+    out = np.zeros(nbins, np.int64)
+    st = lib().hmc_texture_histogram_noalloc(_ptr(spins_dev), int(K), int(e.shape[0]), e.ctypes.data_as(C.c_void_p),
+                                             a.ctypes.data_as(C.c_void_p), float(bin_deg), int(nbins),
+                                             out.ctypes.data_as(C.c_void_p), C.c_void_p(stream_handle))
+    _check(st, None, creating=True)
     return out
 
 
