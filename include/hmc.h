@@ -75,7 +75,9 @@ typedef struct {
                                1 one wavefront per trial, 2 node columns across a
                                256-lane work-group (h <= 2), 3 node columns of whole trials per
                                wavefront, x neighbours exchanged by cross-lane moves
-                               (1 <= h <= 3).  Other values: HMC_EINVAL. */
+                               (1 <= h <= 3), one wavefront per work-group; 4 and 5 the same
+                               kernel with two and four wavefronts (twice and four times the
+                               trials) per work-group.  Other values: HMC_EINVAL. */
     int32_t zone_screen;    /* 1: skip the zone solve of a trial whose rejection is already
                                certain: the point-zone energy 1/2 sigma_p.(S_old - S_new) sigma_p
                                is a lower bound of the zone's (its relaxation only adds
@@ -200,14 +202,17 @@ hmc_status hmc_sweep(hmc_ctx ctx, int32_t n_sweeps);
  * record of every site of this colour is written at its site index (others untouched). */
 hmc_status hmc_colour_pass(hmc_ctx ctx, int32_t colour, hmc_trial_record* records_dev);
 
-/* Number of unlike bonds (each bond once) and the stored elastic energy
- * 1/2 sum_v eps_v . C_{q_v} eps_v (GPa*voxel) of the current spins and displacement state
- * (0 when the elastic term has no state).  Synchronises. */
+/* Number of unlike bonds (each bond once: the grain-boundary energy of Sec. 3, Eq. H_1, is J
+ * times it) and the stored elastic energy 1/2 sum_v eps_v . C_{q_v} eps_v (GPa*voxel; the
+ * strain energy of Sec. 2, Eq. ela_hooke, summed over the voxels) of the current spins and
+ * displacement state (0 when the elastic term has no state).  Synchronises. */
 hmc_status hmc_energy(hmc_ctx ctx, int64_t* unlike_bonds, double* U_el);
 
 /* Volume-weighted histogram of the angle between the unit lab axis and the nearest crystal
  * <100> direction of each site's grain: bin b = floor(angle / bin_deg), clamped to
- * nbins - 1.  counts_host: nbins int64.  1 <= nbins <= 64, bin_deg > 0.  Synchronises. */
+ * nbins - 1 (the texture measure of Sec. 7: for rotations about z and a load along x, the
+ * angle is the deviation from the nearest soft orientation that Eq. text_evl's density is
+ * written in).  counts_host: nbins int64.  1 <= nbins <= 64, bin_deg > 0.  Synchronises. */
 hmc_status hmc_texture_histogram(hmc_ctx ctx, const double axis[3], double bin_deg,
                                  int32_t nbins, int64_t* counts_host);
 
@@ -278,7 +283,8 @@ hmc_status hmc_get_kernel_times(hmc_ctx ctx, hmc_kernel_times* out);
  * refresh_every-th sweep) once into HIP graphs and replay them on later hmc_sweep calls.
  * Needs a context created on a non-null stream (HMC_EINVAL otherwise).  Graphs are
  * dropped and re-captured whenever orientations, spins, loads or the elastic state change.
- * Kernel timing (hmc_set_profiling) bypasses the graphs while it is on. */
+ * Kernel timing (hmc_set_profiling) bypasses the graphs while it is on: HIP events recorded
+ * by a captured graph carry no timestamps on this platform. */
 hmc_status hmc_set_graphs(hmc_ctx ctx, int32_t enable);
 
 /* ---- Batches: many independent replicas in every launch -----------------------------

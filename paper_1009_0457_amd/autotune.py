@@ -16,13 +16,20 @@ from __future__ import annotations
 TILE_DEPTHS = (1, 2, 4, 8, 16, 32)
 
 
+# zone_variant -> (kernel, trials per work-group as a multiple of one wavefront's)
+ZONE_SHAPES = {1: ("one wavefront per trial", 1), 2: ("node columns, 256-lane work-group", 1),
+               3: ("lane shifts", 1), 4: ("lane shifts", 2), 5: ("lane shifts", 4)}
+
+
 def zone_variants_for(zone_h: int) -> list[int]:
-    """Kernels the library accepts for this zone half-width (see ``hmc_params.zone_variant``)."""
+    """Kernels and work-group shapes the library accepts for this zone half-width (see
+    ``hmc_params.zone_variant``): the lane-shift kernel with one, two or four wavefronts (of
+    whole trials) per work-group, the node-column kernel and the one-wavefront-per-trial one."""
     out = [1]
     if zone_h <= 2:
         out.append(2)
     if zone_h >= 1:
-        out.append(3)
+        out += [3, 4, 5]
     return out
 
 
@@ -44,7 +51,8 @@ def tune_zone_variant(ctx, zone_h: int, sweeps: int = 1, candidates=None) -> dic
     best = min(score, key=score.get)
     ctx.set_zone_variant(best)
     ctx.reset_stats()
-    return {"best": best, "ms_per_solve": {str(k): v for k, v in score.items()}}
+    return {"best": best, "ms_per_solve": {str(k): v for k, v in score.items()},
+            "shapes": {str(k): {"kernel": ZONE_SHAPES[k][0], "wavefronts_per_group": ZONE_SHAPES[k][1]} for k in score}}
 
 
 def tune_tile_depth(build, steps: int = 20, depths=TILE_DEPTHS) -> dict:

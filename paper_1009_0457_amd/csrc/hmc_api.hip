@@ -29,8 +29,8 @@ hmc_status check_common(const hmc_params* p)
     if (p->neighbors != 6 && p->neighbors != 26) return HMC_EINVAL;
     if (p->proposal != 0 && p->proposal != 1) return HMC_EINVAL;
     if (p->zone_h < 0 || p->zone_h > 3) return HMC_EINVAL;
-    if (p->zone_variant < 0 || p->zone_variant > 3 || (p->zone_variant == 2 && p->zone_h > 2) ||
-        (p->zone_variant == 3 && p->zone_h < 1))
+    if (p->zone_variant < 0 || p->zone_variant > 5 || (p->zone_variant == 2 && p->zone_h > 2) ||
+        (p->zone_variant >= 3 && p->zone_h < 1))
         return HMC_EINVAL;
     if (p->zone_screen != 0 && p->zone_screen != 1) return HMC_EINVAL;
     if (p->refresh_tile_z != 0 && p->refresh_tile_z != 1 && p->refresh_tile_z != 2 && p->refresh_tile_z != 4 &&

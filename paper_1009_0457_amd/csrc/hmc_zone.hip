@@ -601,13 +601,13 @@ __device__ __forceinline__ void node_forces(float L0, float L1, float L2, float 
     ny = Ab + Db;
 }
 
-template <int H>
+template <int H, int WAVES = 1>
 struct LaneShiftShape {
     static constexpr int N = 2 * H + 1, NN = N + 1;
     static constexpr int LT = NN * N;                   // lanes per trial
     static constexpr int TW = 64 / LT;                  // trials per wavefront
-    static constexpr int THREADS = 64;                  // one wavefront per work-group
-    static constexpr int Z = TW;                        // trials per work-group
+    static constexpr int THREADS = 64 * WAVES;          // wavefronts per work-group
+    static constexpr int Z = TW * WAVES;                // trials per work-group
     static constexpr int ROW = NN * NN;                 // floats per (component, layer) row
     static constexpr int BODY = 3 * NN * ROW;
     // block stride: >= BODY + NN (zero gap), and = LT (mod 64) for conflict-free addressing
@@ -619,10 +619,12 @@ struct LaneShiftShape {
 // few registers spilled, 0.357 against 0.418 ms per colour launch at 2; h = 2 runs 2 (3 spill
 // 131 registers and take 9.6 against 5.7 ms); h = 3 (7 x 21 stiffness registers per lane)
 // spills some 34 registers at 2 and still beats 1 without spills (36.9 against 44.2 ms).
-template <int H>
-__global__ __launch_bounds__(64, H == 1 ? 3 : 2) void k_zone_lane(ZoneArgs a)
+// WAVES wavefronts per work-group (1 by default; 2 and 4 are shapes for the autotuner): each
+// wavefront holds its own trials, the work-group shares its barriers.
+template <int H, int WAVES>
+__global__ __launch_bounds__(64 * WAVES, H == 1 ? 3 : 2) void k_zone_lane(ZoneArgs a)
 {
-    using S = LaneShiftShape<H>;
+    using S = LaneShiftShape<H, WAVES>;
     constexpr int N = S::N, NN = S::NN, LT = S::LT, TW = S::TW, Z = S::Z, ROW = S::ROW, TB = S::TB;
     static_assert(H >= 1 && H <= 3 && TW >= 1 && 3 * NN <= LT, "lane-shift variant needs 1 <= h <= 3");
     static_assert(TB % 64 == LT % 64 && TB >= S::BODY + NN, "block stride");
@@ -631,7 +633,6 @@ __global__ __launch_bounds__(64, H == 1 ? 3 : 2) void k_zone_lane(ZoneArgs a)
     __shared__ float s_u[(Z + 1) * TB];                   // node displacements
     __shared__ __align__(16) float s_n[S::PAD + (Z + 1) * TB];   // forces sent to the +y neighbour
     __shared__ float s_ctr[Z][18];                        // eps_p[6], t[6], -alpha/4 t[6]
-    static_assert(S::THREADS == 64, "one wavefront per work-group");
     static_assert(sizeof(s_n) >= S::THREADS * sizeof(double), "energy scratch does not fit");
     double* s_red = reinterpret_cast<double*>(s_n);
 
@@ -873,12 +874,12 @@ __global__ __launch_bounds__(64, H == 1 ? 3 : 2) void k_zone_lane(ZoneArgs a)
         }
         __syncthreads();   // LDS is reused by the next group of trials
     }
-    // one wavefront per work-group: sum the lane counts across it
+    // sum the lane counts across each wavefront; one atomic per wavefront
     for (int off = 32; off > 0; off >>= 1) {
         n_solved += __shfl_xor(n_solved, off);
         n_accepted += __shfl_xor(n_accepted, off);
     }
-    if (t == 0 && n_solved) {
+    if (li == 0 && n_solved) {
         atomicAdd(&a.stats[stat_copy(blockIdx.x) + kStatSolves], (unsigned long long)n_solved);
         if (n_accepted) atomicAdd(&a.stats[stat_copy(blockIdx.x) + kStatAccepted], (unsigned long long)n_accepted);
     }
@@ -906,11 +907,13 @@ hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
     // automatic: lane shifts for h >= 1 (at h = 3, 1.67e6 solves/s against 3.75e5 for a
     // wavefront per trial, 128^3 workload, n_r = 400); node columns for h = 0
     const int v = c->p.zone_variant;
-    const bool laneshift = (v == 0 && h >= 1) || v == 3;
+    const bool laneshift = (v == 0 && h >= 1) || v == 3 || v == 4 || v == 5;
     const bool column = !laneshift && ((v == 0 && h <= 2) || v == 2);
     const int tok = prof_begin(c, kProfZone);
     if (laneshift) {
-        const int per_wg = h == 1 ? LaneShiftShape<1>::Z : h == 2 ? LaneShiftShape<2>::Z : LaneShiftShape<3>::Z;
+        const int waves = v == 4 ? 2 : v == 5 ? 4 : 1;
+        const int tw = h == 1 ? LaneShiftShape<1>::TW : h == 2 ? LaneShiftShape<2>::TW : LaneShiftShape<3>::TW;
+        const int per_wg = tw * waves;
         int64_t g = (c->max_list + per_wg - 1) / per_wg;
         // many more work-groups than resident slots: a work-group takes at most a group or
         // two, and the hardware's dispatch balances the tail (measured: 8192 -> 65536
@@ -919,13 +922,21 @@ hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
         const int64_t cap = 65536;
         if (g > cap) g = cap;
         if (g < 1) g = 1;
-        const dim3 grid((unsigned)g), block(LaneShiftShape<2>::THREADS);
-        switch (h) {
-            case 1: hipLaunchKernelGGL(k_zone_lane<1>, grid, block, 0, c->stream, a); break;
-            case 2: hipLaunchKernelGGL(k_zone_lane<2>, grid, block, 0, c->stream, a); break;
-            case 3: hipLaunchKernelGGL(k_zone_lane<3>, grid, block, 0, c->stream, a); break;
+        const dim3 grid((unsigned)g), block(64 * waves);
+#define HMC_LANE(HH, WW) hipLaunchKernelGGL((k_zone_lane<HH, WW>), grid, block, 0, c->stream, a)
+        switch (h * 8 + waves) {
+            case 9: HMC_LANE(1, 1); break;
+            case 10: HMC_LANE(1, 2); break;
+            case 12: HMC_LANE(1, 4); break;
+            case 17: HMC_LANE(2, 1); break;
+            case 18: HMC_LANE(2, 2); break;
+            case 20: HMC_LANE(2, 4); break;
+            case 25: HMC_LANE(3, 1); break;
+            case 26: HMC_LANE(3, 2); break;
+            case 28: HMC_LANE(3, 4); break;
             default: return hipErrorInvalidValue;
         }
+#undef HMC_LANE
     } else if (column) {
         const int nn = 2 * h + 2, per_wg = 256 / (nn * nn);
         int64_t g = (c->max_list + per_wg - 1) / per_wg;

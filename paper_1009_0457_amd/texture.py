@@ -23,8 +23,8 @@ import math
 import numpy as np
 
 __all__ = ["signed_deviation", "orientation_fractions", "gaussian_density", "fit_g", "fit_variance_law",
-           "young_x", "young_phi", "modulus_ratio", "modulus_density", "soft_fraction", "mean_abs_deviation",
-           "texture_run"]
+           "young_x", "young_phi", "modulus_ratio", "soft_fraction", "mean_abs_deviation",
+           "texture_run", "orientation_energy_profile", "single_crystal_energy"]
 
 
 def signed_deviation(phi_deg):
@@ -103,14 +103,6 @@ def modulus_ratio(euler, C=(250.8, 150.0, 123.5), axis=0):
     return 1.0 / S[:, axis, axis] / C[0]
 
 
-def modulus_density(x, fractions, lo=0.55, hi=0.929, nbins=91):
-    """Volume fractions binned by modulus ratio x on [lo, hi] (Sec. 7 integrates its 999
-    orientations into 91 points); returns (bin centres, fractions per bin)."""
-    edges = np.linspace(lo, hi, nbins + 1)
-    k = np.clip(np.searchsorted(edges, np.asarray(x, float), side="right") - 1, 0, nbins - 1)
-    return 0.5 * (edges[1:] + edges[:-1]), np.bincount(k, weights=np.asarray(fractions, float), minlength=nbins)
-
-
 def soft_fraction(phi_deg, fractions, within_deg=10.0):
     """Volume fraction within within_deg of a soft orientation."""
     return float(np.asarray(fractions)[np.abs(signed_deviation(phi_deg)) <= within_deg].sum())
@@ -126,7 +118,7 @@ def mean_abs_deviation(phi_deg, fractions):
 def texture_run(K=100, runs=10, *, Q=91, coarsen_steps=100, kT=2.6, load_MPa=30.0, substeps=75,
                 refresh_steps=200, neighbors=26, zone_h=2, zone_steps=200, lambda_scale=1.0, screen=True,
                 record_every=5, C=(250.8, 150.0, 123.5), seed=300, philox_seed=400, profile=False,
-                tile_z=0, euler=None, material_points=1, device="cuda:0"):
+                tile_z=0, euler=None, material_points=1, keep_start=False, device="cuda:0"):
     """Sec. 7's texture experiment as one fused batch of ``runs`` replicas on the library.
 
     Every site starts as an independent random choice among Q orientations (``euler``, Q Bunge
@@ -141,8 +133,9 @@ def texture_run(K=100, runs=10, *, Q=91, coarsen_steps=100, kT=2.6, load_MPa=30.
 
     Returns a dict: t (sweeps since the end of coarsening, every record_every), fractions
     (len(t), runs, Q) volume fractions per orientation, the library's counters, the wall
-    time of the loaded phase (seconds, spin read-backs included) and, with ``profile``, the
-    library's kernel times of that phase."""
+    time of the loaded phase (seconds, spin read-backs included), with ``profile`` the
+    library's kernel times of that phase and with ``keep_start`` the coarsened spins of every
+    run (start_spins: a list of K^3 int32 arrays)."""
     import time
 
     from . import hmc as H
@@ -172,6 +165,7 @@ def texture_run(K=100, runs=10, *, Q=91, coarsen_steps=100, kT=2.6, load_MPa=30.
         def snapshot():
             return np.stack([orientation_fractions(b.get_spins(r).cpu().numpy(), Q) for r in range(runs)])
 
+        starts = [b.get_spins(r).cpu().numpy() for r in range(runs)] if keep_start else None
         ts, fr = [0], [snapshot()]
         b.reset_stats()
         if profile:
@@ -195,4 +189,55 @@ def texture_run(K=100, runs=10, *, Q=91, coarsen_steps=100, kT=2.6, load_MPa=30.
             kt = b.kernel_times()
     finally:
         b.close()
-    return {"t": np.array(ts), "fractions": np.array(fr), "stats": st, "wall_s": wall, "kernel_times": kt}
+    return {"t": np.array(ts), "fractions": np.array(fr), "stats": st, "wall_s": wall, "kernel_times": kt,
+            "start_spins": starts}
+
+
+def orientation_energy_profile(spins, euler, load_MPa, K, C=(250.8, 150.0, 123.5), n_steps=2000, ckpt_every=50,
+                               device="cuda:0"):
+    """The elastic driving force of every orientation of a polycrystal under uniaxial tension
+    along x, from the adjoint of the global solve (extension 3).
+
+    For orientations that are rotations about z (Bunge (phi, 0, 0)) on an increasing grid of
+    phi, the adjoint gives dU/dphi_q summed over the sites of orientation q.  Under stress
+    control the envelope identity makes it sum_v 1/2 sigma_v . (dS_q/dphi) sigma_v, so its value
+    per site, F_q, is the slope of the orientation's stored energy density w(phi) =
+    1/2 sigma . S(phi) sigma as the surrounding polycrystal loads it.  Integrating F over phi
+    gives w up to a constant; w_q - <w> (volume-weighted mean) is the energy a site gains by
+    taking orientation q, the term that drives the soft orientations' growth in Eqs. (1ddri)
+    and (varn_eqn).
+
+    Returns a dict: phi (deg), volume (sites per orientation), F (GPa per rad per site),
+    w (GPa per site, relative to the first orientation), D = w - <w> (GPa per site)."""
+    from . import hmc as H
+
+    e = np.ascontiguousarray(euler, np.float64)
+    if np.any(e[:, 1:] != 0.0) or np.any(np.diff(e[:, 0]) <= 0):
+        raise ValueError("orientations must be rotations about z on an increasing grid")
+    Q = e.shape[0]
+    p = H.hmc_default_params(K, 26, 2)
+    p.C11, p.C12, p.C44 = C
+    r = H.hmc_default_replica(p, K, Q)
+    p.glob_alpha, p.glob_beta, p.glob_alphaE = r.glob_alpha, r.glob_beta, r.glob_alphaE
+    lat = H.Lattice(p, Q, device=device)
+    try:
+        lat.set_spins(np.asarray(spins, np.int32))
+        neg = H.orientation_driving_force(lat, e, [load_MPa, 0, 0, 0, 0, 0], n_steps, ckpt_every)
+    finally:
+        lat.close()
+    vol = np.bincount(np.asarray(spins).ravel(), minlength=Q).astype(float)
+    F = -neg[:, 0] / np.maximum(vol, 1.0)
+    phi = np.degrees(e[:, 0])
+    w = np.concatenate([[0.0], np.cumsum(0.5 * (F[1:] + F[:-1]) * np.diff(e[:, 0]))])
+    D = w - (vol * w).sum() / vol.sum()
+    return {"phi": phi, "volume": vol, "F": F, "w": w, "D": D}
+
+
+def single_crystal_energy(euler, load_MPa, C=(250.8, 150.0, 123.5), axis=0):
+    """1/2 sigma^2 S'_aa of each orientation under uniaxial stress sigma along a lab axis: the
+    stored energy density of an isolated crystal (GPa per site), from the library's tables."""
+    from . import hmc as H
+
+    _, S = H.hmc_grain_tables(np.ascontiguousarray(euler, np.float64), *C)
+    s = load_MPa * 1e-3
+    return 0.5 * s * s * S[:, axis, axis]

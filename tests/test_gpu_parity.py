@@ -460,8 +460,8 @@ def test_elastic_lockstep_other_zone_kernels_at_workload_size(variant):
     assert errs.report(f"full-64 variant {variant}") > 500
 
 
-@pytest.mark.parametrize("h,variant", [(0, 0), (0, 1), (1, 0), (1, 2), (2, 0), (2, 1), (2, 2), (3, 0), (3, 1),
-                                       (3, 3)])
+@pytest.mark.parametrize("h,variant", [(0, 0), (0, 1), (1, 0), (1, 2), (1, 4), (2, 0), (2, 1), (2, 2), (2, 4),
+                                       (2, 5), (3, 0), (3, 1), (3, 3), (3, 5)])
 def test_elastic_lockstep_zone_sizes(h, variant):
     """Every zone size the library accepts, both kernels, on a lattice whose edge is not a
     multiple of the zone (ragged wrap-around), with uniform proposals (many solves)."""

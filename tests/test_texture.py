@@ -84,10 +84,3 @@ def test_modulus_ratio_about_z_follows_the_papers_fit(paper):
     assert abs(x[0] - paper["x_low"]) < 5e-3 and abs(x[45] - paper["x_high"]) < 5e-3
     assert np.abs(x - fit).max() < 5e-3
     assert np.allclose(x, x[::-1], atol=1e-12)          # E(phi) = E(90 - phi)
-
-
-def test_modulus_density_bins():
-    x = np.array([0.55, 0.6, 0.929, 0.7, 0.7])
-    f = np.array([0.1, 0.2, 0.3, 0.15, 0.25])
-    c, d = T.modulus_density(x, f, nbins=10)
-    assert abs(d.sum() - 1.0) < 1e-12 and d[0] == pytest.approx(0.1) and d[-1] == pytest.approx(0.3)
