@@ -76,6 +76,8 @@ def parse():
                     help="neighbor: spin of a random neighbour slot (workload default); uniform: any other "
                          "state, which makes every trial a real flip (zone-solve saturation)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--saturation-steps", type=int, default=4,
+                    help="large: sweeps of the uniform-proposal (every trial a zone solve) saturation line; 0 = off")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--K", type=int, default=0, help="override the lattice edge (diagnostics only)")
     ap.add_argument("--workload", choices=["large", "batched", "adjoint", "potts", "refresh", "growth", "texture"], default="large",
@@ -107,16 +109,31 @@ def parse():
     return ap.parse_args()
 
 
+def cpu_model():
+    """The host CPU's model name (first 'model name' line of /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(lat, p, micro, seconds):
-    """The FP64 oracle, single thread, on a bounded sample of the same workload: random
-    site-trials of one colour pass from the GPU's current state, plus one explicit step of
-    the global solve; combined into site-trials/s of whole sweeps (K^3 trials plus
-    refresh_steps/refresh_every explicit steps per sweep)."""
+    """The FP64 oracle on a bounded sample of the same workload: random site-trials of one
+    colour pass from the GPU's current state, plus one explicit step of the global solve;
+    combined into site-trials/s of whole sweeps (K^3 trials plus refresh_steps/refresh_every
+    explicit steps per sweep).  Serial (one thread: `value`), and as an aggregate of P threads
+    each running the serial oracle on a disjoint part of the same pass's sites (P = the host's
+    hardware threads, at most 16)."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
 
     import oracle as O
 
     K = p.K
+    lat.synchronize()
     spins = lat.get_spins().cpu().numpy()
     sig = lat.get_stress().cpu().numpy().astype(np.float64)
     s = lat.sweep_index()
@@ -147,6 +164,19 @@ def cpu_baseline(lat, p, micro, seconds):
     O.global_solve(K, spins, Ct, St, np.zeros(6), 1, False, p.glob_alpha, p.glob_beta, p.glob_alphaE, u=u, E=E)
     t_step = time.perf_counter() - t0
     t_sweep = K ** 3 * (t_trials / done) + (p.refresh_steps / p.refresh_every) * t_step
+    # P threads: each a serial oracle call on its own chunk of further sites of the same pass
+    # (the library call releases the interpreter lock); trials per chunk sized from the serial
+    # rate so that the wall time is about seconds / 3
+    P = max(1, min(16, os.cpu_count() or 1))
+    per = max(8, int(done / t_trials * seconds / 3))
+    rest = sites[done:]
+    chunks = [rest[i * per:(i + 1) * per] for i in range(P) if i * per < rest.size]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(len(chunks)) as ex:
+        list(ex.map(lambda c: O.trials(prm, spins, Ct, St, sig, s, c), chunks))
+    t_par = time.perf_counter() - t0
+    n_par = int(sum(c.size for c in chunks))
+    t_sweep_par = K ** 3 * (t_par / n_par) + (p.refresh_steps / p.refresh_every) * t_step / len(chunks)
     return {
         "value": K ** 3 / t_sweep,
         "unit": "site-trials/s",
@@ -155,7 +185,73 @@ def cpu_baseline(lat, p, micro, seconds):
         "sample": (f"{done} random site-trials of colour pass 0 at sweep {s} from the GPU state "
                    f"({t_trials:.1f} s) + 1 explicit global step at {K}^3 ({t_step:.1f} s), combined as "
                    f"K^3 trials + {p.refresh_steps}/{p.refresh_every} steps per sweep; serial FP64 C, -O2"),
+        "cpu_model": cpu_model(),
+        "host_threads": os.cpu_count(),
+        "aggregate": {"value": K ** 3 / t_sweep_par, "cores": len(chunks),
+                      "sample": f"{n_par} further site-trials of the same pass in {len(chunks)} threads, one serial "
+                                f"oracle call per thread on a disjoint chunk ({t_par:.1f} s wall); the explicit "
+                                f"step taken as the serial one divided by the threads"},
     }
+
+
+def small_configs():
+    """The two small workloads end to end, on the GPU and in the serial oracle: the 16^3 tiny
+    workload (6 neighbours, 8 grains, 100 MPa along z, 3^3 zone x 50 steps, a cold refresh and
+    then a warm 200-step refresh before every one of its 10 sweeps) and the 64^3 workload's
+    zero-load twin (26 neighbours, 500 grains, 100 sweeps; spins must agree bit for bit)."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_1009_0457_amd import hmc as H
+    from paper_1009_0457_amd.synth import full_config, tiny_config
+
+    out = {}
+    for c in (tiny_config(), full_config().zero_load()):
+        m = c.microstructure()
+        elastic = bool(np.any(c.sigma_MPa != 0))
+        p = H.hmc_default_params(c.K, c.neighbors, c.zone_h)
+        p.kT, p.refresh_every, p.zone_steps, p.seed = c.kT, c.refresh_every, c.zone_steps, c.philox_seed
+        if not elastic:
+            p.lambda_el = 0.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat = H.Lattice(p, m.Q)
+        lat.set_orientations(m.euler)
+        lat.set_spins(m.spins)
+        lat.set_load(c.sigma_MPa)
+        if elastic:
+            lat.stress_refresh(-1, True)
+        lat.sweep(c.sweeps)
+        gpu_spins = lat.get_spins().cpu().numpy()
+        t_gpu = time.perf_counter() - t0
+        lat.close()
+        Ct, St, _ = O.tables(m.euler, p.C11, p.C12, p.C44)
+        prm = O.make_params(c.K, c.neighbors, m.Q, proposal=p.proposal, h=p.zone_h, nr=p.zone_steps, elastic=elastic,
+                            R=p.refresh_every, n_warm=p.refresh_steps, J=p.J, kT=p.kT, lambda_el=p.lambda_el,
+                            zone_alpha=p.zone_alpha, zone_beta=p.zone_beta, glob_alpha=p.glob_alpha,
+                            glob_beta=p.glob_beta, glob_alphaE=p.glob_alphaE, Sigma=np.asarray(c.sigma_MPa) * 1e-3,
+                            seed=p.seed)
+        q = m.spins.copy()
+        t0 = time.perf_counter()
+        if elastic:
+            u, E, sig, _ = O.global_solve(c.K, q, Ct, St, np.asarray(c.sigma_MPa) * 1e-3, p.cold_steps, True,
+                                          p.glob_alpha, p.glob_beta, p.glob_alphaE)
+            u, E, sig = u.ravel().copy(), E.copy(), sig.ravel().copy()
+        else:
+            u = E = sig = np.zeros(1)
+            E = np.zeros(6)
+        O.sweeps(prm, q, Ct.ravel() if elastic else np.zeros(36 * m.Q), St.ravel() if elastic else np.zeros(36 * m.Q),
+                 u, E, sig, 0, c.sweeps)
+        t_ora = time.perf_counter() - t0
+        n = c.sweeps * c.K ** 3
+        out[c.name] = {"site_trials": n, "gpu_s": t_gpu, "oracle_s": t_ora,
+                       "gpu_site_trials_per_s": n / t_gpu, "oracle_site_trials_per_s": n / t_ora,
+                       "spins_equal": bool(np.array_equal(gpu_spins, q)),
+                       "note": ("cold refresh + sweeps with a warm refresh before each, wall clock including the "
+                                "library's set-up" if elastic else "zero load: integer decisions, spins bit-exact")}
+        log(f"[bench] {c.name}: gpu {t_gpu:.3f} s, oracle {t_ora:.2f} s, spins equal {out[c.name]['spins_equal']}")
+    return out
 
 
 def bench_batched(a):
@@ -723,35 +819,41 @@ def main():
     p.seed = cfg.philox_seed
     p.zone_variant = a.zone_variant
     p.refresh_tile_z = a.tile_z
-    lat = H.Lattice(p, micro.Q)
+    # the library's own stream, so that sweeps are captured into HIP graphs and replayed
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    lat = H.Lattice(p, micro.Q, stream=stream)
     lat.set_orientations(micro.euler)
     lat.set_spins(micro.spins)
     lat.set_load(cfg.sigma_MPa)
     if not a.zero_load:
         log(f"[bench] cold refresh ({p.cold_steps} steps)")
         lat.stress_refresh(-1, True)
-    torch.cuda.synchronize()
+    lat.synchronize()
+    # The timed region runs with kernel timing on (a pair of HIP events on the library's
+    # stream around every launch), which launches eagerly; the same sweeps replayed from HIP
+    # graphs without timing follow as a second figure.
+    lat.set_profiling(True)
     log(f"[bench] warmup {a.warmup} sweeps")
     for _ in range(a.warmup):
         lat.sweep(1)
-    torch.cuda.synchronize()
+    lat.synchronize()
     lat.reset_stats()
     lat.kernel_times()
-    lat.set_profiling(True)
     axes = [ax for ax in cfg.histogram_axes]
     hist = []
     log(f"[bench] timing {a.steps} sweeps")
-    torch.cuda.synchronize()
+    lat.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
         s = lat.sweep_index()
         lat.sweep(1)
         if cfg.histogram_every and (s + 1) % cfg.histogram_every == 0:
             hist.append([lat.texture_histogram(ax, 10.0, 6).tolist() for ax in axes])
-    torch.cuda.synchronize()
+    lat.synchronize()
     t1 = time.perf_counter()
-    lat.set_profiling(False)
     kt = lat.kernel_times()
+    lat.set_profiling(False)
     st = lat.stats()
     elapsed = t1 - t0
     trials = a.steps * K ** 3
@@ -818,6 +920,26 @@ def main():
         "potts_roofline": potts_roof,
         "kernel_ms": {k: round(v["total_ms"], 3) for k, v in kt.items()},
     }
+    # the same sweeps replayed from HIP graphs (one graph per sweep), kernel timing off
+    lat.set_graphs(True)
+    lat.sweep(2)                                  # capture both sweep graphs
+    lat.synchronize()
+    lat.reset_stats()
+    tg0 = time.perf_counter()
+    for _ in range(a.steps):
+        s = lat.sweep_index()
+        lat.sweep(1)
+        if cfg.histogram_every and (s + 1) % cfg.histogram_every == 0:
+            hist.append([lat.texture_histogram(ax, 10.0, 6).tolist() for ax in axes])
+    lat.synchronize()
+    tg = time.perf_counter() - tg0
+    stg = lat.stats()
+    lat.set_graphs(False)
+    out["graph_replayed"] = {"value": trials / tg, "unit": "site-trials/s", "ms_per_step": tg / a.steps * 1e3,
+                             "zone_solve_fraction": stg["zone_solves"] / trials,
+                             "note": "the next sweeps of the same run, each replayed from a captured HIP graph "
+                                     "(kernel timing off)"}
+    log(f"[bench] graph-replayed: {trials / tg:.4e} site-trials/s")
     if a.zero_load:
         lat.close()
         print(json.dumps(out), flush=True)
@@ -842,11 +964,56 @@ def main():
         "note": "same workload and sweep count, zone_screen=1: trials whose point-zone lower bound already "
                 "exceeds the Metropolis threshold are rejected without a solve (decisions unchanged)"}
     log(f"[bench] screened: {out['screened']['value']:.4e} site-trials/s, stats {st2}")
+    if a.proposal == "neighbor" and a.saturation_steps > 0:
+        out["saturation_uniform"] = saturation_line(a, p, micro, lat, cfg)
     if not a.no_cpu_baseline:
         log("[bench] oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(lat, p, micro, a.cpu_seconds)
-    lat.close()
+        lat.close()
+        out["cpu_baseline"]["small_configs"] = small_configs()
+    else:
+        lat.close()
     print(json.dumps(out), flush=True)
+
+
+def saturation_line(a, p, micro, lat, cfg):
+    """The same lattice state (spins, stress field and displacements after the timed sweeps)
+    with uniform proposals: every trial is a real flip and gets a zone solve (f_z = 1), which
+    loads the zone kernel fully; a few sweeps with kernel timing on."""
+    from paper_1009_0457_amd import hmc as H
+
+    q = H.hmc_params.from_buffer_copy(p)
+    q.proposal = 1
+    u = H.Lattice(q, micro.Q, stream=lat.stream)
+    u.set_orientations(micro.euler)
+    u.set_spins(lat.get_spins())
+    u.set_load(cfg.sigma_MPa)
+    u.set_elastic_state(lat.get_displacement(), lat.macro_strain())
+    u.stress_refresh(0, False)
+    u.set_sweep_index(lat.sweep_index())
+    u.set_profiling(True)
+    u.sweep(1)
+    u.synchronize()
+    u.reset_stats()
+    u.kernel_times()
+    n = a.saturation_steps
+    t0 = time.perf_counter()
+    u.sweep(n)
+    u.synchronize()
+    el = time.perf_counter() - t0
+    kt = u.kernel_times()
+    st = u.stats()
+    u.close()
+    zt = kt["zone"]
+    fps = zone_flops_per_solve(q.zone_h, q.zone_steps)
+    ach = fps * st["zone_solves"] / (zt["total_ms"] * 1e-3) / 1e12 if zt["total_ms"] > 0 else 0.0
+    log(f"[bench] uniform proposals: {n * q.K ** 3 / el:.4e} site-trials/s, zone {ach:.1f} TFLOP/s")
+    return {"value": n * q.K ** 3 / el, "unit": "site-trials/s", "steps": n, "ms_per_step": el / n * 1e3,
+            "zone_solve_fraction": st["zone_solves"] / (n * q.K ** 3), "zone_solves_per_s": st["zone_solves"] / el,
+            "zone_roofline": {"achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                              "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                              "avg_launch_ms": round(zt["total_ms"] / max(1, zt["launches"]), 4)},
+            "note": "uniform proposals (every trial a real flip, f_z = 1) from the state after the timed sweeps"}
 
 
 if __name__ == "__main__":

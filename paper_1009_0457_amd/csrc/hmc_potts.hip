@@ -84,8 +84,20 @@ __device__ __forceinline__ double point_zone_energy(const float* __restrict__ So
     return d;
 }
 
+// 2-bit fields, for n = 0..26, of n % 3 (which = 0), (n / 3) % 3 (1) and n / 9 (2).
+constexpr uint64_t slot_field_table(int which)
+{
+    uint64_t t = 0;
+    for (int n = 0; n < 27; ++n) {
+        const int v = which == 0 ? n % 3 : which == 1 ? (n / 3) % 3 : n / 9;
+        t |= (uint64_t)v << (2 * n);
+    }
+    return t;
+}
+
 // Offset of neighbour slot k.  6: -x,+x,-y,+y,-z,+z.  26: (dz,dy,dx) lexicographic over
-// {-1,0,1}^3 without the centre.
+// {-1,0,1}^3 without the centre (n = k or k + 1 past the centre; the digits of n in base 3
+// read from three constant bit tables, which a variable k turns into two shifts and masks).
 template <int M>
 __device__ __forceinline__ void slot_offset(int k, int& dx, int& dy, int& dz)
 {
@@ -94,10 +106,11 @@ __device__ __forceinline__ void slot_offset(int k, int& dx, int& dy, int& dz)
         dy = (k == 2) ? -1 : (k == 3 ? 1 : 0);
         dz = (k == 4) ? -1 : (k == 5 ? 1 : 0);
     } else {
-        const int n = k + (k >= 13);
-        dx = n % 3 - 1;
-        dy = (n / 3) % 3 - 1;
-        dz = n / 9 - 1;
+        constexpr uint64_t TX = slot_field_table(0), TY = slot_field_table(1), TZ = slot_field_table(2);
+        const int sh = 2 * (k + (k >= 13));
+        dx = (int)((TX >> sh) & 3u) - 1;
+        dy = (int)((TY >> sh) & 3u) - 1;
+        dz = (int)((TZ >> sh) & 3u) - 1;
     }
 }
 
@@ -200,10 +213,12 @@ __device__ __forceinline__ void block_sum2(uint32_t& a, uint32_t& b)
 // share a chunk, one site per thread (the same sites and draws, a quarter each).  Lattices
 // with few chunks per pass (128^3 with 8 colours has 256) take SPT = 1 at zero load: four
 // times the wavefronts to hide the chain of dependent reads of a site.  Phase 1 draws every trial and
-// keeps only the real flips (q_new != q_old), which a wavefront then compacts through LDS
-// so that phase 2 -- the 26 neighbour reads, the decision or the screen -- runs once per 64
-// real flips instead of once per site slot (inside grains most proposals are no-ops, and a
-// single real flip would otherwise hold the whole wavefront).  A colour pass has tens of
+// keeps only the real flips (q_new != q_old), which each wavefront compacts through LDS; phase
+// 2 -- the 26 neighbour reads, the decision or the screen -- then takes the block's real flips
+// as one list, 256 at a time, so that it runs once per 64 real flips of the block instead of
+// once per site slot (inside grains most proposals are no-ops, and a single real flip would
+// otherwise hold a whole wavefront): on large lattices a block of 1024 sites usually has fewer
+// than 64, and three of its four wavefronts skip phase 2.  A colour pass has tens of
 // thousands of blocks on large lattices, so the block appends its elastic trials with one
 // atomic on the list counter and adds its statistics to one of the spread counter copies.
 static_assert(kPassSites == 4 * 256, "a chunk is four sites per thread of a 256-thread block");
@@ -225,7 +240,8 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
     const uint32_t n_active = (uint32_t)(R.n3 / (M == 26 ? 8 : 2));
     const bool elastic = R.elastic != 0;
     int16_t* spins = a.spins + R.site_off;
-    const int K = R.K, KK = K * K;
+    const int K = R.K, KK = K * K, Km = K - 1;
+    const bool pow2 = (K & Km) == 0;
     const uint32_t sweep = (uint32_t)(*a.sweep);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const unsigned long long below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
@@ -253,7 +269,12 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
                 const int k = (int)__umulhi(rn.v[0], (uint32_t)M);
                 int dx, dy, dz;
                 slot_offset<M>(k, dx, dy, dz);
-                q_new = spins[site_of(wrapi(x + dx, K), wrapi(y + dy, K), wrapi(z + dz, K), K, KK)];
+                uint32_t nb;
+                if (pow2)   // uniform branch: a power-of-two edge wraps by a mask
+                    nb = site_of((x + dx) & Km, (y + dy) & Km, (z + dz) & Km, K, KK);
+                else
+                    nb = site_of(wrapi(x + dx, K), wrapi(y + dy, K), wrapi(z + dz, K), K, KK);
+                q_new = spins[nb];
             } else {
                 const uint32_t step = __umulhi(rn.v[0], (uint32_t)(R.Q - 1));
                 q_new = (int)(((uint32_t)q_old + 1u + step) % (uint32_t)R.Q);
@@ -282,18 +303,24 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
         n_wave += (uint32_t)__popcll(m);
         n_real += real ? 1u : 0u;
     }
+    __shared__ uint32_t s_nw[4];
+    if (lane == 0) s_nw[wid] = n_wave;
     __syncthreads();
+    // the four wavefronts' lists, read as one list of the block's real flips
+    const uint32_t c0 = s_nw[0], c1 = c0 + s_nw[1], c2 = c1 + s_nw[2], n_block = c2 + s_nw[3];
 
-    // ---- phase 2: the wavefront's real flips, 64 at a time ----
+    // ---- phase 2: the block's real flips, 256 at a time (wavefronts past the end skip it) ----
     TrialEntry ent[SPT];
     bool solve[SPT];
     uint32_t n_solve = 0;
 #pragma unroll
     for (int it = 0; it < SPT; ++it) {
-        const uint32_t j = (uint32_t)(it * 64 + lane);
+        const uint32_t j = (uint32_t)(it * 256) + threadIdx.x;
         solve[it] = false;
-        if (j < n_wave) {
-            const uint32_t packed = s_item[wid][j][0], qq = s_item[wid][j][1], r1 = s_item[wid][j][2];
+        if (j < n_block) {
+            const int wv = (j >= c0) + (j >= c1) + (j >= c2);
+            const uint32_t jj = j - (wv == 0 ? 0u : wv == 1 ? c0 : wv == 2 ? c1 : c2);
+            const uint32_t packed = s_item[wv][jj][0], qq = s_item[wv][jj][1], r1 = s_item[wv][jj][2];
             const int x = (int)(packed & 1023u), y = (int)((packed >> 10) & 1023u), z = (int)(packed >> 20);
             const int q_old = (int)(qq & 0xffffu), q_new = (int)(qq >> 16);
             const uint32_t site = site_of(x, y, z, K, KK);

@@ -555,6 +555,9 @@ class Lattice:
     def set_graphs(self, enable=True):
         hmc_set_graphs(self.ctx, enable)
 
+    def synchronize(self):
+        self.stream.synchronize()
+
     # adjoint of the global solve
     def elastic_forward(self, n_steps, ckpt_every=50):
         nbytes = hmc_adjoint_workspace_bytes(self.ctx, n_steps, ckpt_every)
@@ -664,6 +667,19 @@ class Batch(Lattice):
         hmc_batch_get_stress(self.ctx, r, out)
         self.stream.synchronize()
         return out
+
+    def colour_pass(self, colour, records=False):
+        """One colour pass of every replica; with records, the per-trial records of all
+        replicas laid end to end (replica r's sites from the sum of the earlier replicas' K^3)."""
+        rec = None
+        n = sum(self.n3s)
+        if records:
+            rec = self.torch.zeros(n * record_dtype.itemsize, dtype=self.torch.uint8, device=self.device)
+        hmc_colour_pass(self.ctx, colour, rec)
+        if rec is None:
+            return None
+        self.stream.synchronize()
+        return rec.cpu().numpy().view(record_dtype)
 
     def energy(self, r=0):
         return hmc_batch_energy(self.ctx, r)

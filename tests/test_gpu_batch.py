@@ -169,16 +169,18 @@ def test_batch_zero_load_matches_oracle():
     b.close()
 
 
-@pytest.mark.parametrize("material_points", [1, 8])
-def test_graph_replays_match_eager_sweeps(material_points):
+@pytest.mark.parametrize("material_points,refresh_steps", [(1, 50), (8, 50), (1, 51), (8, 51)])
+def test_graph_replays_match_eager_sweeps(material_points, refresh_steps):
     """A single lattice on its own stream: every graph replay (sweeps with and without the
-    refresh, the refresh with one material point per voxel or eight per cell) equals the eager
-    sweep, with eager work and synchronisation in between."""
+    refresh, the refresh with one material point per voxel or eight per cell, an even and an
+    odd number of refresh steps, which leave the displacement in either ping-pong buffer with
+    one point per voxel and always in the first with eight) equals the eager sweep, with eager
+    work and synchronisation in between."""
     K = 16
     m = voronoi_polycrystal(K, 10, 5)
     p = H.hmc_default_params(K, 26, 1)
     p.refresh_every = 2
-    p.refresh_steps = 50
+    p.refresh_steps = refresh_steps
     p.kT = 0.7
     H.hmc_set_material_points(p, material_points)
     outs = {}
@@ -204,3 +206,101 @@ def test_graph_replays_match_eager_sweeps(material_points):
         lat.close()
     for k, (a, b) in enumerate(zip(outs["eager"], outs["graph"])):
         assert np.array_equal(a, b), k
+
+
+
+def ensemble(n=None):
+    """The 64-replica ensemble (K in {32, 48, 64, 96}, 8 grains per 16^3, uniaxial loads on
+    random axes, kT in 0.3-1.0, 26 neighbours, 5^3 zone x 200 steps, refresh every 10)."""
+    from paper_1009_0457_amd.synth import batched_configs
+
+    cfgs = batched_configs()[:n] if n else batched_configs()
+    micros = [c.microstructure() for c in cfgs]
+    common = H.hmc_default_params(16, 26, 2)
+    common.refresh_every = cfgs[0].refresh_every
+    reps = []
+    for c, m in zip(cfgs, micros):
+        r = H.hmc_default_replica(common, c.K, m.Q)
+        r.kT, r.seed = c.kT, c.philox_seed
+        for i in range(6):
+            r.sigma_MPa[i] = float(c.sigma_MPa[i])
+        reps.append(r)
+    return common, cfgs, micros, reps
+
+
+def test_ensemble_zero_load_twin_matches_oracle():
+    """Gate (1) on the whole 64-replica ensemble at zero load (about 20.6 M sites): after two
+    fused, graph-replayed sweeps every replica's spins equal the oracle's, bit for bit."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    common, cfgs, micros, reps = ensemble()
+    for r in reps:
+        for i in range(6):
+            r.sigma_MPa[i] = 0.0
+    b = H.Batch(common, reps)
+    for i, m in enumerate(micros):
+        b.set_replica(i, m.euler, m.spins)
+    say(f"[ensemble zero load] {len(reps)} replicas, {sum(r.K ** 3 for r in reps)} sites, 2 sweeps")
+    b.set_graphs(True)
+    b.sweep(2)
+    got = [b.get_spins(i).cpu().numpy() for i in range(len(reps))]
+    b.close()
+
+    def oracle_run(i):
+        r, m = reps[i], micros[i]
+        q = m.spins.copy()
+        prm = O.make_params(r.K, 26, m.Q, proposal=0, elastic=False, J=common.J, kT=r.kT, seed=r.seed)
+        d = np.zeros(1)
+        O.sweeps(prm, q, np.zeros(36 * m.Q), np.zeros(36 * m.Q), d, np.zeros(6), d, 0, 2)
+        return q
+
+    with ThreadPoolExecutor(16) as ex:
+        want = list(ex.map(oracle_run, range(len(reps))))
+    bad = [i for i in range(len(reps)) if not np.array_equal(got[i], want[i])]
+    changed = sum(int(np.count_nonzero(w != m.spins)) for w, m in zip(want, micros))
+    say(f"    sites changed by the oracle: {changed}; replicas differing: {bad}")
+    assert changed > 0 and not bad
+
+
+def test_ensemble_under_load_matches_oracle_sampled():
+    """The ensemble under load, fused: one colour pass of the first 8 replicas (after a cold
+    refresh and two sweeps, the second of which follows a warm refresh) against the oracle fed
+    each replica's own snapshot spins and stress field, on a 5 % site sample of each replica:
+    proposals, bond counts and draws exact, zone energies within the FP32 tolerance,
+    decisions identical outside the near-threshold band."""
+    from test_gpu_parity import ZoneErrors, compare_pass, oracle_trials_pooled
+
+    common, cfgs, micros, reps = ensemble(8)
+    b = H.Batch(common, reps)
+    for i, m in enumerate(micros):
+        b.set_replica(i, m.euler, m.spins)
+    b.stress_refresh(-1, True)
+    b.sweep(2)
+    s = b.sweep_index()
+    snaps = [b.get_spins(i).cpu().numpy() for i in range(len(reps))]
+    sigs = [b.get_stress(i).cpu().numpy().astype(np.float64) for i in range(len(reps))]
+    col = 5
+    rec = b.colour_pass(col, records=True)
+    b.close()
+    rng = np.random.default_rng(12)
+    errs = ZoneErrors()
+    off = 0
+    for i, (r, m) in enumerate(zip(reps, micros)):
+        K = r.K
+        Ct, St, _ = O.tables(m.euler, common.C11, common.C12, common.C44)
+        prm = O.make_params(K, 26, m.Q, proposal=0, h=2, nr=common.zone_steps, elastic=True, J=common.J, kT=r.kT,
+                            lambda_el=r.lambda_el, zone_alpha=common.zone_alpha, zone_beta=common.zone_beta,
+                            seed=r.seed)
+        sites = np.nonzero(O.colour_of(K, 26) == col)[0]
+        sites = np.sort(rng.choice(sites, size=max(1, sites.size // 20), replace=False))
+        ref = oracle_trials_pooled(prm, snaps[i], Ct, St, sigs[i], s, sites)
+        rr = rec[off:off + K ** 3]
+        tol = errs.add(rr, ref, sites, sigs[i], St, snaps[i])
+
+        class P:   # the replica's decision constants for the comparison
+            kT, lambda_el = r.kT, r.lambda_el
+
+        n, k, w = compare_pass(rr, ref, sites, P, tol, f"replica {i} (K={K})")
+        errs.flagged += k
+        off += K ** 3
+    assert errs.report("ensemble replicas 0-7, colour 5") > 200
