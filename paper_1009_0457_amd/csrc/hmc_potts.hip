@@ -264,7 +264,8 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
             site = site_of(x, y, z, K, KK);
             const Philox4 rn = philox4x32_10(site, sweep, 0u, 0u, R.key0, R.key1);
             r1 = rn.v[1];
-            const int q_old = spins[site];
+            const char* sb = reinterpret_cast<const char*>(spins);
+            const int q_old = *reinterpret_cast<const int16_t*>(sb + 2u * site);
             if (R.proposal == 0) {
                 const int k = (int)__umulhi(rn.v[0], (uint32_t)M);
                 int dx, dy, dz;
@@ -274,7 +275,7 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
                     nb = site_of((x + dx) & Km, (y + dy) & Km, (z + dz) & Km, K, KK);
                 else
                     nb = site_of(wrapi(x + dx, K), wrapi(y + dy, K), wrapi(z + dz, K), K, KK);
-                q_new = spins[nb];
+                q_new = *reinterpret_cast<const int16_t*>(sb + 2u * nb);
             } else {
                 const uint32_t step = __umulhi(rn.v[0], (uint32_t)(R.Q - 1));
                 q_new = (int)(((uint32_t)q_old + 1u + step) % (uint32_t)R.Q);
@@ -324,18 +325,24 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
             const int x = (int)(packed & 1023u), y = (int)((packed >> 10) & 1023u), z = (int)(packed >> 20);
             const int q_old = (int)(qq & 0xffffu), q_new = (int)(qq >> 16);
             const uint32_t site = site_of(x, y, z, K, KK);
-            const int xs[3] = {wrapi(x - 1, K), x, wrapi(x + 1, K)};
-            const int ys[3] = {(int)__umul24((uint32_t)wrapi(y - 1, K), (uint32_t)K), (int)__umul24((uint32_t)y, (uint32_t)K),
-                               (int)__umul24((uint32_t)wrapi(y + 1, K), (uint32_t)K)};
-            const int zs[3] = {(int)__umul24((uint32_t)wrapi(z - 1, K), (uint32_t)KK),
-                               (int)__umul24((uint32_t)z, (uint32_t)KK),
-                               (int)__umul24((uint32_t)wrapi(z + 1, K), (uint32_t)KK)};
+            // byte offsets of the three x, y and z planes around the site (2 bytes per spin;
+            // 2 K^3 <= 2^31 for K <= 1024): each neighbour is one add and a load off the
+            // replica's spin base
+            const uint32_t K2 = 2u * (uint32_t)K, KK2 = 2u * (uint32_t)KK;
+            const uint32_t xs[3] = {2u * (uint32_t)wrapi(x - 1, K), 2u * (uint32_t)x, 2u * (uint32_t)wrapi(x + 1, K)};
+            const uint32_t ys[3] = {(uint32_t)__umul24((uint32_t)wrapi(y - 1, K), K2),
+                                    (uint32_t)__umul24((uint32_t)y, K2),
+                                    (uint32_t)__umul24((uint32_t)wrapi(y + 1, K), K2)};
+            const uint32_t zs[3] = {(uint32_t)__umul24((uint32_t)wrapi(z - 1, K), KK2),
+                                    (uint32_t)__umul24((uint32_t)z, KK2),
+                                    (uint32_t)__umul24((uint32_t)wrapi(z + 1, K), KK2)};
+            const char* sb = reinterpret_cast<const char*>(spins);
             int gb = 0;
 #pragma unroll
             for (int k = 0; k < M; ++k) {
                 int dx, dy, dz;
                 slot_offset<M>(k, dx, dy, dz);
-                const int qn = spins[xs[dx + 1] + ys[dy + 1] + zs[dz + 1]];
+                const int qn = *reinterpret_cast<const int16_t*>(sb + (xs[dx + 1] + ys[dy + 1] + zs[dz + 1]));
                 gb += (qn == q_old) - (qn == q_new);
             }
             bool accepted = false, screened = false;
@@ -382,21 +389,27 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
             n_other += (elastic ? screened : accepted) ? 1u : 0u;
         }
     }
-    // block-collective tail, reached by every thread
-    uint32_t total = 0;
-    uint32_t off = block_exclusive_scan(n_solve, total);
+    // block-collective tail, reached by every thread (`elastic` is uniform over the block: a
+    // block belongs to one replica; at zero load nothing enters the list)
+    uint32_t off = 0;
     __shared__ uint32_t s_base;
-    if (threadIdx.x == 0) s_base = total ? atomicAdd(a.list_count, total) : 0u;
+    if (elastic) {
+        uint32_t total = 0;
+        off = block_exclusive_scan(n_solve, total);
+        if (threadIdx.x == 0) s_base = total ? atomicAdd(a.list_count, total) : 0u;
+    }
     block_sum2(n_real, n_other);   // (its barrier also publishes s_base)
     if (threadIdx.x == 0) {
         unsigned long long* st = a.stats + stat_copy(blockIdx.x);
         if (n_real) atomicAdd(&st[kStatReal], (unsigned long long)n_real);
         if (n_other) atomicAdd(&st[elastic ? kStatScreened : kStatAccepted], (unsigned long long)n_other);
     }
-    off += s_base;
+    if (elastic) {
+        off += s_base;
 #pragma unroll
-    for (int it = 0; it < SPT; ++it)
-        if (solve[it]) a.list[off++] = ent[it];
+        for (int it = 0; it < SPT; ++it)
+            if (solve[it]) a.list[off++] = ent[it];
+    }
 }
 
 // Deferred update of an elastic pass: every accepted entry writes its new state.
