@@ -872,6 +872,11 @@ def main():
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE, profiles/counters_large128.md)",
             "avg_launch_ms": round(zt["total_ms"] / max(1, zt["launches"]), 4),
             "flop_per_solve": fps, "solves_per_launch": round(solves / max(1, zt["launches"]), 1)}
+    # the same launches priced at the survey's per-voxel estimate (200 FLOP per voxel-step), and
+    # against the peak without packed FP32 (which this build does not generate)
+    sfps = p.zone_steps * (200.0 * (2 * p.zone_h + 1) ** 3 + 12.0 * (2 * p.zone_h + 2) ** 3)
+    roof["frac_at_200_flop_per_voxel_step"] = round(achieved * sfps / fps / PEAK_FP32_TFLOPS, 4) if fps else None
+    roof["frac_of_unpacked_fp32_peak"] = round(achieved / (PEAK_FP32_TFLOPS / 2), 4)
     pk = kt["potts"]
     potts_roof = None
     if pk["launches"]:
