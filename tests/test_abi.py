@@ -87,7 +87,7 @@ def test_grain_table_derivatives_match_central_differences_of_the_oracle():
     ("K", 15, H.HMC_ESHAPE), ("K", 0, H.HMC_ESHAPE), ("K", 2048, H.HMC_ESHAPE),
     ("neighbors", 8, H.HMC_EINVAL), ("zone_h", 4, H.HMC_EINVAL), ("kT", 0.0, H.HMC_EINVAL),
     ("kT", float("nan"), H.HMC_ENUMERIC), ("proposal", 2, H.HMC_EINVAL), ("refresh_every", 0, H.HMC_EINVAL),
-    ("C44", -1.0, H.HMC_ENUMERIC), ("zone_variant", 4, H.HMC_EINVAL), ("zone_variant", -1, H.HMC_EINVAL),
+    ("C44", -1.0, H.HMC_ENUMERIC), ("zone_variant", 6, H.HMC_EINVAL), ("zone_variant", -1, H.HMC_EINVAL),
     ("refresh_tile_z", 3, H.HMC_EINVAL), ("refresh_tile_z", 64, H.HMC_EINVAL), ("material_points", 3, H.HMC_EINVAL),
 ])
 def test_create_validates_before_touching_the_device(field, value, status):
@@ -104,7 +104,7 @@ def test_create_validates_before_touching_the_device(field, value, status):
 def test_zone_variant_limits():
     L = _lib_or_skip()
     for h, variant, ok in ((0, 3, False), (3, 3, True), (3, 2, False), (1, 3, True), (2, 3, True), (3, 1, True),
-                           (0, 2, True)):
+                           (0, 2, True), (0, 4, False), (0, 5, False), (2, 4, True), (3, 5, True), (2, 6, False)):
         p = H.hmc_default_params(16, 26, h)
         p.zone_variant = variant
         assert (L.hmc_workspace_bytes(C.byref(p), 8) > 0) == ok, (h, variant)
@@ -115,7 +115,7 @@ def test_autotuner_candidates_are_the_variants_the_library_accepts():
     from paper_1009_0457_amd.autotune import zone_variants_for
     for h in range(4):
         ok = []
-        for v in range(1, 6):
+        for v in range(1, 7):
             p = H.hmc_default_params(16, 26, h)
             p.zone_variant = v
             if L.hmc_workspace_bytes(C.byref(p), 8) > 0:
