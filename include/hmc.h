@@ -259,6 +259,14 @@ hmc_status hmc_set_zone_screen(hmc_ctx ctx, int32_t enable);
  * order.  HMC_EINVAL for a variant the context's zone size does not allow. */
 hmc_status hmc_set_zone_variant(hmc_ctx ctx, int32_t variant);
 
+/* Race detection: the order in which the work-groups of the colour-pass, zone-solve and
+ * explicit-step launches (forward and adjoint) take their parts of the work.  0: the default
+ * (XCD-aware) order; 1: reversed; 2: a fixed shuffle.  No result may depend on it (same-colour
+ * sites are never neighbours, every trial reads the pass's snapshot, and all cross-work-group
+ * sums are integer), so sweeps, refreshes and gradients are bit-identical under all three; a
+ * difference would expose a race.  HMC_EINVAL for other values. */
+hmc_status hmc_set_block_order(hmc_ctx ctx, int32_t order);
+
 /* Kernel timing.  While profiling is enabled the library records a pair of HIP events on
  * the context's stream around every launch of each kernel class below; hmc_get_kernel_times
  * synchronises, resolves the pairs recorded since the last call (or since enabling) into

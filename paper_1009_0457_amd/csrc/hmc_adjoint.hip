@@ -202,6 +202,7 @@ struct AdjStepArgs {
     const RepDev* reps;
     float alpha, beta;
     double betaE, alphaE;
+    int order;               // logical block order (hmc_set_block_order)
 };
 
 // tau = C_q eta and, where `owned`, gq_k = eta . (dC_{q,k} eps) for the three angles k,
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(256, 3) void k_adj_step(AdjStepArgs a)
     const int K = R.K;
     const int64_t n3 = R.n3;
     const int ntx = (K + kTileX - 1) / kTileX, nty = (K + kTileY - 1) / kTileY, tz = R.tile_z;
-    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int lb = logical_block((int)blockIdx.x, (int)gridDim.x, a.order);
     int b = lb;
     const int bx = b % ntx;
     b /= ntx;
@@ -778,6 +779,7 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
             a.beta = R.glob_beta;
             a.betaE = (double)R.glob_beta;
             a.alphaE = R.glob_alphaE;
+            a.order = c->block_order;
             const int tok = prof_begin(c, kProfRefreshStep);
             hipLaunchKernelGGL(k_adj_step, dim3(c->tile_blocks), dim3(256), 0, c->stream, a);
             prof_end(c, tok);

@@ -1217,6 +1217,16 @@ hmc_status hmc_set_zone_variant(hmc_ctx c, int32_t variant)
     return HMC_OK;
 }
 
+hmc_status hmc_set_block_order(hmc_ctx c, int32_t order)
+{
+    if (!c) return HMC_EINVAL;
+    c->err.clear();
+    if (order < 0 || order > 2) return state_fail(c, HMC_EINVAL, "block order must be 0, 1 or 2");
+    c->block_order = order;
+    drop_graphs(c);
+    return HMC_OK;
+}
+
 hmc_status hmc_set_profiling(hmc_ctx c, int32_t enable)
 {
     if (!c) return HMC_EINVAL;

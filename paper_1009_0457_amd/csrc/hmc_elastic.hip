@@ -33,6 +33,7 @@ struct GlobArgs {
     const RepDev* reps;
     const int32_t* tile_rep;
     int64_t plane;
+    int order;                           // logical block order (hmc_set_block_order)
 };
 
 // (E, wE) of the step after the one that started from st_in and whose stress sums are in
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
     __shared__ float4 sPa[VY][VX], sPb[VY][VX];
     __shared__ float4 sraw[3][kTileY][kTileX];
 
-    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);   // neighbouring tiles share an L2
+    const int lb = logical_block((int)blockIdx.x, (int)gridDim.x, a.order);   // neighbouring tiles share an L2
     const int r = a.tile_rep[lb];
     const RepDev R = a.reps[r];
     const int K = R.K;
@@ -480,6 +481,7 @@ hipError_t seq_step(hmc_ctx_s* c, hipStream_t s, int i, const float* uin, float*
     a.E_record = E_record;
     a.reps = c->d.reps;
     a.tile_rep = c->d.tile_rep;
+    a.order = c->block_order;
     a.plane = c->total_sites;
     const int tok = s == c->stream ? prof_begin(c, kProfRefreshStep) : -1;
     hipLaunchKernelGGL(k_global_step_tiled, dim3(c->tile_blocks), dim3(256), 0, s, a);

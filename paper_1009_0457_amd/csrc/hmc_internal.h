@@ -51,6 +51,18 @@ __device__ __forceinline__ int xcd_block(int b, int G)
     return x * q + (x < rm ? x : rm) + i;
 }
 
+// Logical block order of a launch: 0 the XCD-aware order above; 1 reversed; 2 a fixed shuffle
+// (x -> x * 1000003 mod G, a bijection since the prime exceeds any grid).  Results must not
+// depend on it: orders 1 and 2 exist to show that no kernel relies on which work-group runs
+// which part of the work, or when (hmc_set_block_order).
+__device__ __forceinline__ int logical_block(int b, int G, int order)
+{
+    const int x = xcd_block(b, G);
+    if (order == 1) return G - 1 - x;
+    if (order == 2) return (int)(((long long)x * 1000003LL) % (long long)G);
+    return x;
+}
+
 __host__ __device__ constexpr int tile_blocks_of(int K, int tz)
 {
     return ((K + kTileX - 1) / kTileX) * ((K + kTileY - 1) / kTileY) * ((K + tz - 1) / tz);
@@ -168,6 +180,7 @@ struct hmc_ctx_s {
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_u[2] = {-1, -1};
     bool use_graphs = false;
+    int block_order = 0;            // hmc_set_block_order
     int adj_steps = 0, adj_every = 0;   // last hmc_elastic_forward
     // second stream (default priority) on which the adjoint's backward pass recomputes forward
     // segments while the context's stream runs adjoint steps; created on first use

@@ -65,6 +65,7 @@ struct PassArgs {
     int64_t plane;
     int colour;
     int screen;
+    int order;                      // logical block order (hmc_set_block_order)
 };
 
 // Point-zone energy 1/2 sigma.(S_old - S_new) sigma of the trial site: a lower bound of the
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
     static_assert(SPT == 1 || SPT == 4, "one or four sites per thread");
     constexpr int SUB = kPassSites / (256 * SPT);    // blocks per chunk
     __shared__ uint32_t s_item[4][SPT * 64][3];      // per wavefront: coords, q_old | q_new << 16, r1
-    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);   // neighbouring rows share an L2
+    const int lb = logical_block((int)blockIdx.x, (int)gridDim.x, a.order);   // neighbouring rows share an L2
     const int chunk = lb / SUB, sub = lb % SUB;
     const int r = a.pass_rep[chunk];
     const RepDev R = a.reps[r];
@@ -539,6 +540,7 @@ hipError_t launch_potts_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
     a.sigma = c->d.sigma;
     a.plane = c->total_sites;
     a.colour = colour;
+    a.order = c->block_order;
     a.screen = (c->p.zone_screen != 0 && c->d.sigma != nullptr) ? 1 : 0;
     // one site per thread while a pass has fewer chunks than 4 per compute unit and no trial
     // enters the zone-solve list: with the list in use, four times the blocks means four times

@@ -41,6 +41,7 @@ struct ZoneArgs {
     unsigned long long* stats;
     uint32_t* nonfinite;            // counters[kNonFinite]
     int nr;
+    int order;                      // logical block order (hmc_set_block_order)
     int64_t plane;
     float alpha, beta;
 };
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(64) void k_zone(ZoneArgs a)
     const int lane = threadIdx.x;
     const uint32_t count = *a.count;
 
-    for (uint32_t e = blockIdx.x; e < count; e += gridDim.x) {
+    for (uint32_t e = (uint32_t)logical_block((int)blockIdx.x, (int)gridDim.x, a.order); e < count; e += gridDim.x) {
         const TrialEntry ent = a.list[e];
         const TrialCtx tc = trial_ctx(a, ent.qr);
         const int K = tc.K;
@@ -326,7 +327,8 @@ __global__ __launch_bounds__(256, 2) void k_zone_col(ZoneArgs a)
     const uint32_t count = *a.count;
     const float alpha16 = a.alpha * 0.0625f, beta = a.beta;
 
-    for (uint32_t base = blockIdx.x * (uint32_t)Z; base < count; base += gridDim.x * (uint32_t)Z) {
+    for (uint32_t base = (uint32_t)logical_block((int)blockIdx.x, (int)gridDim.x, a.order) * (uint32_t)Z; base < count;
+         base += gridDim.x * (uint32_t)Z) {
         const uint32_t e = base + (uint32_t)zsafe;
         const bool active = in_zone && e < count;
 
@@ -657,7 +659,8 @@ __global__ __launch_bounds__(64 * WAVES, H == 1 ? 3 : 2) void k_zone_lane(ZoneAr
     // solves and acceptances are counted per lane and added to the statistics once per
     // work-group at the end (same-address atomics per trial would serialise in L2)
     uint32_t n_solved = 0, n_accepted = 0;
-    for (uint32_t base = blockIdx.x * (uint32_t)Z; base < count; base += gridDim.x * (uint32_t)Z) {
+    for (uint32_t base = (uint32_t)logical_block((int)blockIdx.x, (int)gridDim.x, a.order) * (uint32_t)Z; base < count;
+         base += gridDim.x * (uint32_t)Z) {
         const uint32_t e = base + (uint32_t)(member ? zs : 0);
         const bool active = member && e < count;
 
@@ -900,6 +903,7 @@ hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
     a.stats = c->d.stats;
     a.nonfinite = c->d.counters + kNonFinite;
     a.nr = c->p.zone_steps;
+    a.order = c->block_order;
     a.plane = c->total_sites;
     a.alpha = (float)c->p.zone_alpha;
     a.beta = (float)c->p.zone_beta;

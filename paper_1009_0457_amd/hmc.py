@@ -83,6 +83,7 @@ _SIGS = [
     ("hmc_colour_pass", C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     ("hmc_energy", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     ("hmc_texture_histogram", C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p]),
+    ("hmc_set_block_order", C.c_int, [C.c_void_p, C.c_int32]),
     ("hmc_texture_histogram_noalloc", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                                 C.c_double, C.c_int32, C.c_void_p, C.c_void_p]),
     ("hmc_get_stress", C.c_int, [C.c_void_p, C.c_void_p]),
@@ -247,6 +248,10 @@ def hmc_texture_histogram_noalloc(spins_dev, K, euler, axis, bin_deg=10.0, nbins
                                              out.ctypes.data_as(C.c_void_p), C.c_void_p(stream_handle))
     _check(st, None, creating=True)
     return out
+
+
+def hmc_set_block_order(ctx, order):
+    _check(lib().hmc_set_block_order(ctx, int(order)), ctx)
 
 
 def hmc_get_stress(ctx, out_dev):
@@ -554,6 +559,9 @@ class Lattice:
 
     def set_graphs(self, enable=True):
         hmc_set_graphs(self.ctx, enable)
+
+    def set_block_order(self, order):
+        hmc_set_block_order(self.ctx, order)
 
     def synchronize(self):
         self.stream.synchronize()

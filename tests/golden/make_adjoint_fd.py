@@ -79,17 +79,17 @@ def main():
         "# oracle.solver_defaults.  Written by make_adjoint_fd.py (oracle only).",
         "# dU/dtheta in GPa*voxel per rad (h = 1e-4 rad), dU/dSigma per MPa (h = 1e-3 MPa).",
         f"steps = {N_STEPS}",
-        f"glob_alpha = {ga!r}",
-        f"glob_beta = {gb!r}",
-        f"U = {res[('U',)]!r}",
+        f"glob_alpha = {float(ga)!r}",
+        f"glob_beta = {float(gb)!r}",
+        f"U = {float(res[('U',)])!r}",
     ]
     for g in probe:
         for k in range(3):
             d = (res[("theta", int(g), k, 1)] - res[("theta", int(g), k, -1)]) / (2 * H_ANGLE)
-            lines.append(f"dU_dtheta_{int(g)}_{k} = {d!r}")
+            lines.append(f"dU_dtheta_{int(g)}_{k} = {float(d)!r}")
     for i in range(6):
         d = (res[("sigma", i, 1)] - res[("sigma", i, -1)]) / (2 * H_SIGMA)
-        lines.append(f"dU_dSigma_{i} = {d!r}")
+        lines.append(f"dU_dSigma_{i} = {float(d)!r}")
     with open(OUT, "w") as f:
         f.write("\n".join(lines) + "\n")
     print(f"wrote {OUT}")
