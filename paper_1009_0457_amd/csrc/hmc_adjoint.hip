@@ -781,7 +781,8 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
             a.alphaE = R.glob_alphaE;
             a.order = c->block_order;
             const int tok = prof_begin(c, kProfRefreshStep);
-            hipLaunchKernelGGL(k_adj_step, dim3(c->tile_blocks), dim3(256), 0, c->stream, a);
+            // the adjoint step keeps 32 x 8 tiles whatever the forward step's rows
+            hipLaunchKernelGGL(k_adj_step, dim3(tile_blocks_of(R.K, R.tile_z, kTileY)), dim3(256), 0, c->stream, a);
             prof_end(c, tok);
             ATRY(hipGetLastError(), "backward: step");
             cur_b = 1 - cur_b;

@@ -94,24 +94,43 @@ struct Layout {
     size_t spins, Ctab, Stab, sigma, u0, u1, w, list, accept, state, partials, sums, seq_state, counters, stats,
         thr, tex, hist, bonds, reps, pass_rep, node_rep, tile_rep, sweep, total;
     int64_t sites, grains, max_list;
-    int pass_blocks, node_blocks, tile_blocks, tile_z;
+    int pass_blocks, node_blocks, tile_blocks, tile_z, tile_y;
     bool elastic;
 };
 
 int64_t n3_of(int K) { return (int64_t)K * K * K; }
 
+// Node rows per block of the forward explicit step: 16 (512-thread blocks) when every
+// replica's edge is a multiple of 16, else 8 (a 16-row tile would pad more rows than it saves).
+int tile_rows_of(int n, const hmc_replica* r)
+{
+    for (int i = 0; i < n; ++i)
+        if (r[i].K % 16 != 0) return 8;
+    return 16;
+}
+
+// Whether the explicit step streams its own nodes' u and w past the caches: when the arrays a
+// step reads and writes (u in, u out, w: 36 bytes per node, and the 2-byte grain ids) are
+// larger than the 256 MB Infinity Cache, which then cannot keep them from one step to the
+// next.  Below that, ordinary accesses let the next step find them there.  Measured (32 x 16
+// tiles): 128^3 (80 MB) 37.0 us plain against 42.2 us non-temporal; 256^3 (640 MB) 250 against
+// 238 us; 512^3 1.73 against 1.66 ms.
+bool step_streams_of(int64_t sites) { return sites * 38 > (int64_t)256 << 20; }
+
 // Node layers per block of the tiled explicit step: the caller's choice, else the deepest
-// tile that still launches at least 1024 blocks over all replicas (4 per compute unit), but
-// 2 rather than 1 (a block's first layer is redone by its neighbour, which one-layer tiles
-// pay on every layer), and 1 when no depth reaches 1024.  Measured: 32 at 256^3 and 512^3
-// (64 is within 1 %), 8 at 128^3, 2 at 64^3 are the fastest depths there.
+// tile that still launches at least 256K threads over all replicas (1024 blocks of 256 or 512
+// of 512, 4 or 2 per compute unit), but 2 rather than 1 (a block's first layer is redone by
+// its neighbour, which one-layer tiles pay on every layer), and 1 when no depth reaches it.
+// Measured with 32 x 8 tiles: 32 at 256^3 and 512^3 (64 is within 1 %), 8 at 128^3, 2 at 64^3
+// are the fastest depths there.
 int tile_depth_of(const hmc_params* p, int n, const hmc_replica* r)
 {
     if (p->refresh_tile_z > 0) return p->refresh_tile_z;
+    const int ty = tile_rows_of(n, r);
     for (int tz = kTileZMax; tz >= 1; tz /= 2) {
         int64_t blocks = 0;
-        for (int i = 0; i < n; ++i) blocks += tile_blocks_of(r[i].K, tz);
-        if (blocks >= 1024) return tz > 1 ? tz : 2;
+        for (int i = 0; i < n; ++i) blocks += tile_blocks_of(r[i].K, tz, ty);
+        if (blocks * ty >= 1024 * 8) return tz > 1 ? tz : 2;
     }
     return 1;
 }
@@ -121,6 +140,7 @@ Layout layout_of(const hmc_params* p, int n, const hmc_replica* r)
     Layout L{};
     const int C = colours_of(p->neighbors);
     L.tile_z = tile_depth_of(p, n, r);
+    L.tile_y = tile_rows_of(n, r);
     for (int i = 0; i < n; ++i) {
         const int64_t n3 = n3_of(r[i].K);
         L.sites += n3;
@@ -130,7 +150,7 @@ Layout layout_of(const hmc_params* p, int n, const hmc_replica* r)
         int64_t nb = (n3 + kSiteBlock - 1) / kSiteBlock;
         if (nb > kMaxChunkBlocks) nb = kMaxChunkBlocks;
         L.node_blocks += (int)nb;
-        L.tile_blocks += tile_blocks_of(r[i].K, L.tile_z);
+        L.tile_blocks += tile_blocks_of(r[i].K, L.tile_z, L.tile_y);
         L.elastic = L.elastic || r[i].lambda_el != 0.0;
     }
     size_t o = 0;
@@ -500,6 +520,7 @@ hmc_status build_context(const hmc_params* p, int n, const hmc_replica* r, void*
     c->pass_blocks = L.pass_blocks;
     c->node_blocks = L.node_blocks;
     c->tile_blocks = L.tile_blocks;
+    c->step_streams = step_streams_of(L.sites);
     c->elastic_buffers = L.elastic;
     char* b = (char*)ws;
     c->d.spins = (int16_t*)(b + L.spins);
@@ -554,7 +575,8 @@ hmc_status build_context(const hmc_params* p, int n, const hmc_replica* r, void*
         R.node_blocks = (int)(nb > kMaxChunkBlocks ? kMaxChunkBlocks : nb);
         R.tile_first = tf;
         R.tile_z = L.tile_z;
-        R.tile_blocks = tile_blocks_of(R.K, R.tile_z);
+        R.tile_y = L.tile_y;
+        R.tile_blocks = tile_blocks_of(R.K, R.tile_z, R.tile_y);
         R.J = p->J;
         R.kT = r[i].kT;
         R.lambda = r[i].lambda_el;

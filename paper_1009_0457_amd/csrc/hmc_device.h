@@ -71,18 +71,24 @@ __device__ __forceinline__ void symv21_grains(const float* tab, int q, const flo
 // is an own node, as four 8 x 8 patches, one per wavefront (neighbouring voxels mostly share
 // a grain), then the low halo row and column.
 constexpr int kStepVox = (kTileX + 1) * (kTileY + 1);
-static_assert(kTileX == 32 && kTileY == 8, "voxel patches assume a 32 x 8 tile");
+static_assert(kTileX == 32 && kTileY == 8, "voxel patches assume 32-wide tiles of 8 or 16 rows");
+// For a 32 x TY tile (TY = 8 or 16, 32 TY threads): wavefront w takes the 8 x 8 patch at x in
+// [8 (w % 4) + 1, 8 (w % 4) + 8], y in [8 (w / 4) + 1, 8 (w / 4) + 8].
+template <int TY = kTileY>
 __device__ __forceinline__ void step_voxel_pos(int i, int& ix, int& iy)
 {
-    if (i < 256) {                         // interior: wavefront w takes x in [8w + 1, 8w + 8]
-        ix = 1 + 8 * (i >> 6) + (i & 7);
-        iy = 1 + ((i & 63) >> 3);
-    } else if (i < 256 + kTileX + 1) {     // halo row y = 0
-        ix = i - 256;
+    static_assert(TY == 8 || TY == 16, "tile rows");
+    constexpr int NI = kTileX * TY;
+    if (i < NI) {                          // interior patches
+        const int w = i >> 6;
+        ix = 1 + 8 * (w & 3) + (i & 7);
+        iy = 1 + 8 * (w >> 2) + ((i & 63) >> 3);
+    } else if (i < NI + kTileX + 1) {      // halo row y = 0
+        ix = i - NI;
         iy = 0;
     } else {                               // halo column x = 0
         ix = 0;
-        iy = i - (256 + kTileX + 1) + 1;
+        iy = i - (NI + kTileX + 1) + 1;
     }
 }
 
@@ -201,6 +207,29 @@ __device__ __forceinline__ double block_total(const double v[NVALS])
         for (int k = 0; k < NVALS; ++k) red[k][t >> 6] = s[k];
     __syncthreads();
     return t < NVALS ? (red[t][0] + red[t][1]) + (red[t][2] + red[t][3]) : 0.0;
+}
+
+// block_total for blocks of 4 Q wavefronts, per group of four: thread 256 g + k (k < NVALS)
+// receives the total k of wavefronts 4g .. 4g+3, summed exactly as block_total sums a block of
+// four; the other threads receive 0.
+template <int NVALS, int Q>
+__device__ __forceinline__ double block_total_quads(const double v[NVALS])
+{
+    __shared__ double red[NVALS][4 * Q];
+    double s[NVALS];
+#pragma unroll
+    for (int k = 0; k < NVALS; ++k) s[k] = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < NVALS; ++k) s[k] += __shfl_xor(s[k], o, 64);
+    const int t = threadIdx.x;
+    if ((t & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < NVALS; ++k) red[k][t >> 6] = s[k];
+    __syncthreads();
+    const int k = t & 255, g = t >> 8;
+    return k < NVALS ? (red[k][4 * g] + red[k][4 * g + 1]) + (red[k][4 * g + 2] + red[k][4 * g + 3]) : 0.0;
 }
 
 // Deterministic block sum of NVALS doubles per thread into partials[slot * 8 + k] (slot: the

@@ -74,28 +74,39 @@ __device__ __forceinline__ void advance_E(const RepDev* reps, int r, const doubl
 // are formed in 8 x 8 patches, one per wavefront, so that a wavefront's voxels mostly share
 // one grain and its stiffness comes through the scalar cache.
 // (At most 128 VGPRs, so that four blocks share a CU: the LDS would allow five.)
-__global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
+// TY = 8 (256 threads, four blocks per CU) or 16 (512 threads, two blocks per CU: fewer halo
+// nodes and voxels per owned node, half the y-halo rows re-read by neighbouring tiles).  Both
+// give bit-identical results: a 16-row tile's wavefronts 0-3 hold the voxels and sums of the
+// 8-row tile at its top, wavefronts 4-7 those of the one below, and each half's stress sums
+// are totalled and rounded to fixed point on their own, as two 8-row blocks would.  The own
+// nodes' u and w are read and written once per step; with NT (lattices too large for the
+// Infinity Cache) non-temporal accesses keep them from displacing the halo rows that
+// neighbouring tiles read from L2 (512^3: 1.73 -> 1.66 ms).
+template <int TY, bool NT>
+__global__ __launch_bounds__(32 * TY, TY == 8 ? 4 : 2) void k_global_step_tiled(GlobArgs a)
 {
-    constexpr int NX = kTileX + 2, NY = kTileY + 2, VX = kTileX + 1, VY = kTileY + 1;
-    constexpr int NP = (NX * NY + 255) / 256, VP = (kStepVox + 255) / 256;
+    constexpr int THREADS = kTileX * TY;
+    constexpr int NX = kTileX + 2, NY = TY + 2, VX = kTileX + 1, VY = TY + 1;
+    constexpr int NVOX = VX * VY;
+    constexpr int NP = (NX * NY + THREADS - 1) / THREADS, VP = (NVOX + THREADS - 1) / THREADS;
     // LDS entries are vectors, so that each holds what one lane writes or reads at a time:
     // node pair (S0, D0, S1, D1) and (S2, D2); voxel pair (P_xx, P_yy, P_yz, P_xz) and
     // (P_xy, M_zz, M_yz, M_xz); own node (u0, u1, u2, -)
     __shared__ float4 sNa[NY][NX];
     __shared__ float2 sNb[NY][NX];
     __shared__ float4 sPa[VY][VX], sPb[VY][VX];
-    __shared__ float4 sraw[3][kTileY][kTileX];
+    __shared__ float4 sraw[3][TY][kTileX];
 
     const int lb = logical_block((int)blockIdx.x, (int)gridDim.x, a.order);   // neighbouring tiles share an L2
     const int r = a.tile_rep[lb];
     const RepDev R = a.reps[r];
     const int K = R.K;
-    const int ntx = (K + kTileX - 1) / kTileX, nty = (K + kTileY - 1) / kTileY, tz = R.tile_z;
+    const int ntx = (K + kTileX - 1) / kTileX, nty = (K + TY - 1) / TY, tz = R.tile_z;
     int b = lb - R.tile_first;
     const int bx = b % ntx;
     b /= ntx;
     const int by = b % nty, bz = b / nty;
-    const int x0 = bx * kTileX, y0 = by * kTileY, z0 = bz * tz;
+    const int x0 = bx * kTileX, y0 = by * TY, z0 = bz * tz;
     const int z1 = (z0 + tz < K) ? z0 + tz : K;
     const int16_t* spins = a.spins + R.site_off;
     const float* Ctab = a.Ctab + R.grain_off * kTab;
@@ -128,13 +139,13 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
     int node_xy[NP], vox_xy[VP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        const int i = t + 256 * k, ix = i % NX, iy = i / NX;
+        const int i = t + THREADS * k, ix = i % NX, iy = i / NX;
         node_xy[k] = wrap_tile(x0 - 1 + ix, K) + K * wrap_tile(y0 - 1 + iy, K);
     }
 #pragma unroll
     for (int k = 0; k < VP; ++k) {
         int ix, iy;
-        step_voxel_pos(t + 256 * k, ix, iy);
+        step_voxel_pos<TY>(t + THREADS * k, ix, iy);
         vox_xy[k] = wrap_tile(x0 - 1 + ix, K) + K * wrap_tile(y0 - 1 + iy, K);
     }
     // Node layer z+2 and voxel layer z+1's grains are fetched into registers while layer z
@@ -145,7 +156,7 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
         const int64_t zoff = (int64_t)K * K * wrap_tile(z, K);
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            const int i = t + 256 * k;
+            const int i = t + THREADS * k;
             if (i < NX * NY) {
                 const int64_t n = node_xy[k] + zoff;
                 pf[k][0] = uin[n];
@@ -158,9 +169,9 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
         const int64_t zoff = (int64_t)K * K * wrap_tile(z, K);
 #pragma unroll
         for (int k = 0; k < VP; ++k) {
-            const int i = t + 256 * k;
+            const int i = t + THREADS * k;
             sp[k] = 0;
-            if (i < kStepVox) sp[k] = spins[vox_xy[k] + zoff];
+            if (i < NVOX) sp[k] = spins[vox_xy[k] + zoff];
         }
     };
     // pf holds node layer z+1 and prev layer z: write the pair's S and D, and layer z+1's own
@@ -168,13 +179,13 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
     auto store_pair = [&](int raw) {
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            const int i = t + 256 * k;
+            const int i = t + THREADS * k;
             if (i < NX * NY) {
                 const int ix = i % NX, iy = i / NX;
                 pair_node_entry(pf[k], prev[k], sNa[iy][ix], sNb[iy][ix]);
 #pragma unroll
                 for (int j = 0; j < 3; ++j) prev[k][j] = pf[k][j];
-                if (ix >= 1 && ix <= kTileX && iy >= 1 && iy <= kTileY)
+                if (ix >= 1 && ix <= kTileX && iy >= 1 && iy <= TY)
                     sraw[raw][iy - 1][ix - 1] = make_float4(pf[k][0], pf[k][1], pf[k][2], 0.f);
             }
         }
@@ -182,7 +193,7 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
     // stress of voxel position k of the layer whose node pair is in sNa / sNb (grains in q)
     auto voxel_stress = [&](int k, int q, float s6[6]) {
         int ix, iy;
-        step_voxel_pos(t + 256 * k, ix, iy);
+        step_voxel_pos<TY>(t + THREADS * k, ix, iy);
         float e[6];
         pair_strain<NX>(sNa, sNb, ix, iy, E, e);
         symv21_grains(Ctab, q, e, s6);
@@ -204,7 +215,7 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
     float sprev[VP][6];
 #pragma unroll
     for (int k = 0; k < VP; ++k)
-        if (t + 256 * k < kStepVox) voxel_stress(k, sp[k], sprev[k]);
+        if (t + THREADS * k < NVOX) voxel_stress(k, sp[k], sprev[k]);
     fetch_nodes(z0 + 1);
     fetch_spins(z0);
     __syncthreads();                             // the prologue's reads of sNa / sNb are done
@@ -225,7 +236,7 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
         const int64_t n = nx + (int64_t)K * (ny + (int64_t)K * z);
         if (own) {
 #pragma unroll
-            for (int j = 0; j < 3; ++j) wz[j] = w[(int64_t)j * P + n];
+            for (int j = 0; j < 3; ++j) wz[j] = NT ? __builtin_nontemporal_load(&w[(int64_t)j * P + n]) : w[(int64_t)j * P + n];
         }
         if (z + 1 < z1) {
             fetch_nodes(z + 2);                  // in flight during this layer
@@ -234,10 +245,10 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
         __syncthreads();                         // the node pair is complete
 #pragma unroll
         for (int k = 0; k < VP; ++k) {
-            const int i = t + 256 * k;
-            if (i >= kStepVox) continue;
+            const int i = t + THREADS * k;
+            if (i >= NVOX) continue;
             int ix, iy;
-            step_voxel_pos(i, ix, iy);
+            step_voxel_pos<TY>(i, ix, iy);
             float s6[6];
             voxel_stress(k, sp_cur[k], s6);
             pair_voxel_entry(s6, sprev[k], sPa[iy][ix], sPb[iy][ix]);
@@ -259,17 +270,22 @@ __global__ __launch_bounds__(256, 4) void k_global_step_tiled(GlobArgs a)
             for (int j = 0; j < 3; ++j) {
                 const int64_t idx = (int64_t)j * P + n;
                 const float wn = beta * wz[j] - alpha4 * F[j];
-                w[idx] = wn;
-                uout[idx] = uz[j] + wn;
+                if (NT) {
+                    __builtin_nontemporal_store(wn, &w[idx]);
+                    __builtin_nontemporal_store(uz[j] + wn, &uout[idx]);
+                } else {
+                    w[idx] = wn;
+                    uout[idx] = uz[j] + wn;
+                }
             }
         }
         ring = ring_next;
     }
-    const double tot = block_total<6>(acc);
-    if (threadIdx.x < 6) {
-        const unsigned copy = (unsigned)(lb - R.tile_first) & (kSumCopies - 1);
-        atomicAdd(a.sums_out + (int64_t)r * kSumSlots + copy * 8 + threadIdx.x,
-                  (unsigned long long)llrint(tot * kSumScale));
+    const double tot = block_total_quads<6, TY / 8>(acc);
+    const int k = threadIdx.x & 255;             // total k of the half threadIdx.x / 256
+    if (k < 6) {
+        const unsigned copy = (unsigned)(lb - R.tile_first + (threadIdx.x >> 8)) & (kSumCopies - 1);
+        atomicAdd(a.sums_out + (int64_t)r * kSumSlots + copy * 8 + k, (unsigned long long)llrint(tot * kSumScale));
     }
 }
 
@@ -484,7 +500,18 @@ hipError_t seq_step(hmc_ctx_s* c, hipStream_t s, int i, const float* uin, float*
     a.order = c->block_order;
     a.plane = c->total_sites;
     const int tok = s == c->stream ? prof_begin(c, kProfRefreshStep) : -1;
-    hipLaunchKernelGGL(k_global_step_tiled, dim3(c->tile_blocks), dim3(256), 0, s, a);
+    const dim3 g(c->tile_blocks);
+    if (c->reps[0].tile_y == 16) {
+        if (c->step_streams)
+            hipLaunchKernelGGL((k_global_step_tiled<16, true>), g, dim3(kTileX * 16), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_global_step_tiled<16, false>), g, dim3(kTileX * 16), 0, s, a);
+    } else {
+        if (c->step_streams)
+            hipLaunchKernelGGL((k_global_step_tiled<8, true>), g, dim3(kTileX * 8), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_global_step_tiled<8, false>), g, dim3(kTileX * 8), 0, s, a);
+    }
     prof_end(c, tok);
     return hipGetLastError();
 }

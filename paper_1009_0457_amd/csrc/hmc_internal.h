@@ -52,20 +52,32 @@ __device__ __forceinline__ int xcd_block(int b, int G)
 }
 
 // Logical block order of a launch: 0 the XCD-aware order above; 1 reversed; 2 a fixed shuffle
-// (x -> x * 1000003 mod G, a bijection since the prime exceeds any grid).  Results must not
-// depend on it: orders 1 and 2 exist to show that no kernel relies on which work-group runs
-// which part of the work, or when (hmc_set_block_order).
-__device__ __forceinline__ int logical_block(int b, int G, int order)
+// (x -> x * 1000003 mod G, a bijection of [0, G) whenever the prime does not divide G; reversed
+// when it does).  Results must not depend on it: orders 1 and 2 exist to show that no kernel
+// relies on which work-group runs which part of the work, or when (hmc_set_block_order).
+__device__ __forceinline__ int reorder_block(int x, int G, int order)
 {
-    const int x = xcd_block(b, G);
-    if (order == 1) return G - 1 - x;
-    if (order == 2) return (int)(((long long)x * 1000003LL) % (long long)G);
+    if (order == 2 && G % 1000003 != 0) return (int)(((long long)x * 1000003LL) % (long long)G);
+    if (order != 0) return G - 1 - x;
     return x;
 }
 
-__host__ __device__ constexpr int tile_blocks_of(int K, int tz)
+__device__ __forceinline__ int logical_block(int b, int G, int order)
 {
-    return ((K + kTileX - 1) / kTileX) * ((K + kTileY - 1) / kTileY) * ((K + tz - 1) / tz);
+    return reorder_block(xcd_block(b, G), G, order);
+}
+
+// The same orders for grid-stride loops over a work list that may fill only part of the
+// grid: order 0 keeps the dispatch index, so that the busy work-groups spread over all XCDs
+// (under the XCD-aware order they would fill the first XCDs and leave the others idle).
+__device__ __forceinline__ int stride_block(int b, int G, int order)
+{
+    return reorder_block(b, G, order);
+}
+
+__host__ __device__ constexpr int tile_blocks_of(int K, int tz, int ty = kTileY)
+{
+    return ((K + kTileX - 1) / kTileX) * ((K + ty - 1) / ty) * ((K + tz - 1) / tz);
 }
 
 // Device description of one replica.
@@ -73,6 +85,7 @@ struct RepDev {
     int32_t K, Kh, Q, proposal;
     int32_t elastic;                 // elastic term on for this replica (lambda != 0, load != 0)
     int32_t tile_z;                  // node layers per block of the tiled explicit step
+    int32_t tile_y;                  // node rows per block of the forward explicit step (8 or 16)
     int64_t n3;
     int64_t site_off;                // into spins / sigma / u / w planes (sites)
     int64_t grain_off;               // into Ctab / Stab (grains)
@@ -160,6 +173,7 @@ struct hmc_ctx_s {
     int pass_blocks = 0;            // total blocks of a colour pass
     int node_blocks = 0;            // total blocks of node kernels
     int tile_blocks = 0;            // total blocks of the tiled explicit step
+    bool step_streams = false;      // explicit step: own-node u and w read / written non-temporally
     bool elastic_buffers = false;
     bool have_orient = false, have_spins = false, have_load = false, have_stress = false;
     bool have_state = false;

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(64) void k_zone(ZoneArgs a)
     const int lane = threadIdx.x;
     const uint32_t count = *a.count;
 
-    for (uint32_t e = (uint32_t)logical_block((int)blockIdx.x, (int)gridDim.x, a.order); e < count; e += gridDim.x) {
+    for (uint32_t e = (uint32_t)stride_block((int)blockIdx.x, (int)gridDim.x, a.order); e < count; e += gridDim.x) {
         const TrialEntry ent = a.list[e];
         const TrialCtx tc = trial_ctx(a, ent.qr);
         const int K = tc.K;
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256, 2) void k_zone_col(ZoneArgs a)
     const uint32_t count = *a.count;
     const float alpha16 = a.alpha * 0.0625f, beta = a.beta;
 
-    for (uint32_t base = (uint32_t)logical_block((int)blockIdx.x, (int)gridDim.x, a.order) * (uint32_t)Z; base < count;
+    for (uint32_t base = (uint32_t)stride_block((int)blockIdx.x, (int)gridDim.x, a.order) * (uint32_t)Z; base < count;
          base += gridDim.x * (uint32_t)Z) {
         const uint32_t e = base + (uint32_t)zsafe;
         const bool active = in_zone && e < count;
@@ -659,7 +659,7 @@ __global__ __launch_bounds__(64 * WAVES, H == 1 ? 3 : 2) void k_zone_lane(ZoneAr
     // solves and acceptances are counted per lane and added to the statistics once per
     // work-group at the end (same-address atomics per trial would serialise in L2)
     uint32_t n_solved = 0, n_accepted = 0;
-    for (uint32_t base = (uint32_t)logical_block((int)blockIdx.x, (int)gridDim.x, a.order) * (uint32_t)Z; base < count;
+    for (uint32_t base = (uint32_t)stride_block((int)blockIdx.x, (int)gridDim.x, a.order) * (uint32_t)Z; base < count;
          base += gridDim.x * (uint32_t)Z) {
         const uint32_t e = base + (uint32_t)(member ? zs : 0);
         const bool active = member && e < count;

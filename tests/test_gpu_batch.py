@@ -101,6 +101,95 @@ def test_batch_equals_replicas_run_alone(graphs):
     b.close()
 
 
+def test_explicit_step_tile_heights_agree():
+    """A 48^3 replica alone runs the forward explicit step on 32 x 16 node tiles (every edge a
+    multiple of 16); batched with a 40^3 replica it runs on 32 x 8 tiles.  The 16-row tile
+    totals its two 8-row halves on their own, so the stress fields and stored energies agree
+    bit for bit, and so do the spins and stresses of the sweeps that follow."""
+    common = H.hmc_default_params(48, 26, 2)
+    common.refresh_every = 2
+    common.refresh_steps = 90
+    common.cold_steps = 200
+    common.zone_steps = 60
+    common.refresh_tile_z = 4      # the same tile depth alone and in the batch
+    reps, micros = [], []
+    for r, (K, G) in enumerate(((48, 40), (40, 30))):
+        m = voronoi_polycrystal(K, G, 200 + r)
+        rep = H.hmc_default_replica(common, K, m.Q)
+        rep.kT, rep.seed = 0.7, 11 + r
+        rep.sigma_MPa[0], rep.sigma_MPa[5] = 180.0, -60.0 * (r + 1)
+        reps.append(rep)
+        micros.append(m)
+    say(f"[tile heights] K={[r.K for r in reps]} tile_z=4")
+    b = H.Batch(common, reps)
+    for r, m in enumerate(micros):
+        b.set_replica(r, m.euler, m.spins)
+    b.stress_refresh(-1, True)
+    sig_b = b.get_stress(0).cpu().numpy()
+    e_b = b.energy(0)
+    b.sweep(4)
+    b.synchronize()
+    spins_b, sig_b4 = b.get_spins(0).cpu().numpy(), b.get_stress(0).cpu().numpy()
+    b.close()
+
+    p = H.hmc_params.from_buffer_copy(common)
+    rep, m = reps[0], micros[0]
+    p.K, p.kT, p.lambda_el, p.seed = rep.K, rep.kT, rep.lambda_el, rep.seed
+    p.glob_alpha, p.glob_beta, p.glob_alphaE = rep.glob_alpha, rep.glob_beta, rep.glob_alphaE
+    lat = H.Lattice(p, m.Q)
+    lat.set_orientations(m.euler)
+    lat.set_spins(m.spins)
+    lat.set_load(list(rep.sigma_MPa))
+    lat.stress_refresh(-1, True)
+    sig_a, e_a = lat.get_stress().cpu().numpy(), lat.energy()
+    lat.sweep(4)
+    spins_a, sig_a4 = lat.get_spins().cpu().numpy(), lat.get_stress().cpu().numpy()
+    lat.close()
+    assert np.array_equal(sig_a, sig_b)
+    assert e_a == e_b
+    assert np.array_equal(spins_a, spins_b)
+    assert np.array_equal(sig_a4, sig_b4)
+
+
+def test_streamed_explicit_step_equals_cached_step():
+    """Two 160^3 replicas together (8.2 M sites, more than the Infinity Cache holds of the
+    step's arrays) run the explicit step with non-temporal own-node accesses; one alone
+    (4.1 M sites) with ordinary ones.  The stress fields and energies agree bit for bit."""
+    common = H.hmc_default_params(160, 26, 1)
+    common.refresh_steps = 60
+    common.cold_steps = 120
+    common.refresh_tile_z = 16
+    reps, micros = [], []
+    for r in range(2):
+        m = voronoi_polycrystal(160, 200, 300 + r)
+        rep = H.hmc_default_replica(common, 160, m.Q)
+        rep.sigma_MPa[2], rep.sigma_MPa[3] = 150.0, 40.0 * (r + 1)
+        reps.append(rep)
+        micros.append(m)
+    say("[streamed step] 2 x 160^3 batched against the first alone")
+    b = H.Batch(common, reps)
+    for r, m in enumerate(micros):
+        b.set_replica(r, m.euler, m.spins)
+    b.stress_refresh(-1, True)
+    b.stress_refresh(-1, False)
+    sig_b, e_b = b.get_stress(0).cpu().numpy(), b.energy(0)
+    b.close()
+    p = H.hmc_params.from_buffer_copy(common)
+    rep, m = reps[0], micros[0]
+    p.K, p.kT, p.lambda_el, p.seed = rep.K, rep.kT, rep.lambda_el, rep.seed
+    p.glob_alpha, p.glob_beta, p.glob_alphaE = rep.glob_alpha, rep.glob_beta, rep.glob_alphaE
+    lat = H.Lattice(p, m.Q)
+    lat.set_orientations(m.euler)
+    lat.set_spins(m.spins)
+    lat.set_load(list(rep.sigma_MPa))
+    lat.stress_refresh(-1, True)
+    lat.stress_refresh(-1, False)
+    sig_a, e_a = lat.get_stress().cpu().numpy(), lat.energy()
+    lat.close()
+    assert np.array_equal(sig_a, sig_b)
+    assert e_a == e_b
+
+
 @pytest.mark.parametrize("loaded", [False, True])
 def test_batch_of_large_replicas_equals_alone(loaded):
     """Four 128^3 replicas fill 1024 chunks per colour pass, so at zero load the batch runs the

@@ -124,9 +124,11 @@ def test_zero_load_energy_and_resume():
 # --------------------------------------------------------------------------------------
 @pytest.mark.parametrize("K,ng,steps,tile_z", [(8, 5, 300, 0), (16, 8, 500, 0), (20, 30, 200, 0), (20, 30, 200, 2),
                                                (20, 30, 200, 8), (18, 20, 150, 4), (18, 20, 150, 8),
-                                               (34, 40, 120, 16), (34, 40, 120, 32)])
+                                               (34, 40, 120, 16), (34, 40, 120, 32), (32, 30, 150, 0),
+                                               (48, 40, 120, 4), (48, 40, 120, 32)])
 def test_refresh_matches_oracle(K, ng, steps, tile_z):
-    """Every tile depth of the explicit step, including tiles cut short by the lattice edge."""
+    """Every tile depth of the explicit step, including tiles cut short by the lattice edge, and
+    both tile heights (16 rows when K is a multiple of 16: 16, 32, 48; 8 rows otherwise)."""
     say(f"[refresh] K={K} grains={ng} steps={steps} tile_z={tile_z}")
     micro = voronoi_polycrystal(K, ng, 9)
     p, lat = make_lattice(K, 26, 1, micro, refresh_tile_z=tile_z)
