@@ -48,14 +48,14 @@ def zone_flops_per_solve(h: int, nr: int) -> float:
 REFRESH_BYTES_PER_NODE_STEP = 50.0   # read u, w (24 B) + write u, w (24 B) + spin (2 B)
 
 
-def measured_traffic(key_bytes, key_hash, source):
-    """HBM bytes from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, valid only while
+def measured_traffic(key_bytes, key_hash, source, summary="counters_large128.md"):
+    """HBM bytes from a committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, valid only while
     the kernel source still has the hash it had when the counters were taken (else None)."""
     import hashlib
 
     try:
         vals = {}
-        for line in open(os.path.join(ROOT, "profiles", "counters_large128.md")):
+        for line in open(os.path.join(ROOT, "profiles", summary)):
             if "=" in line and not line.startswith(("|", "`", "cd ")):
                 k, v = (t.strip() for t in line.split("=", 1))
                 vals[k] = v
@@ -104,6 +104,9 @@ def parse():
     ap.add_argument("--zero-load", action="store_true",
                     help="the same lattice with no load: the elastic term is off and every trial is decided "
                          "by the integer threshold table inside the colour pass")
+    ap.add_argument("--bandwidth-K", type=int, default=512,
+                    help="large: also time the colour pass and the explicit step on the grain structure refined "
+                         "to this edge (a multiple of 128; 0 skips)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -452,10 +455,13 @@ def bench_adjoint(a):
 def big_lattice(a, default_K=512):
     """The large workload's grain structure on a bigger lattice (K a multiple of 128: each
     128^3 Voronoi site refined into a block), for bandwidth measurements beyond the caches."""
+    return big_lattice_of(a.K or default_K)
+
+
+def big_lattice_of(K):
     from paper_1009_0457_amd.synth import large_config, refined_polycrystal, voronoi_polycrystal
 
     cfg = large_config()
-    K = a.K or default_K
     if K % cfg.K == 0:
         micro = refined_polycrystal(K, K // cfg.K, cfg.n_grains, cfg.seed)
     else:
@@ -463,32 +469,29 @@ def big_lattice(a, default_K=512):
     return cfg, K, micro
 
 
-def bench_potts(a):
-    """Zero-load colour passes (integer thresholds decide inside the pass) on a lattice whose
-    spins (2 B per site) exceed the 256 MB Infinity Cache."""
+def measure_potts(cfg, K, micro, proposal, steps, warmup):
+    """Zero-load sweeps with kernel timing on: (elapsed s, statistics, colour-pass roofline)."""
     import numpy as np
     import torch
 
     from paper_1009_0457_amd import hmc as H
 
-    cfg, K, micro = big_lattice(a)
-    log(f"[bench] potts: {K}^3, {micro.Q} grains, zero load")
     p = H.hmc_default_params(K, cfg.neighbors, cfg.zone_h)
     p.kT = cfg.kT
-    p.proposal = 0 if a.proposal == "neighbor" else 1
+    p.proposal = 0 if proposal == "neighbor" else 1
     p.seed = cfg.philox_seed
     lat = H.Lattice(p, micro.Q)
     lat.set_orientations(micro.euler)
     lat.set_spins(micro.spins)
     lat.set_load(np.zeros(6))
-    for _ in range(a.warmup):
+    for _ in range(warmup):
         lat.sweep(1)
     torch.cuda.synchronize()
     lat.reset_stats()
     lat.kernel_times()
     lat.set_profiling(True)
     t0 = time.perf_counter()
-    lat.sweep(a.steps)
+    lat.sweep(steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     lat.set_profiling(False)
@@ -499,17 +502,29 @@ def bench_potts(a):
     bytes_pass = (2 * colours + 2) * K ** 3 / colours
     ms = kt["total_ms"] / max(1, kt["launches"])
     ach = bytes_pass / (ms * 1e-3) / 1e9
+    tr = measured_traffic("potts512_pass_traffic_bytes_per_launch", "potts_source_sha256_16", "hmc_potts.hip",
+                          "bandwidth512.md") if K == 512 else None
+    roof = {"kernel": "colour pass", "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None if tr is None else round(tr),
+            "avg_launch_ms": round(ms, 4), "launches": kt["launches"],
+            "note": f"(2C+2) bytes of spins per site-trial; lattice {2 * K ** 3 / 2 ** 20:.0f} MiB"}
+    return el, st, roof
+
+
+def bench_potts(a):
+    """Zero-load colour passes (integer thresholds decide inside the pass) on a lattice whose
+    spins (2 B per site) exceed the 256 MB Infinity Cache."""
+    cfg, K, micro = big_lattice(a)
+    log(f"[bench] potts: {K}^3, {micro.Q} grains, zero load")
+    el, st, roof = measure_potts(cfg, K, micro, a.proposal, a.steps, a.warmup)
     out = {"metric": "site-trials/sec at zero load (colour passes, integer Metropolis thresholds)",
            "value": a.steps * K ** 3 / el, "unit": "site-trials/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
            "ms_per_step": el / a.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "int16", "data": "synthetic",
            "config": {"workload": f"potts-{K}: {K}^3 periodic, 26 neighbours / 8 colours, the 128^3 4000-grain "
-                                  f"Voronoi structure refined x{K // 128 if K % 128 == 0 else 1}, no load, kT {p.kT}, "
+                                  f"Voronoi structure refined x{K // 128 if K % 128 == 0 else 1}, no load, kT {cfg.kT}, "
                                   f"proposal {a.proposal}", "K": K},
-           "roofline": {"kernel": "colour pass", "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
-                        "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
-                        "avg_launch_ms": round(ms, 4),
-                        "note": f"(2C+2) bytes of spins per site-trial; lattice {2 * K ** 3 / 2 ** 20:.0f} MiB"},
+           "roofline": roof,
            "real_flip_fraction": st["real_flips"] / max(1, st["site_trials"]),
            "acceptance": st["accepted"] / max(1, st["real_flips"])}
     print(json.dumps(out), flush=True)
@@ -717,26 +732,21 @@ def bench_texture(a):
     print(json.dumps(out), flush=True)
 
 
-def bench_refresh(a):
-    """Explicit global steps (Sec. 5 relaxation) on a lattice whose 54 B/site working set
-    exceeds the 256 MB Infinity Cache."""
+def measure_refresh(cfg, K, micro, n, warm, tile_z=0, mp8=False):
+    """Warm explicit steps with kernel timing on: (elapsed s, explicit-step roofline, fold ms)."""
     import torch
 
     from paper_1009_0457_amd import hmc as H
 
-    cfg, K, micro = big_lattice(a)
-    n = a.steps * 10
-    log(f"[bench] refresh: {K}^3, {micro.Q} grains, {n} steps")
     p = H.hmc_default_params(K, cfg.neighbors, cfg.zone_h)
-    p.refresh_tile_z = a.tile_z
-    mp8 = a.material_points == 8
+    p.refresh_tile_z = tile_z
     if mp8:
         H.hmc_set_material_points(p, 8)
     lat = H.Lattice(p, micro.Q)
     lat.set_orientations(micro.euler)
     lat.set_spins(micro.spins)
     lat.set_load(cfg.sigma_MPa)
-    lat.stress_refresh(max(1, a.warmup * 10), True)
+    lat.stress_refresh(max(1, warm), True)
     torch.cuda.synchronize()
     lat.kernel_times()
     lat.set_profiling(True)
@@ -753,6 +763,25 @@ def bench_refresh(a):
     # 16 B, 24 corner forces written 96 B and read back 96 B, u and w read and written 48 B
     per_site = 268.0 / 8 if mp8 else REFRESH_BYTES_PER_NODE_STEP
     ach = per_site * K ** 3 / (ms * 1e-3) / 1e9
+    tr = measured_traffic("refresh512_step_traffic_bytes_per_launch", "elastic_source_sha256_16", "hmc_elastic.hip",
+                          "bandwidth512.md") if (K == 512 and not mp8 and tile_z == 0) else None
+    roof = {"kernel": "global explicit step", "bound": "hbm", "achieved": round(ach, 1),
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
+            "traffic": None if tr is None else round(tr), "avg_launch_ms": round(ms, 4), "launches": ks["launches"],
+            "note": (f"{per_site} B per site-step (cell pass, node pass and E fold)" if mp8 else
+                     f"50 B per node-step; working set {(13 * 4 + 2) * K ** 3 / 2 ** 30:.2f} GiB")}
+    fold = round(kt["refresh_other"]["total_ms"] / max(1, kt["refresh_other"]["launches"]), 4)
+    return el, roof, fold
+
+
+def bench_refresh(a):
+    """Explicit global steps (Sec. 5 relaxation) on a lattice whose 54 B/site working set
+    exceeds the 256 MB Infinity Cache."""
+    cfg, K, micro = big_lattice(a)
+    n = a.steps * 10
+    mp8 = a.material_points == 8
+    log(f"[bench] refresh: {K}^3, {micro.Q} grains, {n} steps")
+    el, roof, fold = measure_refresh(cfg, K, micro, n, a.warmup * 10, a.tile_z, mp8)
     out = {"metric": "explicit global stress-refresh steps/sec", "value": n / el, "unit": "steps/s", "n_gpus": 1,
            "steps": n, "warmup": a.warmup * 10, "ms_per_step": el / n * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -760,12 +789,8 @@ def bench_refresh(a):
                                   f"x{K // 128 if K % 128 == 0 else 1}, biaxial 150/150 MPa, warm steps"
                                   + (", 2x2x2 material points per cell of 2^3 sites" if mp8 else ""), "K": K,
                       "tile_z": a.tile_z, "material_points": 8 if mp8 else 1},
-           "roofline": {"kernel": "global explicit step", "bound": "hbm", "achieved": round(ach, 1),
-                        "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
-                        "avg_launch_ms": round(ms, 4),
-                        "note": (f"{per_site} B per site-step (cell pass, node pass and E fold)" if mp8 else
-                                 f"50 B per node-step; working set {(13 * 4 + 2) * K ** 3 / 2 ** 30:.2f} GiB")},
-           "fold_ms": round(kt["refresh_other"]["total_ms"] / max(1, kt["refresh_other"]["launches"]), 4)}
+           "roofline": roof,
+           "fold_ms": fold}
     print(json.dumps(out), flush=True)
 
 
@@ -978,7 +1003,24 @@ def main():
         out["cpu_baseline"]["small_configs"] = small_configs()
     else:
         lat.close()
+    if a.bandwidth_K:
+        out["beyond_caches"] = bandwidth_leg(a.bandwidth_K)
     print(json.dumps(out), flush=True)
+
+
+def bandwidth_leg(K):
+    """The two bandwidth-bound kernels on the large workload's grain structure refined to K^3
+    (512^3: 256 MiB of spins and 6.75 GiB of explicit-step arrays, beyond the 256 MB Infinity
+    Cache): zero-load colour passes and warm explicit steps, kernel timing on."""
+    cfg, K, micro = big_lattice_of(K)
+    log(f"[bench] beyond the caches: {K}^3 colour passes and explicit steps")
+    sweeps, steps = 10, 40
+    _, st, potts = measure_potts(cfg, K, micro, "neighbor", sweeps, 2)
+    _, step, _ = measure_refresh(cfg, K, micro, steps, 20)
+    return {"workload": f"{K}^3 periodic, the 128^3 4000-grain Voronoi structure refined x{K // 128}, 26 neighbours / "
+                        f"8 colours: {sweeps} zero-load sweeps, then {steps} warm explicit steps under biaxial 150/150 MPa",
+            "colour_pass": potts, "explicit_step": step,
+            "real_flip_fraction": st["real_flips"] / max(1, st["site_trials"])}
 
 
 def saturation_line(a, p, micro, lat, cfg):
