@@ -252,55 +252,73 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
     ActiveWalk walk = walk_start(first, Kh, NJ);
 
     // ---- phase 1: draws, proposals; real flips to the wavefront's list ----
+    // In three stages, so that all of a thread's spin reads are in flight together: the sites
+    // and their draws (arithmetic only), then every own and proposed-neighbour spin read, then
+    // the decisions and the list appends.
+    uint32_t site[SPT], packed[SPT], nbr[SPT], r0[SPT], r1[SPT];
+    bool ok[SPT];
 #pragma unroll
     for (int it = 0; it < SPT; ++it) {
-        const uint32_t t = first + (uint32_t)it * 256u;
-        bool real = false;
-        uint32_t packed = 0, qq = 0, r1 = 0, site = 0;
-        int q_new = 0;
         if (it > 0) walk_advance(walk, Kh, NJ, di, dr);
-        if (t < n_active) {
-            int x, y, z;
-            walk_site<M>(walk, a.colour, x, y, z);
-            site = site_of(x, y, z, K, KK);
-            const Philox4 rn = philox4x32_10(site, sweep, 0u, 0u, R.key0, R.key1);
-            r1 = rn.v[1];
-            const char* sb = reinterpret_cast<const char*>(spins);
-            const int q_old = *reinterpret_cast<const int16_t*>(sb + 2u * site);
-            if (R.proposal == 0) {
-                const int k = (int)__umulhi(rn.v[0], (uint32_t)M);
-                int dx, dy, dz;
-                slot_offset<M>(k, dx, dy, dz);
-                uint32_t nb;
-                if (pow2)   // uniform branch: a power-of-two edge wraps by a mask
-                    nb = site_of((x + dx) & Km, (y + dy) & Km, (z + dz) & Km, K, KK);
-                else
-                    nb = site_of(wrapi(x + dx, K), wrapi(y + dy, K), wrapi(z + dz, K), K, KK);
-                q_new = *reinterpret_cast<const int16_t*>(sb + 2u * nb);
-            } else {
-                const uint32_t step = __umulhi(rn.v[0], (uint32_t)(R.Q - 1));
-                q_new = (int)(((uint32_t)q_old + 1u + step) % (uint32_t)R.Q);
+        ok[it] = first + (uint32_t)it * 256u < n_active;
+        int x, y, z;
+        walk_site<M>(walk, a.colour, x, y, z);
+        site[it] = site_of(x, y, z, K, KK);
+        packed[it] = (uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20);
+        const Philox4 rn = philox4x32_10(site[it], sweep, 0u, 0u, R.key0, R.key1);
+        r0[it] = rn.v[0];
+        r1[it] = rn.v[1];
+        nbr[it] = site[it];
+        if (R.proposal == 0) {
+            const int k = (int)__umulhi(rn.v[0], (uint32_t)M);
+            int dx, dy, dz;
+            slot_offset<M>(k, dx, dy, dz);
+            if (pow2)   // uniform branch: a power-of-two edge wraps by a mask
+                nbr[it] = site_of((x + dx) & Km, (y + dy) & Km, (z + dz) & Km, K, KK);
+            else
+                nbr[it] = site_of(wrapi(x + dx, K), wrapi(y + dy, K), wrapi(z + dz, K), K, KK);
+        }
+    }
+    int q_old[SPT], q_nb[SPT];
+    const char* sb = reinterpret_cast<const char*>(spins);
+#pragma unroll
+    for (int it = 0; it < SPT; ++it) {
+        q_old[it] = 0;
+        q_nb[it] = 0;
+        if (ok[it]) {
+            q_old[it] = *reinterpret_cast<const int16_t*>(sb + 2u * site[it]);
+            q_nb[it] = *reinterpret_cast<const int16_t*>(sb + 2u * nbr[it]);
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < SPT; ++it) {
+        bool real = false;
+        uint32_t qq = 0;
+        if (ok[it]) {
+            int q_new = q_nb[it];
+            if (R.proposal != 0) {
+                const uint32_t step = __umulhi(r0[it], (uint32_t)(R.Q - 1));
+                q_new = (int)(((uint32_t)q_old[it] + 1u + step) % (uint32_t)R.Q);
             }
-            real = (q_new != q_old);
-            packed = (uint32_t)x | ((uint32_t)y << 10) | ((uint32_t)z << 20);
-            qq = (uint32_t)q_old | ((uint32_t)q_new << 16);
+            real = (q_new != q_old[it]);
+            qq = (uint32_t)q_old[it] | ((uint32_t)q_new << 16);
             if (!real && a.rec) {
                 hmc_trial_record rc;
                 rc.q_new = q_new;
                 rc.gb = 0;
                 rc.dPi = 0.0f;
-                rc.r1 = r1;
+                rc.r1 = r1[it];
                 rc.flags = 0;
                 rc.reserved = 0;
-                a.rec[R.site_off + site] = rc;
+                a.rec[R.site_off + site[it]] = rc;
             }
         }
         const unsigned long long m = __ballot(real);
         if (real) {
             const uint32_t j = n_wave + (uint32_t)__popcll(m & below);
-            s_item[wid][j][0] = packed;
+            s_item[wid][j][0] = packed[it];
             s_item[wid][j][1] = qq;
-            s_item[wid][j][2] = r1;
+            s_item[wid][j][2] = r1[it];
         }
         n_wave += (uint32_t)__popcll(m);
         n_real += real ? 1u : 0u;
