@@ -86,10 +86,12 @@ typedef struct {
                                Decisions are those of the full solve; the trial's record then
                                carries flag 8 and no dPi.  0: solve every real flip. */
     int32_t refresh_tile_z; /* node layers per work-group of the explicit global step and of its
-                               adjoint: 1, 2, 4, 8, 16 or 32, or 0 to pick the deepest tile that
-                               still gives at least 1024 work-groups (2 rather than 1; 1 if none
-                               does): shallower tiles recompute more halo voxels but fill the GPU
-                               on small lattices.  Other values: HMC_EINVAL. */
+                               adjoint, at most: 1, 2, 4, 8, 16 or 32, or 0 to pick the deepest
+                               tile that still gives at least 1024 work-groups of 256 threads
+                               (2 rather than 1; 1 if none does): shallower tiles recompute more
+                               halo voxels but fill the GPU on small lattices.  A lattice of edge
+                               K takes n = ceil(K / t) z-tiles of ceil(K / n) layers each.  Other
+                               values: HMC_EINVAL. */
     int32_t material_points;/* material points of the global solve: 0 or 1, one per site at the
                                centre of its voxel (mesh = lattice, the default); 8, two per
                                direction in background cells of 2 x 2 x 2 sites (the paper's MPM

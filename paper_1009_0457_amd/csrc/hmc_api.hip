@@ -111,11 +111,21 @@ int tile_rows_of(int n, const hmc_replica* r)
 
 // Whether the explicit step streams its own nodes' u and w past the caches: when the arrays a
 // step reads and writes (u in, u out, w: 36 bytes per node, and the 2-byte grain ids) are
-// larger than the 256 MB Infinity Cache, which then cannot keep them from one step to the
-// next.  Below that, ordinary accesses let the next step find them there.  Measured (32 x 16
-// tiles): 128^3 (80 MB) 37.0 us plain against 42.2 us non-temporal; 256^3 (640 MB) 250 against
-// 238 us; 512^3 1.73 against 1.66 ms.
-bool step_streams_of(int64_t sites) { return sites * 38 > (int64_t)256 << 20; }
+// more than twice the 256 MB Infinity Cache, which then keeps little of them from one step to
+// the next.  Below that, ordinary accesses let the next step find much of them there.
+// Measured: 128^3 (80 MB, 32 x 16 tiles) 37.0 us plain against 42.2 us non-temporal; ten 100^3
+// runs (380 MB, 32 x 8 tiles) 234 against 281 us; 256^3 (640 MB) 250 against 238 us; 512^3
+// 1.73 against 1.66 ms.
+bool step_streams_of(int64_t sites) { return sites * 38 > (int64_t)512 << 20; }
+
+// Node layers per block of one replica's explicit step: as many z-tiles as depth t gives, made
+// equal (a 100-layer lattice at t = 32 takes four tiles of 25 layers instead of 32, 32, 32 and
+// 4), so that no block marches further than it has to.
+int balanced_depth(int t, int K)
+{
+    const int n = (K + t - 1) / t;
+    return (K + n - 1) / n;
+}
 
 // Node layers per block of the tiled explicit step: the caller's choice, else the deepest
 // tile that still launches at least 256K threads over all replicas (1024 blocks of 256 or 512
@@ -150,7 +160,7 @@ Layout layout_of(const hmc_params* p, int n, const hmc_replica* r)
         int64_t nb = (n3 + kSiteBlock - 1) / kSiteBlock;
         if (nb > kMaxChunkBlocks) nb = kMaxChunkBlocks;
         L.node_blocks += (int)nb;
-        L.tile_blocks += tile_blocks_of(r[i].K, L.tile_z, L.tile_y);
+        L.tile_blocks += tile_blocks_of(r[i].K, balanced_depth(L.tile_z, r[i].K), L.tile_y);
         L.elastic = L.elastic || r[i].lambda_el != 0.0;
     }
     size_t o = 0;
@@ -574,7 +584,7 @@ hmc_status build_context(const hmc_params* p, int n, const hmc_replica* r, void*
         int64_t nb = (R.n3 + kSiteBlock - 1) / kSiteBlock;
         R.node_blocks = (int)(nb > kMaxChunkBlocks ? kMaxChunkBlocks : nb);
         R.tile_first = tf;
-        R.tile_z = L.tile_z;
+        R.tile_z = balanced_depth(L.tile_z, R.K);
         R.tile_y = L.tile_y;
         R.tile_blocks = tile_blocks_of(R.K, R.tile_z, R.tile_y);
         R.J = p->J;

@@ -152,30 +152,29 @@ def test_explicit_step_tile_heights_agree():
 
 
 def test_streamed_explicit_step_equals_cached_step():
-    """Two 160^3 replicas together (8.2 M sites, more than the Infinity Cache holds of the
-    step's arrays) run the explicit step with non-temporal own-node accesses; one alone
-    (4.1 M sites) with ordinary ones.  The stress fields and energies agree bit for bit."""
+    """Four 160^3 replicas together (16.4 M sites: 620 MB of explicit-step arrays, more than
+    twice the Infinity Cache) run the explicit step with non-temporal own-node accesses; one
+    alone (4.1 M sites) with ordinary ones.  The stress fields and energies agree bit for bit."""
     common = H.hmc_default_params(160, 26, 1)
     common.refresh_steps = 60
     common.cold_steps = 120
     common.refresh_tile_z = 16
-    reps, micros = [], []
-    for r in range(2):
-        m = voronoi_polycrystal(160, 200, 300 + r)
+    m = voronoi_polycrystal(160, 200, 300)
+    reps = []
+    for r in range(4):
         rep = H.hmc_default_replica(common, 160, m.Q)
         rep.sigma_MPa[2], rep.sigma_MPa[3] = 150.0, 40.0 * (r + 1)
         reps.append(rep)
-        micros.append(m)
-    say("[streamed step] 2 x 160^3 batched against the first alone")
+    say("[streamed step] 4 x 160^3 batched against the first alone")
     b = H.Batch(common, reps)
-    for r, m in enumerate(micros):
+    for r in range(4):
         b.set_replica(r, m.euler, m.spins)
     b.stress_refresh(-1, True)
     b.stress_refresh(-1, False)
     sig_b, e_b = b.get_stress(0).cpu().numpy(), b.energy(0)
     b.close()
     p = H.hmc_params.from_buffer_copy(common)
-    rep, m = reps[0], micros[0]
+    rep = reps[0]
     p.K, p.kT, p.lambda_el, p.seed = rep.K, rep.kT, rep.lambda_el, rep.seed
     p.glob_alpha, p.glob_beta, p.glob_alphaE = rep.glob_alpha, rep.glob_beta, rep.glob_alphaE
     lat = H.Lattice(p, m.Q)
