@@ -37,10 +37,18 @@ def log(*a):
 
 
 def zone_flops_per_solve(h: int, nr: int) -> float:
-    """Algorithmic FP32 work of one zone solve: per relaxation step and voxel, the strain
-    from the 8 corners (9 gradient entries as separable sums/differences: 24 + 3 shear
-    sums), the 6x6 stress (36 FMA = 72) and the corner forces (transposed sums: 27);
-    per node the heavy-ball update (3 x 4)."""
+    """FP32 work of one zone solve as the method's per-unit figure: n_r [(2h+1)^3 200 +
+    (2h+2)^3 12] FLOP (200 per voxel and relaxation step for strain, stress and corner
+    forces, 12 per node for the heavy-ball update)."""
+    nv, nn = (2 * h + 1) ** 3, (2 * h + 2) ** 3
+    return nr * (200.0 * nv + 12.0 * nn)
+
+
+def zone_flops_minimal(h: int, nr: int) -> float:
+    """The least FP32 work of one zone solve in the separable form the kernels use: per
+    relaxation step and voxel, the strain from the 8 corners (9 gradient entries as
+    separable sums/differences: 24 + 3 shear sums), the 6x6 stress (36 FMA = 72) and the
+    corner forces (transposed sums: 27); per node the heavy-ball update (3 x 4)."""
     nv, nn = (2 * h + 1) ** 3, (2 * h + 2) ** 3
     return nr * (126.0 * nv + 12.0 * nn)
 
@@ -49,8 +57,9 @@ REFRESH_BYTES_PER_NODE_STEP = 50.0   # read u, w (24 B) + write u, w (24 B) + sp
 
 
 def measured_traffic(key_bytes, key_hash, source, summary="counters_large128.md"):
-    """HBM bytes from a committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, valid only while
-    the kernel source still has the hash it had when the counters were taken (else None)."""
+    """A figure (HBM bytes, executed operations) from a committed rocprofv3 counter summary,
+    valid only while the kernel source still has the hash it had when the counters were taken
+    (else None)."""
     import hashlib
 
     try:
@@ -888,7 +897,8 @@ def main():
     solves = st["zone_solves"]
     zt = kt["zone"]
     fps = zone_flops_per_solve(p.zone_h, p.zone_steps)
-    achieved = fps * solves / (zt["total_ms"] * 1e-3) / 1e12 if zt["total_ms"] > 0 else 0.0
+    zsec = zt["total_ms"] * 1e-3
+    achieved = fps * solves / zsec / 1e12 if zsec > 0 else 0.0
     per_solve = measured_traffic("zone_traffic_bytes_per_solve", "zone_source_sha256_16", "hmc_zone.hip")
     spl = solves / max(1, zt["launches"])
     roof = {"kernel": "zone solve", "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
@@ -897,11 +907,18 @@ def main():
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE, profiles/counters_large128.md)",
             "avg_launch_ms": round(zt["total_ms"] / max(1, zt["launches"]), 4),
             "flop_per_solve": fps, "solves_per_launch": round(solves / max(1, zt["launches"]), 1)}
-    # the same launches priced at the survey's per-voxel estimate (200 FLOP per voxel-step), and
-    # against the peak without packed FP32 (which this build does not generate)
-    sfps = p.zone_steps * (200.0 * (2 * p.zone_h + 1) ** 3 + 12.0 * (2 * p.zone_h + 2) ** 3)
-    roof["frac_at_200_flop_per_voxel_step"] = round(achieved * sfps / fps / PEAK_FP32_TFLOPS, 4) if fps else None
-    roof["frac_of_unpacked_fp32_peak"] = round(achieved / (PEAK_FP32_TFLOPS / 2), 4)
+    # the same launches priced at the least work of the kernels' separable form, at the FP32
+    # operations the kernel executes (its VALU counters, lanes without a voxel included), and
+    # against the peak without packed FP32, which this build does not generate
+    mfps = zone_flops_minimal(p.zone_h, p.zone_steps)
+    roof["flop_per_solve_minimal"] = mfps
+    roof["frac_minimal"] = round(mfps * solves / zsec / 1e12 / PEAK_FP32_TFLOPS, 4) if zsec > 0 else None
+    roof["frac_minimal_of_unpacked_fp32_peak"] = round(mfps * solves / zsec / 1e12 / (PEAK_FP32_TFLOPS / 2), 4) \
+        if zsec > 0 else None
+    xfps = measured_traffic("zone_executed_fp32_flop_per_solve", "zone_source_sha256_16", "hmc_zone.hip",
+                            "zone_instruction_mix_large128.md") if (p.zone_h, p.zone_steps) == (2, 200) else None
+    roof["flop_per_solve_executed"] = xfps
+    roof["frac_executed"] = round(xfps * solves / zsec / 1e12 / PEAK_FP32_TFLOPS, 4) if (xfps and zsec > 0) else None
     pk = kt["potts"]
     potts_roof = None
     if pk["launches"]:
@@ -1059,6 +1076,8 @@ def saturation_line(a, p, micro, lat, cfg):
             "zone_solve_fraction": st["zone_solves"] / (n * q.K ** 3), "zone_solves_per_s": st["zone_solves"] / el,
             "zone_roofline": {"achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                               "frac": round(ach / PEAK_FP32_TFLOPS, 4),
+                              "frac_minimal": round(ach * zone_flops_minimal(q.zone_h, q.zone_steps) / fps
+                                                    / PEAK_FP32_TFLOPS, 4),
                               "avg_launch_ms": round(zt["total_ms"] / max(1, zt["launches"]), 4)},
             "note": "uniform proposals (every trial a real flip, f_z = 1) from the state after the timed sweeps"}
 
