@@ -65,11 +65,11 @@ __device__ __forceinline__ void symv21_grains(const float* tab, int q, const flo
     }
 }
 
-// Voxel positions of a 32 x 8 node tile's layer (33 x 9 voxels, tile-relative; voxel (ix, iy)
-// has the tile's nodes ix, ix+1 and iy, iy+1 as corners, node 0 being the low halo) in the
-// order the 256 threads of a tiled step take them: first the 32 x 8 voxels whose high corner
-// is an own node, as four 8 x 8 patches, one per wavefront (neighbouring voxels mostly share
-// a grain), then the low halo row and column.
+// Voxel positions of a 32 x TY node tile's layer (33 x (TY + 1) voxels, tile-relative; voxel
+// (ix, iy) has the tile's nodes ix, ix+1 and iy, iy+1 as corners, node 0 being the low halo)
+// in the order the 32 TY threads of a tiled step take them: first the 32 x TY voxels whose
+// high corner is an own node, as 8 x 8 patches, one per wavefront (neighbouring voxels mostly
+// share a grain), then the low halo row and column.  kStepVox counts them for TY = 8.
 constexpr int kStepVox = (kTileX + 1) * (kTileY + 1);
 static_assert(kTileX == 32 && kTileY == 8, "voxel patches assume 32-wide tiles of 8 or 16 rows");
 // For a 32 x TY tile (TY = 8 or 16, 32 TY threads): wavefront w takes the 8 x 8 patch at x in

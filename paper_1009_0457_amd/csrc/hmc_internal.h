@@ -91,7 +91,7 @@ struct RepDev {
     int64_t grain_off;               // into Ctab / Stab (grains)
     int32_t pass_first, pass_blocks; // blocks of a colour pass (active sites / kPassSites, rounded up)
     int32_t node_first, node_blocks; // blocks of node-parallel kernels (<= kMaxChunkBlocks)
-    int32_t tile_first, tile_blocks; // blocks of the tiled explicit step (32 x 8 x tile_z nodes)
+    int32_t tile_first, tile_blocks; // blocks of the tiled explicit step (32 x tile_y x tile_z nodes)
     double J, kT, lambda;
     float glob_alpha, glob_beta;
     double glob_alphaE;
