@@ -15,6 +15,8 @@ FLAGS = [
     # packed FP32 (v_pk_*_f32) code generation stays off on this target
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+    # roctx ranges around sweeps, colour passes, refreshes and adjoint passes
+    "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib",
 ]
 
 

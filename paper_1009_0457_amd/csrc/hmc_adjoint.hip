@@ -611,6 +611,7 @@ size_t hmc_adjoint_workspace_bytes(hmc_ctx c, int32_t n_steps, int32_t ckpt_ever
 
 hmc_status hmc_elastic_forward(hmc_ctx c, int32_t n_steps, int32_t ckpt_every, void* ws, size_t bytes, double* U)
 {
+    TraceRange range("hmc adjoint forward");
     if (!c) return HMC_EINVAL;
     c->err.clear();
     AdjLayout L;
@@ -648,6 +649,7 @@ hmc_status hmc_elastic_backward(hmc_ctx c, void* ws, size_t bytes, double dU, do
                                 double grad_sigma_MPa[6])
 {
     if (!c) return HMC_EINVAL;
+    TraceRange range("hmc adjoint backward");
     c->err.clear();
     if (c->adj_steps < 1) return afail(c, HMC_ESTATE, "no forward pass recorded");
     AdjLayout L;

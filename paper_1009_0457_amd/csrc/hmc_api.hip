@@ -386,6 +386,7 @@ bool elastic_on(const hmc_ctx c) { return c->elastic_buffers && c->any_elastic()
 // ------------------------------------------------------------------------------------
 hmc_status refresh(hmc_ctx c, int n_steps, bool cold)
 {
+    TraceRange range(cold ? "hmc stress refresh (cold)" : "hmc stress refresh");
     if (c->p.material_points == 8) {
         // nodes and velocities in place in the first displacement buffer, corner forces in
         // the second
@@ -423,6 +424,10 @@ hmc_status refresh(hmc_ctx c, int n_steps, bool cold)
 
 hmc_status run_pass(hmc_ctx c, int colour, hmc_trial_record* rec)
 {
+    static const char* const kPassName[8] = {"hmc colour pass 0", "hmc colour pass 1", "hmc colour pass 2",
+                                             "hmc colour pass 3", "hmc colour pass 4", "hmc colour pass 5",
+                                             "hmc colour pass 6", "hmc colour pass 7"};
+    TraceRange range(kPassName[colour & 7]);
     // Only trials that need a zone solve enter the colour's trial list; with the elastic term
     // off for every replica the list stays empty and its count is neither read nor written.
     const bool el = elastic_on(c);
@@ -439,6 +444,7 @@ hmc_status run_pass(hmc_ctx c, int colour, hmc_trial_record* rec)
 // one sweep without host synchronisation: [refresh], colour passes, sweep index + 1
 hmc_status enqueue_sweep(hmc_ctx c, bool with_refresh)
 {
+    TraceRange range("hmc sweep");
     if (with_refresh) {
         hmc_status st = refresh(c, c->p.refresh_steps, false);
         if (st != HMC_OK) return st;
@@ -478,7 +484,10 @@ hmc_status graph_sweep(hmc_ctx c, bool with_refresh)
         if (e != hipSuccess) return device_fail(c, e, "graph: instantiate");
         c->graph_u[k] = u0;
     }
-    HMC_TRY(c, hipGraphLaunch(c->graph[k], c->stream), "graph: launch");
+    {
+        TraceRange range("hmc sweep (graph replay)");
+        HMC_TRY(c, hipGraphLaunch(c->graph[k], c->stream), "graph: launch");
+    }
     // mirror what the replayed sweep did
     if (with_refresh) {
         // what refresh() leaves: the 8-point solve always ends in buffer 0, the one-point

@@ -6,6 +6,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cstdint>
 #include <string>
@@ -74,6 +75,16 @@ __device__ __forceinline__ int stride_block(int b, int G, int order)
 {
     return reorder_block(b, G, order);
 }
+
+// A named roctx range on the host thread for the scope's lifetime (sweeps, colour passes,
+// refreshes, adjoint passes), so that a marker trace (rocprofv3 --marker-trace) shows the
+// library's phases around its kernels.  Costs a call each way when no tool is attached.
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 __host__ __device__ constexpr int tile_blocks_of(int K, int tz, int ty = kTileY)
 {
