@@ -18,7 +18,9 @@ Spins are 0-based grain indices, flat index ``x + K*(y + K*z)``.
 """
 from __future__ import annotations
 
+import json
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -168,51 +170,71 @@ class RunConfig:
         return c
 
 
+# The workloads are described by the JSON files under configs/ at the repository root (one per
+# workload; a zero-load twin is the same with the load set to zero, RunConfig.zero_load).
+CONFIG_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "configs")
+_RUN_KEYS = ("K", "neighbors", "n_grains", "kT", "zone_h", "zone_steps", "sweeps", "refresh_every", "seed",
+             "philox_seed", "J", "C11", "C12", "C44", "proposal", "refresh_steps", "cold_steps", "histogram_every")
+
+
+def load_config(name: str) -> dict:
+    """The JSON description of workload `name` (configs/<name>.json)."""
+    with open(os.path.join(CONFIG_DIR, name + ".json")) as f:
+        return json.load(f)
+
+
+def run_config(name: str) -> RunConfig:
+    """A single-lattice workload from its JSON description."""
+    d = load_config(name)
+    kw = {k: d[k] for k in _RUN_KEYS if k in d}
+    return RunConfig(name=d["name"], sigma_MPa=np.array(d["sigma_MPa"], float),
+                     histogram_axes=tuple(tuple(float(v) for v in ax) for ax in d.get("histogram_axes", ())), **kw)
+
+
 def tiny_config() -> RunConfig:
     """16^3, 6 neighbours (red/black), 8 grains, 100 MPa along z, 3^3 zone x 50 steps."""
-    return RunConfig(name="tiny-16", K=16, neighbors=6, n_grains=8,
-                     sigma_MPa=np.array([0, 0, 100.0, 0, 0, 0]), kT=0.5,
-                     zone_h=1, zone_steps=50, sweeps=10, refresh_every=1)
+    return run_config("tiny-16")
 
 
 def full_config() -> RunConfig:
     """64^3, 26 neighbours (8 colours), 500 grains, 200 MPa along z, 5^3 zone x 200 steps."""
-    return RunConfig(name="full-64", K=64, neighbors=26, n_grains=500,
-                     sigma_MPa=np.array([0, 0, 200.0, 0, 0, 0]), kT=0.5,
-                     zone_h=2, zone_steps=200, sweeps=100, refresh_every=10)
+    return run_config("full-64")
 
 
 def large_config() -> RunConfig:
     """128^3, 26 neighbours, 4000 grains, biaxial 150/150 MPa, 5^3 zone x 200 steps."""
-    return RunConfig(name="large-128", K=128, neighbors=26, n_grains=4000,
-                     sigma_MPa=np.array([150.0, 150.0, 0, 0, 0, 0]), kT=0.7,
-                     zone_h=2, zone_steps=200, sweeps=200, refresh_every=10,
-                     histogram_every=10, histogram_axes=((1.0, 0, 0), (0, 1.0, 0)))
+    return run_config("large-128")
 
 
-def batched_configs(n_replicas: int = 64) -> list[RunConfig]:
+def batched_configs(n_replicas: int | None = None) -> list[RunConfig]:
     """Replica ensemble: K in {32,48,64,96}, 8 grains per 16^3, random uniaxial load."""
-    rng = np.random.default_rng(0)
+    d = load_config("batched-64")
+    n_replicas = d["replicas"] if n_replicas is None else n_replicas
+    rng = np.random.default_rng(d["rng_seed"])
+    choices = tuple(int(k) for k in d["K_choices"])
+    lo, hi = d["kT_range"]
     out = []
     for r in range(n_replicas):
-        K = int((32, 48, 64, 96)[rng.integers(0, 4)])
-        s = float(rng.uniform(0.0, 300.0))
+        K = int(choices[rng.integers(0, len(choices))])
+        s = float(rng.uniform(0.0, d["load_MPa_max"]))
         n = rng.normal(size=3)
         n /= np.linalg.norm(n)
-        kT = float(rng.uniform(0.3, 1.0))
+        kT = float(rng.uniform(lo, hi))
         sig = s * np.outer(n, n)
         voigt = np.array([sig[0, 0], sig[1, 1], sig[2, 2], sig[1, 2], sig[0, 2], sig[0, 1]])
-        out.append(RunConfig(name=f"replica-{r}", K=K, neighbors=26,
-                             n_grains=8 * (K // 16) ** 3, sigma_MPa=voigt, kT=kT,
-                             zone_h=2, zone_steps=200, sweeps=50, refresh_every=10,
-                             seed=r + 1, philox_seed=r + 1, extra={"axis": n, "load_MPa": s}))
+        out.append(RunConfig(name=f"replica-{r}", K=K, neighbors=d["neighbors"],
+                             n_grains=d["grains_per_16_cube"] * (K // 16) ** 3, sigma_MPa=voigt, kT=kT,
+                             zone_h=d["zone_h"], zone_steps=d["zone_steps"], sweeps=d["sweeps"],
+                             refresh_every=d["refresh_every"], seed=r + 1, philox_seed=r + 1,
+                             extra={"axis": n, "load_MPa": s}))
     return out
 
 
 def adjoint_config():
     """64^3, 500 grains; six stress components U(-200, 200) MPa; 10 probe grains."""
-    rng = np.random.default_rng(1)
-    micro = voronoi_polycrystal(64, 500, 1, rng=rng)
-    sigma = rng.uniform(-200.0, 200.0, size=6)
-    probe = rng.choice(500, size=10, replace=False)
+    d = load_config("adjoint-64")
+    rng = np.random.default_rng(d["rng_seed"])
+    micro = voronoi_polycrystal(d["K"], d["n_grains"], d["rng_seed"], rng=rng)
+    sigma = rng.uniform(-d["sigma_MPa_max"], d["sigma_MPa_max"], size=6)
+    probe = rng.choice(d["n_grains"], size=d["probe_grains"], replace=False)
     return micro, sigma, probe

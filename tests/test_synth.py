@@ -44,6 +44,40 @@ def test_batched_configs_follow_the_ensemble_recipe():
     assert [c.philox_seed for c in cfgs] == list(range(1, 65))
 
 
+@pytest.mark.parametrize("name,K,M,grains,sigma,kT,h,nr,sweeps,R", [
+    ("tiny-16", 16, 6, 8, [0, 0, 100, 0, 0, 0], 0.5, 1, 50, 10, 1),
+    ("full-64", 64, 26, 500, [0, 0, 200, 0, 0, 0], 0.5, 2, 200, 100, 10),
+    ("large-128", 128, 26, 4000, [150, 150, 0, 0, 0, 0], 0.7, 2, 200, 200, 10),
+])
+def test_workload_files_hold_the_stated_workloads(name, K, M, grains, sigma, kT, h, nr, sweeps, R):
+    """configs/<name>.json against the workload statements (lattice, neighbours, grains, load,
+    temperature, zone size and steps, sweeps, refresh interval), and its zero-load twin."""
+    from paper_1009_0457_amd.synth import run_config
+    c = run_config(name)
+    assert (c.name, c.K, c.neighbors, c.n_grains) == (name, K, M, grains)
+    assert np.array_equal(c.sigma_MPa, np.array(sigma, float))
+    assert (c.kT, c.zone_h, c.zone_steps, c.sweeps, c.refresh_every) == (kT, h, nr, sweeps, R)
+    assert (c.seed, c.philox_seed, c.refresh_steps, c.cold_steps) == (1, 1, 200, 2000)
+    assert (c.C11, c.C12, c.C44) == (246.5, 147.3, 124.7)
+    z = c.zero_load()
+    assert not z.sigma_MPa.any() and z.K == K and z.name == name + "-zero-load"
+
+
+def test_ensemble_and_adjoint_files():
+    from paper_1009_0457_amd.synth import adjoint_config, load_config
+    cfgs = batched_configs()
+    assert len(cfgs) == 64
+    sites = sum(c.K ** 3 for c in cfgs)
+    assert 15e6 < sites < 26e6                     # about 20.6 M expected for the draw
+    assert all((c.zone_h, c.zone_steps, c.sweeps, c.refresh_every) == (2, 200, 50, 10) for c in cfgs)
+    d = load_config("adjoint-64")
+    assert (d["K"], d["n_grains"], d["steps"], d["checkpoint_every"], d["probe_grains"]) == (64, 500, 2000, 50, 10)
+    micro, sigma, probe = adjoint_config()
+    assert micro.K == 64 and micro.Q == 500
+    assert sigma.shape == (6,) and np.abs(sigma).max() <= 200.0
+    assert len(set(probe.tolist())) == 10 and probe.max() < 500
+
+
 def test_texture_run_inputs():
     from paper_1009_0457_amd.synth import texture_run_inputs, z_rotation_euler
     runs = texture_run_inputs(6, 3, 91, 5)
