@@ -909,7 +909,7 @@ def main():
             "flop_per_solve": fps, "solves_per_launch": round(solves / max(1, zt["launches"]), 1)}
     # the same launches priced at the least work of the kernels' separable form, at the FP32
     # operations the kernel executes (its VALU counters, lanes without a voxel included), and
-    # against the peak without packed FP32, which this build does not generate
+    # against the peak without packed FP32, which the library is compiled without
     mfps = zone_flops_minimal(p.zone_h, p.zone_steps)
     roof["flop_per_solve_minimal"] = mfps
     roof["frac_minimal"] = round(mfps * solves / zsec / 1e12 / PEAK_FP32_TFLOPS, 4) if zsec > 0 else None
