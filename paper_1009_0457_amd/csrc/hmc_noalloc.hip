@@ -12,7 +12,6 @@
 #include <cmath>
 #include <mutex>
 #include <string>
-#include <vector>
 
 #include "hmc_internal.h"
 
@@ -28,8 +27,15 @@ constexpr size_t kNaBytes = (kNaBins + sizeof(int32_t) * kNaMaxQ + 255) / 256 * 
 
 static __device__ __align__(256) unsigned char scratch[kNaBytes];
 
+constexpr int kNaMaxDevices = 64;
 std::mutex g_addr_mu;
-std::vector<unsigned char*> g_addr;            // per device: scratch's address there
+unsigned char* g_addr[kNaMaxDevices] = {};     // per device: scratch's address there
+
+// Host bin table of the call in progress: a fixed array, so that a call allocates nothing on
+// the host either; the lock is held until the call's stream is synchronised, which is after
+// the copy that reads it.
+std::mutex g_bins_mu;
+int32_t g_bins[kNaMaxQ];
 
 // The scratch array's device address on the current device (taken once per device).
 hipError_t scratch_address(unsigned char** out)
@@ -37,8 +43,8 @@ hipError_t scratch_address(unsigned char** out)
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kNaMaxDevices) return hipErrorInvalidDevice;
     std::lock_guard<std::mutex> lock(g_addr_mu);
-    if ((int)g_addr.size() <= dev) g_addr.resize((size_t)dev + 1, nullptr);
     if (!g_addr[(size_t)dev]) {
         void* p = nullptr;
         e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
@@ -111,8 +117,8 @@ extern "C" hmc_status hmc_texture_histogram_noalloc(const int32_t* spins_dev, in
     if (!(nrm > 0) || !std::isfinite(nrm)) return na_fail(HMC_EINVAL, "axis must be finite and non-zero");
     for (int64_t i = 0; i < 3 * (int64_t)Q; ++i)
         if (!std::isfinite(euler_host[i])) return na_fail(HMC_ENUMERIC, "non-finite Euler angle");
-    std::vector<int32_t> bins((size_t)Q);
-    texture_bins(euler_host, Q, axis, bin_deg, nbins, bins.data());
+    std::lock_guard<std::mutex> bins_lock(g_bins_mu);
+    texture_bins(euler_host, Q, axis, bin_deg, nbins, g_bins);
 
     unsigned char* s = nullptr;
     hipError_t e = scratch_address(&s);
@@ -122,7 +128,7 @@ extern "C" hmc_status hmc_texture_histogram_noalloc(const int32_t* spins_dev, in
     if (g > 2048) g = 2048;
     unsigned long long h[64];
     uint32_t flag = 0;
-    e = hipMemcpyAsync(s + kNaBins, bins.data(), bins.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream);
+    e = hipMemcpyAsync(s + kNaBins, g_bins, (size_t)Q * sizeof(int32_t), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_na_clear, dim3(1), dim3(64), 0, stream, s);
         hipLaunchKernelGGL(k_na_hist, dim3((unsigned)g), dim3(256), 0, stream, spins_dev, n3, Q, (int)nbins, s);
