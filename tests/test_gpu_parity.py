@@ -385,6 +385,45 @@ def lockstep_schedule(c, compare, variant=0, seed=11):
     return errs
 
 
+@pytest.mark.parametrize("prop", [0, 1])
+def test_elastic_pass_with_the_largest_grain_count(prop):
+    """Q = 32767, the most grains the 16-bit spins hold: a 24^3 lattice of random spins (nearly
+    every site its own grain, so nearly every trial a real flip and a zone solve), 26
+    neighbours, 3^3 zones under load.  Every trial of colour 0 against the oracle: draws,
+    proposals (both kinds; the uniform proposal spans all 32766 other grains), bond counts
+    exactly, zone energies within tolerance, decisions outside the band, and the pass's spins."""
+    from paper_1009_0457_amd.synth import Microstructure, haar_euler
+    K, Q = 24, 32767
+    rng = np.random.default_rng(41)
+    micro = Microstructure(K=K, spins=rng.integers(0, Q, size=K ** 3).astype(np.int32),
+                           euler=haar_euler(np.random.default_rng(42), Q))
+    say(f"[largest Q] K={K} Q={Q} proposal={prop}")
+    p, lat = make_lattice(K, 26, 1, micro, kT=0.8, proposal=prop, zone_steps=50)
+    lat.set_load([80.0, 0, -40.0, 0, 25.0, 0])
+    lat.stress_refresh(-1, True)
+    lat.set_sweep_index(3)
+    Ct, St, _ = O.tables(micro.euler, p.C11, p.C12, p.C44)
+    prm = oracle_params(p, Q, True)
+    sig = lat.get_stress().cpu().numpy().astype(np.float64)
+    snap = lat.get_spins().cpu().numpy()
+    rec = lat.colour_pass(0, records=True)
+    sites = np.nonzero(O.colour_of(K, 26) == 0)[0]
+    ref = oracle_trials_pooled(prm, snap, Ct, St, sig, 3, sites)
+    errs = ZoneErrors()
+    tol = errs.add(rec, ref, sites, sig, St, snap)
+    n, k, w = compare_pass(rec, ref, sites, p, tol, f"Q={Q} proposal {prop}")
+    errs.flagged += k
+    assert n > 0.9 * sites.size
+    if prop == 1:
+        assert np.unique(ref["q_new"]).size > 0.9 * sites.size      # spread over the grains
+    want = snap.copy()
+    acc = (ref["flags"] & 2) != 0
+    want[sites[acc]] = ref["q_new"][acc]
+    assert np.count_nonzero(lat.get_spins().cpu().numpy() != want) <= k
+    errs.report(f"Q={Q} proposal {prop}")
+    lat.close()
+
+
 @pytest.mark.parametrize("variant", [1, 2, 3])
 @pytest.mark.parametrize("cfg", ["tiny", "tiny-uniform"])
 def test_elastic_lockstep_tiny_workload(cfg, variant):
