@@ -530,6 +530,33 @@ def test_elastic_lockstep_zone_sizes(h, variant):
     lat.close()
 
 
+@pytest.mark.parametrize("h,K", [(1, 4), (2, 6), (3, 8)])
+def test_elastic_pass_on_the_smallest_lattice_a_zone_fits(h, K):
+    """K = 2h + 2, the smallest edge the library accepts with the elastic term on: a zone's
+    (2h+2)^3 nodes then cover every node of the periodic lattice exactly once.  Every trial of
+    every colour of one sweep against the oracle, uniform proposals."""
+    micro = voronoi_polycrystal(K, 5, 60 + h)
+    p, lat = make_lattice(K, 26, h, micro, kT=0.9, proposal=1, zone_steps=(50, 200, 120)[h - 1])
+    lat.set_load([90.0, 0.0, -60.0, 0.0, 30.0, 0.0])
+    lat.stress_refresh(400, True)
+    Ct, St, _ = O.tables(micro.euler, p.C11, p.C12, p.C44)
+    prm = oracle_params(p, micro.Q, True)
+    cols = O.colour_of(K, 26)
+    solves = 0
+    for col in range(8):
+        sig = lat.get_stress().cpu().numpy().astype(np.float64)
+        snap = lat.get_spins().cpu().numpy()
+        rec = lat.colour_pass(col, records=True)
+        ref = O.colour_pass(prm, snap.copy(), Ct, St, sig, 0, col, want_records=True)
+        sites = np.nonzero(cols == col)[0]
+        tol, _ = zone_tol(sig[:, sites], St, snap[sites], ref["dPi"][sites])
+        n, k, w = compare_pass(rec, ref[sites], sites, p, tol, f"K={K} h={h} colour {col}")
+        solves += n
+    say(f"[smallest lattice] K={K} h={h}: {solves} zone solves compared")
+    assert solves > 0
+    lat.close()
+
+
 @pytest.mark.parametrize("which", ["full", "large"])
 def test_zone_screen_preserves_every_decision(which):
     """The lower-bound screen skips solves but not decisions: the same colour passes with and
