@@ -21,6 +21,15 @@ struct Philox4 {
     uint32_t v[4];
 };
 
+// a ^ b ^ k in one instruction (gfx950's three-input bitwise op with truth table 0x96; the
+// compiler emits two XORs for it); k is the round key, uniform across the wavefront.
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k)
+{
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
 __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                  uint32_t k0, uint32_t k1)
 {
@@ -31,8 +40,8 @@ __device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
         const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
         const uint32_t a = (uint32_t)pa, ah = (uint32_t)(pa >> 32);
         const uint32_t b = (uint32_t)pb, bh = (uint32_t)(pb >> 32);
-        const uint32_t n0 = bh ^ c1 ^ k0;
-        const uint32_t n2 = ah ^ c3 ^ k1;
+        const uint32_t n0 = xor3_key(bh, c1, k0);
+        const uint32_t n2 = xor3_key(ah, c3, k1);
         c0 = n0;
         c1 = b;
         c2 = n2;
