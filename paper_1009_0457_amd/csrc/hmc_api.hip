@@ -100,13 +100,27 @@ struct Layout {
 
 int64_t n3_of(int K) { return (int64_t)K * K * K; }
 
-// Node rows per block of the forward explicit step: 16 (512-thread blocks) when every
-// replica's edge is a multiple of 16, else 8 (a 16-row tile would pad more rows than it saves).
-int tile_rows_of(int n, const hmc_replica* r)
+// Node layers per block of one replica's explicit step: as many z-tiles as depth t gives, made
+// equal (a 100-layer lattice at t = 32 takes four tiles of 25 layers instead of 32, 32, 32 and
+// 4), so that no block marches further than it has to.
+int balanced_depth(int t, int K)
 {
-    for (int i = 0; i < n; ++i)
+    const int n = (K + t - 1) / t;
+    return (K + n - 1) / n;
+}
+
+// Node rows per block of the forward explicit step at depth tz: 16 (512-thread blocks) when
+// every replica's edge is a multiple of 16 and the launch still gives two blocks per compute
+// unit, else 8 (a 16-row tile would pad rows, or leave compute units half empty: 64^3 at depth
+// 2 takes 15.1 us per step on 256 blocks of 16 rows against 14.6 us on 512 of 8).
+int tile_rows_of(int n, const hmc_replica* r, int tz)
+{
+    int64_t blocks = 0;
+    for (int i = 0; i < n; ++i) {
         if (r[i].K % 16 != 0) return 8;
-    return 16;
+        blocks += tile_blocks_of(r[i].K, balanced_depth(tz, r[i].K), 16);
+    }
+    return blocks >= 512 ? 16 : 8;
 }
 
 // Whether the explicit step streams its own nodes' u and w past the caches: when the arrays a
@@ -118,29 +132,19 @@ int tile_rows_of(int n, const hmc_replica* r)
 // 1.73 against 1.66 ms.
 bool step_streams_of(int64_t sites) { return sites * 38 > (int64_t)512 << 20; }
 
-// Node layers per block of one replica's explicit step: as many z-tiles as depth t gives, made
-// equal (a 100-layer lattice at t = 32 takes four tiles of 25 layers instead of 32, 32, 32 and
-// 4), so that no block marches further than it has to.
-int balanced_depth(int t, int K)
-{
-    const int n = (K + t - 1) / t;
-    return (K + n - 1) / n;
-}
-
 // Node layers per block of the tiled explicit step: the caller's choice, else the deepest
-// tile that still launches at least 256K threads over all replicas (1024 blocks of 256 or 512
-// of 512, 4 or 2 per compute unit), but 2 rather than 1 (a block's first layer is redone by
+// tile that still launches at least 1024 blocks of 32 x 8 nodes over all replicas (4 per
+// compute unit), but 2 rather than 1 (a block's first layer is redone by
 // its neighbour, which one-layer tiles pay on every layer), and 1 when no depth reaches it.
 // Measured with 32 x 8 tiles: 32 at 256^3 and 512^3 (64 is within 1 %), 8 at 128^3, 2 at 64^3
 // are the fastest depths there.
 int tile_depth_of(const hmc_params* p, int n, const hmc_replica* r)
 {
     if (p->refresh_tile_z > 0) return p->refresh_tile_z;
-    const int ty = tile_rows_of(n, r);
     for (int tz = kTileZMax; tz >= 1; tz /= 2) {
         int64_t blocks = 0;
-        for (int i = 0; i < n; ++i) blocks += tile_blocks_of(r[i].K, tz, ty);
-        if (blocks * ty >= 1024 * 8) return tz > 1 ? tz : 2;
+        for (int i = 0; i < n; ++i) blocks += tile_blocks_of(r[i].K, tz, 8);
+        if (blocks >= 1024) return tz > 1 ? tz : 2;
     }
     return 1;
 }
@@ -150,7 +154,7 @@ Layout layout_of(const hmc_params* p, int n, const hmc_replica* r)
     Layout L{};
     const int C = colours_of(p->neighbors);
     L.tile_z = tile_depth_of(p, n, r);
-    L.tile_y = tile_rows_of(n, r);
+    L.tile_y = tile_rows_of(n, r, L.tile_z);
     for (int i = 0; i < n; ++i) {
         const int64_t n3 = n3_of(r[i].K);
         L.sites += n3;

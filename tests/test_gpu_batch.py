@@ -102,18 +102,18 @@ def test_batch_equals_replicas_run_alone(graphs):
 
 
 def test_explicit_step_tile_heights_agree():
-    """A 48^3 replica alone runs the forward explicit step on 32 x 16 node tiles (every edge a
-    multiple of 16); batched with a 40^3 replica it runs on 32 x 8 tiles.  The 16-row tile
-    totals its two 8-row halves on their own, so the stress fields and stored energies agree
-    bit for bit, and so do the spins and stresses of the sweeps that follow."""
-    common = H.hmc_default_params(48, 26, 2)
+    """A 112^3 replica alone runs the forward explicit step on 32 x 16 node tiles (every edge a
+    multiple of 16, 784 blocks at depth 4); batched with a 40^3 replica it runs on 32 x 8 tiles.
+    The 16-row tile totals its two 8-row halves on their own, so the stress fields and stored
+    energies agree bit for bit, and so do the spins and stresses of the sweeps that follow."""
+    common = H.hmc_default_params(112, 26, 2)
     common.refresh_every = 2
     common.refresh_steps = 90
     common.cold_steps = 200
     common.zone_steps = 60
     common.refresh_tile_z = 4      # the same tile depth alone and in the batch
     reps, micros = [], []
-    for r, (K, G) in enumerate(((48, 40), (40, 30))):
+    for r, (K, G) in enumerate(((112, 120), (40, 30))):
         m = voronoi_polycrystal(K, G, 200 + r)
         rep = H.hmc_default_replica(common, K, m.Q)
         rep.kT, rep.seed = 0.7, 11 + r
