@@ -109,18 +109,24 @@ int balanced_depth(int t, int K)
     return (K + n - 1) / n;
 }
 
-// Node rows per block of the forward explicit step at depth tz: 16 (512-thread blocks) when
-// every replica's edge is a multiple of 16 and the launch still gives two blocks per compute
-// unit, else 8 (a 16-row tile would pad rows, or leave compute units half empty: 64^3 at depth
-// 2 takes 15.1 us per step on 256 blocks of 16 rows against 14.6 us on 512 of 8).
+// Node rows per block of the forward explicit step at depth tz: the tallest of 32 (1024-thread
+// blocks, one per compute unit), 16 (512 threads, two) and 8 (256 threads, four) that divides
+// every replica's edge and still launches at least 512 blocks; taller tiles re-read fewer halo
+// rows per owned node (512^3: 1.77, 1.73 and 1.62 ms per step on 8, 16 and 32 rows; 256^3:
+// 262, 250 and 231 us), but a launch short of blocks leaves compute units idle (64^3 at depth
+// 2: 15.1 us per step on 256 blocks of 16 rows against 14.6 us on 512 of 8).
 int tile_rows_of(int n, const hmc_replica* r, int tz)
 {
-    int64_t blocks = 0;
-    for (int i = 0; i < n; ++i) {
-        if (r[i].K % 16 != 0) return 8;
-        blocks += tile_blocks_of(r[i].K, balanced_depth(tz, r[i].K), 16);
+    for (int ty = 32; ty >= 16; ty /= 2) {
+        int64_t blocks = 0;
+        bool fits = true;
+        for (int i = 0; i < n && fits; ++i) {
+            fits = r[i].K % ty == 0;
+            blocks += tile_blocks_of(r[i].K, balanced_depth(tz, r[i].K), ty);
+        }
+        if (fits && blocks >= 512) return ty;
     }
-    return blocks >= 512 ? 16 : 8;
+    return 8;
 }
 
 // Whether the explicit step streams its own nodes' u and w past the caches: when the arrays a

@@ -71,13 +71,13 @@ __device__ __forceinline__ void symv21_grains(const float* tab, int q, const flo
 // high corner is an own node, as 8 x 8 patches, one per wavefront (neighbouring voxels mostly
 // share a grain), then the low halo row and column.  kStepVox counts them for TY = 8.
 constexpr int kStepVox = (kTileX + 1) * (kTileY + 1);
-static_assert(kTileX == 32 && kTileY == 8, "voxel patches assume 32-wide tiles of 8 or 16 rows");
-// For a 32 x TY tile (TY = 8 or 16, 32 TY threads): wavefront w takes the 8 x 8 patch at x in
+static_assert(kTileX == 32 && kTileY == 8, "voxel patches assume 32-wide tiles of 8, 16 or 32 rows");
+// For a 32 x TY tile (TY = 8, 16 or 32; 32 TY threads): wavefront w takes the 8 x 8 patch at x in
 // [8 (w % 4) + 1, 8 (w % 4) + 8], y in [8 (w / 4) + 1, 8 (w / 4) + 8].
 template <int TY = kTileY>
 __device__ __forceinline__ void step_voxel_pos(int i, int& ix, int& iy)
 {
-    static_assert(TY == 8 || TY == 16, "tile rows");
+    static_assert(TY == 8 || TY == 16 || TY == 32, "tile rows");
     constexpr int NI = kTileX * TY;
     if (i < NI) {                          // interior patches
         const int w = i >> 6;

@@ -74,16 +74,16 @@ __device__ __forceinline__ void advance_E(const RepDev* reps, int r, const doubl
 // are formed in 8 x 8 patches, one per wavefront, so that a wavefront's voxels mostly share
 // one grain and its stiffness comes through the scalar cache.
 // (At most 128 VGPRs, so that four blocks share a CU: the LDS would allow five.)
-// TY = 8 (256 threads, four blocks per CU) or 16 (512 threads, two blocks per CU: fewer halo
-// nodes and voxels per owned node, half the y-halo rows re-read by neighbouring tiles).  Both
-// give bit-identical results: a 16-row tile's wavefronts 0-3 hold the voxels and sums of the
-// 8-row tile at its top, wavefronts 4-7 those of the one below, and each half's stress sums
-// are totalled and rounded to fixed point on their own, as two 8-row blocks would.  The own
-// nodes' u and w are read and written once per step; with NT (lattices too large for the
-// Infinity Cache) non-temporal accesses keep them from displacing the halo rows that
-// neighbouring tiles read from L2 (512^3: 1.73 -> 1.66 ms).
+// TY = 8 (256 threads, four blocks per CU), 16 (512 threads, two) or 32 (1024 threads, one):
+// taller tiles load fewer halo nodes and voxels per owned node and re-read fewer y-halo rows
+// of neighbouring tiles.  All give bit-identical results: wavefronts 4g .. 4g+3 of a tall tile
+// hold exactly the voxels and sums of the g-th 8-row tile inside it, and each 8-row group's
+// stress sums are totalled and rounded to fixed point on their own, as an 8-row block would.
+// The own nodes' u and w are read and written once per step; with NT (lattices too large for
+// the Infinity Cache) non-temporal accesses keep them from displacing the halo rows that
+// neighbouring tiles read from L2 (512^3 on 16-row tiles: 1.73 -> 1.66 ms).
 template <int TY, bool NT>
-__global__ __launch_bounds__(32 * TY, TY == 8 ? 4 : 2) void k_global_step_tiled(GlobArgs a)
+__global__ __launch_bounds__(32 * TY, TY == 8 ? 4 : TY == 16 ? 2 : 1) void k_global_step_tiled(GlobArgs a)
 {
     constexpr int THREADS = kTileX * TY;
     constexpr int NX = kTileX + 2, NY = TY + 2, VX = kTileX + 1, VY = TY + 1;
@@ -501,7 +501,12 @@ hipError_t seq_step(hmc_ctx_s* c, hipStream_t s, int i, const float* uin, float*
     a.plane = c->total_sites;
     const int tok = s == c->stream ? prof_begin(c, kProfRefreshStep) : -1;
     const dim3 g(c->tile_blocks);
-    if (c->reps[0].tile_y == 16) {
+    if (c->reps[0].tile_y == 32) {
+        if (c->step_streams)
+            hipLaunchKernelGGL((k_global_step_tiled<32, true>), g, dim3(kTileX * 32), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_global_step_tiled<32, false>), g, dim3(kTileX * 32), 0, s, a);
+    } else if (c->reps[0].tile_y == 16) {
         if (c->step_streams)
             hipLaunchKernelGGL((k_global_step_tiled<16, true>), g, dim3(kTileX * 16), 0, s, a);
         else

@@ -101,21 +101,23 @@ def test_batch_equals_replicas_run_alone(graphs):
     b.close()
 
 
-def test_explicit_step_tile_heights_agree():
+@pytest.mark.parametrize("K", [112, 128])
+def test_explicit_step_tile_heights_agree(K):
     """A 112^3 replica alone runs the forward explicit step on 32 x 16 node tiles (every edge a
-    multiple of 16, 784 blocks at depth 4); batched with a 40^3 replica it runs on 32 x 8 tiles.
-    The 16-row tile totals its two 8-row halves on their own, so the stress fields and stored
-    energies agree bit for bit, and so do the spins and stresses of the sweeps that follow."""
-    common = H.hmc_default_params(112, 26, 2)
+    multiple of 16, 784 blocks at depth 4), a 128^3 one on 32 x 32 tiles (512 blocks); batched
+    with a 40^3 replica either runs on 32 x 8 tiles.  A tall tile totals each of its 8-row
+    groups on its own, so the stress fields and stored energies agree bit for bit, and so do
+    the spins and stresses of the sweeps that follow."""
+    common = H.hmc_default_params(K, 26, 2)
     common.refresh_every = 2
     common.refresh_steps = 90
     common.cold_steps = 200
     common.zone_steps = 60
     common.refresh_tile_z = 4      # the same tile depth alone and in the batch
     reps, micros = [], []
-    for r, (K, G) in enumerate(((112, 120), (40, 30))):
-        m = voronoi_polycrystal(K, G, 200 + r)
-        rep = H.hmc_default_replica(common, K, m.Q)
+    for r, (Kr, G) in enumerate(((K, 120), (40, 30))):
+        m = voronoi_polycrystal(Kr, G, 200 + r)
+        rep = H.hmc_default_replica(common, Kr, m.Q)
         rep.kT, rep.seed = 0.7, 11 + r
         rep.sigma_MPa[0], rep.sigma_MPa[5] = 180.0, -60.0 * (r + 1)
         reps.append(rep)
