@@ -235,7 +235,9 @@ static_assert(kPassSites == 4 * 256, "a chunk is four sites per thread of a 256-
 // SCREEN: the lower-bound screen's FP64 path is compiled in only where it is used, since it
 // more than doubles the kernel's registers (126 against 48 VGPRs: 4 against 8 wavefronts per
 // SIMD, which hide the chain of dependent reads of every site).
-template <int M, bool SCREEN, int SPT>
+// NP2: every replica proposes a neighbour's spin and has a power-of-two edge, known at compile
+// time (the common case), so the proposal and the wrap need no uniform branches.
+template <int M, bool SCREEN, int SPT, bool NP2>
 __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
 {
     static_assert(SPT == 1 || SPT == 4, "one or four sites per thread");
@@ -251,7 +253,8 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
     const bool elastic = R.elastic != 0;
     int16_t* spins = a.spins + R.site_off;
     const int K = R.K, KK = K * K, Km = K - 1;
-    const bool pow2 = (K & Km) == 0;
+    const bool pow2 = NP2 || (K & Km) == 0;
+    const bool nbr_prop = NP2 || R.proposal == 0;
     const uint32_t sweep = (uint32_t)(*a.sweep);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const unsigned long long below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
@@ -278,7 +281,7 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
         r0[it] = rn.v[0];
         r1[it] = rn.v[1];
         nbr[it] = site[it];
-        if (R.proposal == 0) {
+        if (nbr_prop) {
             const int k = (int)__umulhi(rn.v[0], (uint32_t)M);
             int dx, dy, dz;
             slot_offset<M>(k, dx, dy, dz);
@@ -305,7 +308,7 @@ __global__ __launch_bounds__(256) void k_potts_pass(PassArgs a)
         uint32_t qq = 0;
         if (ok[it]) {
             int q_new = q_nb[it];
-            if (R.proposal != 0) {
+            if (!nbr_prop) {
                 const uint32_t step = __umulhi(r0[it], (uint32_t)(R.Q - 1));
                 q_new = (int)(((uint32_t)q_old[it] + 1u + step) % (uint32_t)R.Q);
             }
@@ -574,24 +577,32 @@ hipError_t launch_potts_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
     // the same-address list appends (measured at 128^3 under load: 16.2 against 9.6 us)
     const bool one = c->pass_blocks < kPassSplitBelow && !(c->elastic_buffers && c->any_elastic());
     const dim3 grid((unsigned)(one ? 4 * c->pass_blocks : c->pass_blocks)), block(256);
+    bool np2 = true;
+    for (const RepDev& R : c->reps) np2 = np2 && R.proposal == 0 && (R.K & (R.K - 1)) == 0;
     const int tok = prof_begin(c, kProfPotts);
+#define HMC_PASS(MM, SC, SPT)                                                                      \
+    do {                                                                                           \
+        if (np2) hipLaunchKernelGGL((k_potts_pass<MM, SC, SPT, true>), grid, block, 0, c->stream, a);  \
+        else hipLaunchKernelGGL((k_potts_pass<MM, SC, SPT, false>), grid, block, 0, c->stream, a);     \
+    } while (0)
     if (c->p.neighbors == 26) {
         if (one) {
-            if (a.screen) hipLaunchKernelGGL((k_potts_pass<26, true, 1>), grid, block, 0, c->stream, a);
-            else hipLaunchKernelGGL((k_potts_pass<26, false, 1>), grid, block, 0, c->stream, a);
+            if (a.screen) HMC_PASS(26, true, 1);
+            else HMC_PASS(26, false, 1);
         } else {
-            if (a.screen) hipLaunchKernelGGL((k_potts_pass<26, true, 4>), grid, block, 0, c->stream, a);
-            else hipLaunchKernelGGL((k_potts_pass<26, false, 4>), grid, block, 0, c->stream, a);
+            if (a.screen) HMC_PASS(26, true, 4);
+            else HMC_PASS(26, false, 4);
         }
     } else {
         if (one) {
-            if (a.screen) hipLaunchKernelGGL((k_potts_pass<6, true, 1>), grid, block, 0, c->stream, a);
-            else hipLaunchKernelGGL((k_potts_pass<6, false, 1>), grid, block, 0, c->stream, a);
+            if (a.screen) HMC_PASS(6, true, 1);
+            else HMC_PASS(6, false, 1);
         } else {
-            if (a.screen) hipLaunchKernelGGL((k_potts_pass<6, true, 4>), grid, block, 0, c->stream, a);
-            else hipLaunchKernelGGL((k_potts_pass<6, false, 4>), grid, block, 0, c->stream, a);
+            if (a.screen) HMC_PASS(6, true, 4);
+            else HMC_PASS(6, false, 4);
         }
     }
+#undef HMC_PASS
     prof_end(c, tok);
     return hipGetLastError();
 }
