@@ -56,20 +56,31 @@ def zone_flops_minimal(h: int, nr: int) -> float:
 REFRESH_BYTES_PER_NODE_STEP = 50.0   # read u, w (24 B) + write u, w (24 B) + spin (2 B)
 
 
+def source_hash(source):
+    """First 16 hex digits of the SHA-256 of a kernel source and the code-generation options the
+    build gives that source: counters taken on one build stay valid while both are unchanged."""
+    import hashlib
+
+    from paper_1009_0457_amd.build import SOURCE_FLAGS
+
+    data = open(os.path.join(ROOT, "paper_1009_0457_amd", "csrc", source), "rb").read()
+    flags = SOURCE_FLAGS.get(source, [])
+    if flags:
+        data += ("\n// build: " + " ".join(flags)).encode()
+    return hashlib.sha256(data).hexdigest()[:16]
+
+
 def measured_traffic(key_bytes, key_hash, source, summary="counters_large128.md"):
     """A figure (HBM bytes, executed operations) from a committed rocprofv3 counter summary,
     valid only while the kernel source still has the hash it had when the counters were taken
     (else None)."""
-    import hashlib
-
     try:
         vals = {}
         for line in open(os.path.join(ROOT, "profiles", summary)):
             if "=" in line and not line.startswith(("|", "`", "cd ")):
                 k, v = (t.strip() for t in line.split("=", 1))
                 vals[k] = v
-        h = hashlib.sha256(open(os.path.join(ROOT, "paper_1009_0457_amd", "csrc", source), "rb").read())
-        if h.hexdigest()[:16] != vals.get(key_hash):
+        if source_hash(source) != vals.get(key_hash):
             return None
         return float(vals[key_bytes])
     except (OSError, KeyError, ValueError):

@@ -1,20 +1,33 @@
-"""Builds the HIP library libhmc.so in-tree for gfx950 with hipcc."""
+"""Builds the HIP library libhmc.so in-tree for gfx950 with hipcc: each source compiled to an
+object (in parallel, in a temporary directory), then linked."""
 from __future__ import annotations
 
 import glob
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhmc.so")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 (v_pk_*_f32) code generation stays off on this target
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+]
+# Per-source code-generation options.  The zone solve's step loop is pure FP32 arithmetic at
+# two wavefronts per SIMD: the scheduler's instruction-level-parallelism strategy orders it
+# 2 % faster per solve (the same registers, no spills); on the colour pass the same strategy
+# costs occupancy, so it stays with the default there.
+SOURCE_FLAGS = {
+    "hmc_zone.hip": ["-mllvm", "--amdgpu-sched-strategy=max-ilp"],
+}
+LINK = [
+    "--offload-arch=gfx950", "-shared", "-fPIC",
     # roctx ranges around sweeps, colour passes, refreshes and adjoint passes
     "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib",
 ]
@@ -25,11 +38,23 @@ def sources():
 
 
 def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = ["hipcc", *FLAGS, "-I", os.path.join(HERE, "..", "include"), *sources(), "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+    inc = ["-I", os.path.join(HERE, "..", "include")]
+    with tempfile.TemporaryDirectory(prefix="hmc_build_") as tmpdir:
+        def compile_one(src):
+            obj = os.path.join(tmpdir, os.path.basename(src)[:-4] + ".o")
+            cmd = ["hipcc", *FLAGS, *SOURCE_FLAGS.get(os.path.basename(src), []), *inc, "-c", src, "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.check_call(cmd)
+            return obj
+
+        with ThreadPoolExecutor(min(8, os.cpu_count() or 1)) as ex:
+            objs = list(ex.map(compile_one, sources()))
+        tmp = LIB + ".tmp"
+        cmd = ["hipcc", *LINK, *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB
 
