@@ -56,21 +56,27 @@ def zone_flops_minimal(h: int, nr: int) -> float:
 REFRESH_BYTES_PER_NODE_STEP = 50.0   # read u, w (24 B) + write u, w (24 B) + spin (2 B)
 
 
-def source_hash(source):
-    """First 16 hex digits of the SHA-256 of a kernel source and the code-generation options the
-    build gives that source: counters taken on one build stay valid while both are unchanged."""
+def source_hash(*sources):
+    """First 16 hex digits of the SHA-256 of a kernel's sources and the code-generation options
+    the build gives them: counters taken on one build stay valid while both are unchanged."""
     import hashlib
 
     from paper_1009_0457_amd.build import SOURCE_FLAGS
 
-    data = open(os.path.join(ROOT, "paper_1009_0457_amd", "csrc", source), "rb").read()
-    flags = SOURCE_FLAGS.get(source, [])
-    if flags:
-        data += ("\n// build: " + " ".join(flags)).encode()
+    data = b""
+    for source in sources:
+        data += open(os.path.join(ROOT, "paper_1009_0457_amd", "csrc", source), "rb").read()
+        flags = SOURCE_FLAGS.get(source, [])
+        if flags:
+            data += ("\n// build: " + " ".join(flags)).encode()
     return hashlib.sha256(data).hexdigest()[:16]
 
 
-def measured_traffic(key_bytes, key_hash, source, summary="counters_large128.md"):
+# the lane-shift zone solve of the 5^3 zone: its template and the unit that instantiates it
+ZONE_H2_SOURCES = ("hmc_zone_h2.hip", "hmc_zone_kernels.h")
+
+
+def measured_traffic(key_bytes, key_hash, sources, summary="counters_large128.md"):
     """A figure (HBM bytes, executed operations) from a committed rocprofv3 counter summary,
     valid only while the kernel source still has the hash it had when the counters were taken
     (else None)."""
@@ -80,7 +86,7 @@ def measured_traffic(key_bytes, key_hash, source, summary="counters_large128.md"
             if "=" in line and not line.startswith(("|", "`", "cd ")):
                 k, v = (t.strip() for t in line.split("=", 1))
                 vals[k] = v
-        if source_hash(source) != vals.get(key_hash):
+        if source_hash(*((sources,) if isinstance(sources, str) else sources)) != vals.get(key_hash):
             return None
         return float(vals[key_bytes])
     except (OSError, KeyError, ValueError):
@@ -910,7 +916,9 @@ def main():
     fps = zone_flops_per_solve(p.zone_h, p.zone_steps)
     zsec = zt["total_ms"] * 1e-3
     achieved = fps * solves / zsec / 1e12 if zsec > 0 else 0.0
-    per_solve = measured_traffic("zone_traffic_bytes_per_solve", "zone_source_sha256_16", "hmc_zone.hip")
+    workload_zone = (p.zone_h, p.zone_steps) == (2, 200)   # the zone the counters were taken on
+    per_solve = measured_traffic("zone_traffic_bytes_per_solve", "zone_source_sha256_16",
+                                 ZONE_H2_SOURCES) if workload_zone else None
     spl = solves / max(1, zt["launches"])
     roof = {"kernel": "zone solve", "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
@@ -918,16 +926,13 @@ def main():
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE, profiles/counters_large128.md)",
             "avg_launch_ms": round(zt["total_ms"] / max(1, zt["launches"]), 4),
             "flop_per_solve": fps, "solves_per_launch": round(solves / max(1, zt["launches"]), 1)}
-    # the same launches priced at the least work of the kernels' separable form, at the FP32
-    # operations the kernel executes (its VALU counters, lanes without a voxel included), and
-    # against the peak without packed FP32, which the library is compiled without
+    # the same launches priced at the least work of the kernels' separable form and at the FP32
+    # operations the kernel executes (its VALU counters, lanes without a voxel included)
     mfps = zone_flops_minimal(p.zone_h, p.zone_steps)
     roof["flop_per_solve_minimal"] = mfps
     roof["frac_minimal"] = round(mfps * solves / zsec / 1e12 / PEAK_FP32_TFLOPS, 4) if zsec > 0 else None
-    roof["frac_minimal_of_unpacked_fp32_peak"] = round(mfps * solves / zsec / 1e12 / (PEAK_FP32_TFLOPS / 2), 4) \
-        if zsec > 0 else None
-    xfps = measured_traffic("zone_executed_fp32_flop_per_solve", "zone_source_sha256_16", "hmc_zone.hip",
-                            "zone_instruction_mix_large128.md") if (p.zone_h, p.zone_steps) == (2, 200) else None
+    xfps = measured_traffic("zone_executed_fp32_flop_per_solve", "zone_source_sha256_16", ZONE_H2_SOURCES,
+                            "zone_instruction_mix_large128.md") if workload_zone else None
     roof["flop_per_solve_executed"] = xfps
     roof["frac_executed"] = round(xfps * solves / zsec / 1e12 / PEAK_FP32_TFLOPS, 4) if (xfps and zsec > 0) else None
     pk = kt["potts"]

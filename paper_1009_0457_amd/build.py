@@ -22,9 +22,15 @@ FLAGS = [
 # Per-source code-generation options.  The zone solve's step loop is pure FP32 arithmetic at
 # two wavefronts per SIMD: the scheduler's instruction-level-parallelism strategy orders it
 # 2 % faster per solve (the same registers, no spills); on the colour pass the same strategy
-# costs occupancy, so it stays with the default there.
+# costs occupancy, so it stays with the default there.  For the 5^3 zone (h = 2, its own
+# source) the AMDGPU register-pressure trackers in that scheduler give a further 7 % (128^3
+# workload: 5.62 -> 5.24 ms per colour launch, 254 of 256 registers, no spills); the same
+# option makes h = 1 and h = 3 slower (0.365 -> 0.386 and 37.4 -> 38.1 ms) and the colour
+# pass, explicit step and adjoint step too, so it is given to that source alone.
+_MAX_ILP = ["-mllvm", "--amdgpu-sched-strategy=max-ilp"]
 SOURCE_FLAGS = {
-    "hmc_zone.hip": ["-mllvm", "--amdgpu-sched-strategy=max-ilp"],
+    "hmc_zone.hip": _MAX_ILP,
+    "hmc_zone_h2.hip": _MAX_ILP + ["-mllvm", "--amdgpu-use-amdgpu-trackers"],
 }
 LINK = [
     "--offload-arch=gfx950", "-shared", "-fPIC",
