@@ -1,7 +1,8 @@
 // hmc_zone_h2.hip -- the lane-shift zone solve for h = 2 (5^3 voxels), the workloads' zone
-// size, in a translation unit of its own: the build schedules it with register-pressure
-// tracking that suits its 236-register step loop (128^3 workload: 5.62 -> 5.24 ms per colour
-// launch), while the h = 1 and h = 3 instances, which that option slows, keep the others.
+// size, in a translation unit of its own: the build schedules it with the AMDGPU
+// register-pressure trackers (the same instructions in another order, 254 registers, no
+// spills; 128^3 workload: 5.62 -> 5.24 ms per colour launch), while the h = 1 and h = 3
+// instances, which that option slows, keep the options of hmc_zone.hip.
 #include "hmc_zone_kernels.h"
 
 namespace hmc {
