@@ -53,9 +53,11 @@ hipError_t launch_zone_pass(hmc_ctx_s* c, int colour, hmc_trial_record* rec)
             case 20:
                 if (launch_zone_lane_h2(waves, grid, block, c->stream, a) != hipSuccess) return hipErrorInvalidValue;
                 break;
-            case 25: HMC_LANE(3, 1); break;
-            case 26: HMC_LANE(3, 2); break;
-            case 28: HMC_LANE(3, 4); break;
+            case 25:
+            case 26:
+            case 28:
+                if (launch_zone_lane_h3(waves, grid, block, c->stream, a) != hipSuccess) return hipErrorInvalidValue;
+                break;
             default: return hipErrorInvalidValue;
         }
 #undef HMC_LANE

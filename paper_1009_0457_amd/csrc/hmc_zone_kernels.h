@@ -889,10 +889,11 @@ __global__ __launch_bounds__(64 * WAVES, H == 1 ? 3 : 2) void k_zone_lane(ZoneAr
     }
 }
 
-// Launches k_zone_lane<2, waves> for waves = 1, 2 or 4 (else hipErrorInvalidValue) on the
-// stream; a launch error stays pending for hipGetLastError.  The instance of the workloads'
-// 5^3 zone lives in a translation unit of its own so that the build can give it its own
-// scheduling options.
+// Launch k_zone_lane<2, waves> and k_zone_lane<3, waves> for waves = 1, 2 or 4 (else
+// hipErrorInvalidValue) on the stream; a launch error stays pending for hipGetLastError.  The
+// instances of the 5^3 and 7^3 zones live in translation units of their own so that the build
+// can give each its own scheduling options.
 hipError_t launch_zone_lane_h2(int waves, dim3 grid, dim3 block, hipStream_t stream, const ZoneArgs& a);
+hipError_t launch_zone_lane_h3(int waves, dim3 grid, dim3 block, hipStream_t stream, const ZoneArgs& a);
 
 }  // namespace hmc
