@@ -1,8 +1,8 @@
 // hmc_zone_h2.hip -- the lane-shift zone solve for h = 2 (5^3 voxels), the workloads' zone
 // size, in a translation unit of its own: the build schedules it with the AMDGPU
 // register-pressure trackers (the same instructions in another order, 254 registers, no
-// spills; 128^3 workload: 5.62 -> 5.24 ms per colour launch), while the h = 1 and h = 3
-// instances, which that option slows, keep the options of hmc_zone.hip.
+// spills; 128^3 workload: 5.62 -> 5.24 ms per colour launch); it slows the h = 1 instance,
+// which keeps the options of hmc_zone.hip, and the h = 3 one, which has a unit of its own.
 #include "hmc_zone_kernels.h"
 
 namespace hmc {
