@@ -200,3 +200,28 @@ def test_material_points_constants_and_limits():
     reps[0], reps[1] = r, H.hmc_default_replica(p, 2, 8)
     assert L.hmc_batch_workspace_bytes(C.byref(p), 1, reps) > 0
     assert L.hmc_batch_workspace_bytes(C.byref(p), 2, reps) == 0     # K = 2 is too small for it
+
+
+def test_per_source_build_options_name_existing_sources():
+    """The build's per-source code-generation options and the sources the bench hashes for its
+    counter keys must name files that exist: a renamed kernel source would otherwise lose its
+    options (or its counters) without a word."""
+    import sys
+
+    sys.path.insert(0, ROOT)
+    from paper_1009_0457_amd.build import SOURCE_FLAGS, sources
+
+    import bench
+
+    csrc = os.path.join(ROOT, "paper_1009_0457_amd", "csrc")
+    built = {os.path.basename(s) for s in sources()}
+    for name, flags in SOURCE_FLAGS.items():
+        assert name in built, name
+        assert flags and all(isinstance(f, str) for f in flags)
+    for name in bench.ZONE_H2_SOURCES + ("hmc_potts.hip", "hmc_elastic.hip"):
+        assert os.path.exists(os.path.join(csrc, name)), name
+    # the per-size zone units instantiate their own lane-shift kernels and nothing else does
+    for h, unit in ((2, "hmc_zone_h2.hip"), (3, "hmc_zone_h3.hip")):
+        text = open(os.path.join(csrc, unit)).read()
+        assert f"k_zone_lane<{h}, 1>" in text
+        assert f"k_zone_lane<{h}," not in open(os.path.join(csrc, "hmc_zone.hip")).read()
